@@ -1,0 +1,187 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of batched OMP on one MI355X.
+
+One step = one complete omp_solve over the batch: every iteration of
+Algorithm 1 for every signal (correlation product with the fused argmax, the
+Cholesky append and both triangular solves, the residual and the stop test),
+plus the set-up and output kernels. The dictionary is prepared once before the
+timed region (the paper shares the Gram precomputation between batches) and its
+time is reported separately. Inputs are resident in device memory before the
+timed region starts.
+
+Workload: A 1024 x 4096 Gaussian N(0, 1/M), a batch of 4096 signals, 64-sparse
+x with values +-(1 + |N(0,1)|), noise at 30 dB SNR per signal, S = 64 and no
+early stop (synthetic stand-in for the paper's unnamed application data).
+
+Prints ONE JSON line (rank 0, one GPU).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "signals/sec, M=1024 N=4096 S=64 batched OMP vs plain FP32, same supports"
+PEAK = {"fp32_mfma": 157.3, "bf16_mfma": 2500.0, "hbm": 8000.0}  # TFLOP/s, TFLOP/s, GB/s
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def corr_flops_per_launch(M, N, B):
+    """Algorithmic flops of one correlation launch: 2 M N per live signal."""
+    return 2.0 * M * N * B
+
+
+def update_bytes_per_launch(M, S, B):
+    """Algorithmic bytes of one update launch, averaged over the S iterations:
+    per signal at support size K: K gathered atoms (4 M K), y read and r written
+    (8 M), the atom n* read for beta (4 M), the packed factor read and one row
+    appended (~2 K^2 + 4 K)."""
+    tot = 0.0
+    for K in range(1, S + 1):
+        tot += 4.0 * M * K + 12.0 * M + 2.0 * K * K + 4.0 * K
+    return B * tot / S
+
+
+def run_gpu(w, precision, steps, warmup):
+    import torch
+    from paper_2407_06434_amd import omp
+
+    dev = torch.device("cuda:0")
+    A = torch.from_numpy(w.A).to(dev)
+    Y = torch.from_numpy(w.Y).to(dev)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    d = omp.Dictionary(A, precision)
+    e1.record()
+    torch.cuda.synchronize()
+    dict_ms = e0.elapsed_time(e1)
+    ws = torch.empty(omp.workspace_bytes(w.M, w.N, w.B, w.S, precision, with_dict=True), dtype=torch.uint8,
+                     device=dev)
+    out = None
+    for _ in range(warmup):
+        out = omp.solve(A, Y, w.S, w.eps, precision=precision, dictionary=d, workspace=ws, out=out)
+    torch.cuda.synchronize()
+    timing = {}
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = omp.solve(A, Y, w.S, w.eps, precision=precision, dictionary=d, workspace=ws, out=out,
+                        timing=timing)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    res = dict(support=out.support.cpu().numpy(), coef=out.coef.cpu().numpy(),
+               status=out.status.cpu().numpy(), rnorm=out.rnorm.cpu().numpy())
+    return dict(wall=wall, timing=timing, dict_ms=dict_ms, res=res)
+
+
+def cpu_baseline(w, target_s):
+    """The oracle, as it stands, on the first n signals of the same workload."""
+    import oracle
+    threads = oracle.default_threads()
+    n0 = threads
+    t0 = time.perf_counter()
+    first = oracle.omp(w.A, w.Y[:n0], w.S, w.eps, threads=threads)
+    t1 = time.perf_counter() - t0
+    n = n0
+    if t1 < target_s:
+        extra = int(max(0, (target_s - t1) / max(t1, 1e-6)) * n0)
+        extra = min(extra, w.B - n0)
+        if extra > 0:
+            t0 = time.perf_counter()
+            oracle.omp(w.A, w.Y[n0:n0 + extra], w.S, w.eps, threads=threads)
+            t1 += time.perf_counter() - t0
+            n += extra
+    return dict(value=n / t1, unit="signals/s", cores=threads, kind="oracle",
+                sample=f"first {n} of the {w.B} signals of the benchmark workload, FP64, "
+                       f"{threads} host threads, {t1:.1f} s"), first
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--compare-fp32", action="store_true",
+                    help="also time the plain FP32 form and count identical supports")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
+              f"(the batch would shard by signals with no in-loop communication).", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_2407_06434_amd import workloads
+
+    t = time.perf_counter()
+    w = workloads.bf16_1024x4096()
+    log(f"workload {w.name} M={w.M} N={w.N} B={w.B} S={w.S} generated in {time.perf_counter() - t:.1f}s")
+
+    g = run_gpu(w, args.precision, args.steps, args.warmup)
+    sps = w.B * args.steps / g["wall"]
+    ms_step = 1e3 * g["wall"] / args.steps
+    log(f"{args.precision}: {sps:.0f} signals/s, {ms_step:.2f} ms/step, phases {g['timing']}")
+
+    tim = g["timing"]
+    phase_ms = {k: v[0] / args.steps for k, v in tim.items()}
+    corr_ms, corr_n = tim["corr"]
+    upd_ms, upd_n = tim["update"]
+    corr_avg = corr_ms / max(corr_n, 1)
+    upd_avg = upd_ms / max(upd_n, 1)
+    if corr_ms >= upd_ms:
+        flops = corr_flops_per_launch(w.M, w.N, w.B)
+        peak = PEAK["bf16_mfma"] if args.precision == "bf16" else PEAK["fp32_mfma"]
+        ach = flops / (corr_avg * 1e-3) / 1e12
+        roof = dict(kernel="k_corr_select", bound="mfma", achieved=round(ach, 2), peak=peak, unit="TFLOP/s",
+                    frac=round(ach / peak, 4), traffic=None, avg_launch_ms=round(corr_avg, 5),
+                    per_launch=f"{flops:.4e} flop")
+    else:
+        nbytes = update_bytes_per_launch(w.M, w.S, w.B)
+        ach = nbytes / (upd_avg * 1e-3) / 1e9
+        roof = dict(kernel="k_update", bound="hbm", achieved=round(ach, 1), peak=PEAK["hbm"], unit="GB/s",
+                    frac=round(ach / PEAK["hbm"], 4), traffic=None, avg_launch_ms=round(upd_avg, 5),
+                    per_launch=f"{nbytes:.4e} B")
+
+    line = {
+        "metric": METRIC, "value": round(sps, 1), "unit": "signals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32" if args.precision == "fp32" else "bf16",
+        "data": "synthetic (seeded Gaussian dictionary and sparse signals at 30 dB)",
+        "config": {"workload": "omp_1024x4096_S64_B4096", "M": w.M, "N": w.N, "S": w.S, "B": w.B,
+                   "precision": args.precision, "early_stop": False},
+        "roofline": roof,
+        "phase_ms_per_step": {k: round(v, 4) for k, v in phase_ms.items()},
+        "corr_avg_ms": round(corr_avg, 5), "update_avg_ms": round(upd_avg, 5),
+        "dict_prep_ms": round(g["dict_ms"], 3),
+    }
+
+    if args.compare_fp32 and args.precision != "fp32":
+        f = run_gpu(w, "fp32", max(2, args.steps // 2), 1)
+        line["fp32_signals_per_s"] = round(w.B * max(2, args.steps // 2) / f["wall"], 1)
+        same = [set(a.tolist()) == set(b.tolist()) for a, b in zip(g["res"]["support"], f["res"]["support"])]
+        line["same_supports_vs_fp32"] = f"{sum(same)}/{w.B}"
+
+    if not args.no_cpu_baseline:
+        cb, first = cpu_baseline(w, args.cpu_seconds)
+        line["cpu_baseline"] = cb
+        n = first["support"].shape[0]
+        same = [set(first["support"][i].tolist()) == set(g["res"]["support"][i].tolist()) for i in range(n)]
+        line["oracle_same_supports"] = f"{sum(same)}/{n}"
+        log(f"cpu baseline {cb}")
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

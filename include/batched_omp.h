@@ -1,0 +1,175 @@
+/*
+ * batched_omp.h — C ABI of the MI355X (gfx950) batched Orthogonal Matching
+ * Pursuit library, libbatched_omp.so.
+ *
+ * The problem (Section 1 of Lubonja, Praesius & Tran, "A Practical
+ * GPU-Accelerated Implementation of Orthogonal Matching Pursuit"): given a
+ * dictionary A (M x N, atoms a_n as columns), a batch of B measurement vectors
+ * y_b (length M), a sparsity level S and an optional tolerance eps, find for
+ * every b an S-sparse x_b with y_b ~ A x_b by Algorithm 1 (OMP):
+ *
+ *   r_0 = y, support empty; for k = 1..S:
+ *     n* = argmax_n |<r_{k-1}, a_n>| / ||a_n||     (not yet selected atoms)
+ *     support_k = support_{k-1} + n*
+ *     x_k = argmin_x ||y - A_support x||
+ *     r_k = y - A_support x_k
+ *   stop as soon as ||r_k|| <= eps.
+ *
+ * The library runs the whole iteration on the GPU: the correlation A^T R for
+ * the batch as one matrix product (Section 3.2), the per-signal argmax fused
+ * into that product's epilogue (Section 3.4), the least squares by the
+ * progressive Cholesky update of Section 2.2 (Eqs. 4-5) driven by the
+ * precomputed Gram matrix A^T A (Section 2.2, last paragraph), and the residual
+ * recomputed from y at every step.
+ *
+ * Conventions for every entry point:
+ *   - All array pointers are DEVICE pointers on the caller's current HIP
+ *     device, unless a comment says "host".
+ *   - The caller allocates and owns every buffer (inputs, outputs, workspace,
+ *     dictionary memory). The library allocates no device memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls only enqueue work; results are valid once the stream has reached
+ *     the enqueued work (e.g. after hipStreamSynchronize).
+ *   - A negative return value means nothing was enqueued, except OMP_EDEVICE,
+ *     which means a HIP call failed part-way (omp_last_hip_error() holds the
+ *     hipError_t). Per-signal numerical outcomes are status bits, not errors.
+ *   - Calls are re-entrant; concurrent calls must use distinct workspaces.
+ *   - For fixed inputs, options and device, results are bit-identical from
+ *     call to call.
+ */
+#ifndef BATCHED_OMP_H
+#define BATCHED_OMP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ------------------------------------------------------ */
+#define OMP_OK 0
+#define OMP_EINVAL (-1)     /* invalid argument (sizes, null pointers, alignment, NaN eps) */
+#define OMP_EWORKSPACE (-2) /* workspace or dictionary memory missing / too small / misaligned */
+#define OMP_EDEVICE (-3)    /* a HIP runtime call failed, or the device is not gfx950 */
+#define OMP_ENOTSUPP (-4)   /* valid request beyond this build's limits (e.g. S > OMP_MAX_S) */
+
+/* ---- limits ------------------------------------------------------------ */
+#define OMP_MAX_S 256 /* largest sparsity level S (the Cholesky factor lives in LDS) */
+
+/* ---- precision of the correlation product ------------------------------ */
+#define OMP_PREC_FP32 0 /* A^T R with FP32 inputs and FP32 accumulation */
+#define OMP_PREC_BF16 1 /* A^T R in BF16 with FP32 accumulation; the leading candidates
+                           are re-scored in FP32 so that the pick is the FP32 argmax */
+
+/* ---- per-signal status bits (status_out) -------------------------------
+ * status_out[b] = (k_b << 8) | bits, k_b = number of atoms selected. */
+#define OMP_SIG_EPS 1        /* stopped because ||r|| <= eps_b */
+#define OMP_SIG_SMAX 2       /* stopped because k_b reached S_b */
+#define OMP_SIG_DEPENDENT 4  /* the picked atom was (numerically) in the span of the support:
+                                Cholesky pivot d^2 <= 1e-6 ||a_n*||^2; it was not added */
+#define OMP_SIG_NONFINITE 8  /* y_b held a NaN or Inf; nothing was selected, x_b = 0 */
+#define OMP_SIG_EXHAUSTED 32 /* no selectable atom was left (all selected or zero norm) */
+#define OMP_SIG_WIDENED 64   /* BF16 form: the FP32 re-score needed the widened candidate set */
+
+/* ---- prepared dictionary ------------------------------------------------
+ * Everything about A that does not depend on the signals (Section 2.2: the
+ * Gram matrix A^T A is computed once and shared between batches):
+ *   atom norms ||a_n||^2 in FP64 and 1/||a_n|| in FP32, a zero-padded FP32
+ *   copy of A, the FP32 Gram matrix, and (BF16 form) a BF16 copy of A rounded
+ *   to nearest even.
+ * The struct lives in host memory and is filled by omp_dict_init; its `mem`
+ * points to caller-owned device memory of at least omp_dict_size() bytes. */
+typedef struct omp_dict {
+  uint32_t magic;    /* set by omp_dict_init */
+  int32_t precision; /* OMP_PREC_* the dictionary was prepared for */
+  int64_t M, N;      /* dictionary shape */
+  int64_t Mp, Np;    /* padded shape used by the kernels */
+  const float *A;    /* the caller's A it was prepared from (device) */
+  void *mem;         /* device memory holding the prepared data */
+  size_t bytes;
+} omp_dict_t;
+
+/* Bytes of device memory omp_dict_init needs for an M x N dictionary. */
+size_t omp_dict_size(int64_t M, int64_t N, int32_t precision);
+
+/* Prepare a dictionary.
+ *   A      device, atom-major: atom n occupies A[n*lda .. n*lda+M-1] (lda >= M).
+ *          (Equivalently A is M x N column-major.) Read only.
+ *   mem    device, >= omp_dict_size(M, N, precision) bytes, 256-byte aligned.
+ *   dict   host struct, filled on success.
+ * Enqueued on `stream`. A must stay unchanged while the dictionary is used. */
+int omp_dict_init(omp_dict_t *dict, const float *A, int64_t M, int64_t N, int64_t lda,
+                  int32_t precision, void *mem, size_t bytes, void *stream);
+
+/* ---- options ------------------------------------------------------------ */
+typedef struct omp_opts {
+  int32_t precision;            /* OMP_PREC_FP32 (default) or OMP_PREC_BF16 */
+  int32_t reserved0;
+  const int32_t *S_per_signal;  /* device [B], optional: per-signal S_b in 0..S */
+  const float *eps_per_signal;  /* device [B], optional: per-signal eps_b (replaces eps) */
+  int32_t *status_out;          /* device [B], optional: (k_b << 8) | OMP_SIG_* bits */
+  float *rnorm_out;             /* device [B], optional: final ||r_b|| */
+  float *coef_out;              /* device [B][S], optional: coefficients aligned with
+                                   support_out (0 where support_out is -1) */
+  const omp_dict_t *dict;       /* host, optional: a dictionary prepared for the same A, M, N,
+                                   and precision; NULL prepares one inside the workspace */
+  void *workspace;              /* device, required: >= omp_workspace_size(...) bytes,
+                                   256-byte aligned; contents on entry are ignored */
+  size_t workspace_bytes;
+  float *phase_ms;              /* HOST [OMP_NPHASE], optional profiling: when set, every kernel
+                                   launch is bracketed by hipEvents on `stream`, the call waits for
+                                   the stream, and phase_ms[p] receives the summed kernel time (ms)
+                                   of phase p; NULL (default) keeps the call asynchronous */
+  int32_t *phase_launches;      /* HOST [OMP_NPHASE], optional: launches per phase (with phase_ms) */
+} omp_opts_t;
+
+/* Phases reported through omp_opts_t.phase_ms. */
+#define OMP_PHASE_DICT 0     /* dictionary preparation inside omp_solve (no prepared dictionary) */
+#define OMP_PHASE_INIT 1     /* padded copies of Y, norms, stop tests */
+#define OMP_PHASE_CORR 2     /* correlation product A^T R with the fused select epilogue */
+#define OMP_PHASE_UPDATE 3   /* Cholesky append, solves, residual, stop test */
+#define OMP_PHASE_OUTPUT 4   /* dense X, support, coefficients, status */
+#define OMP_NPHASE 5
+
+/* Fill `opts` with the defaults (FP32, no optional arrays, no workspace). */
+void omp_opts_default(omp_opts_t *opts);
+
+/* Bytes of workspace omp_solve needs. `opts` is read for precision and for
+ * whether a prepared dictionary is supplied (without one the workspace also
+ * holds the dictionary). Returns 0 for invalid sizes. */
+size_t omp_workspace_size(int64_t M, int64_t N, int64_t B, int32_t S, const omp_opts_t *opts);
+
+/* Solve B independent OMP problems y_b ~ A x_b (Algorithm 1).
+ *   A            device, atom-major [N][lda] FP32 (see omp_dict_init). Must equal opts->dict->A
+ *                when a prepared dictionary is given.
+ *   M, N         1 <= M, N; S <= min(M, N).
+ *   Y            device, signal-major: y_b = Y[b*ldy .. b*ldy+M-1], ldy >= M. Read only.
+ *   B            number of signals, B >= 0 (B = 0 enqueues nothing and returns OMP_OK).
+ *   S            sparsity level, 1 <= S <= min(M, N, OMP_MAX_S); caps every S_b.
+ *   eps          stop signal b when ||r_b|| <= eps (eps <= 0: only when r_b is exactly 0).
+ *                Must not be NaN. Ignored when opts->eps_per_signal is given.
+ *   X_out        device [B][N] FP32, optional (NULL): the dense solution x_b, zero off the support.
+ *   support_out  device [B][S] int32, required: selected atoms in selection order, -1 padded.
+ *   opts         host, required (workspace).
+ * Ties in the argmax go to the lowest atom index. Atoms of zero norm are never
+ * selected. Column norms need not be 1: selection divides by ||a_n||, and x is
+ * in the scale of the caller's A (Appendix A of the paper). */
+int omp_solve(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y, int64_t B,
+              int64_t ldy, int32_t S, float eps, float *X_out, int32_t *support_out,
+              const omp_opts_t *opts, void *stream);
+
+/* Human-readable text for a return code (static storage). */
+const char *omp_status_string(int status);
+
+/* hipError_t of the most recent OMP_EDEVICE on this thread (0 if none). */
+int omp_last_hip_error(void);
+
+/* Library version, e.g. "0.1.0". */
+const char *omp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BATCHED_OMP_H */

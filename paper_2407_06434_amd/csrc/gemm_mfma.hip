@@ -1,0 +1,295 @@
+// MFMA matrix products of the OMP iteration, for gfx950 (CDNA4).
+//
+// Both products have the "NT" form C[n][j] = sum_m P[n][m] Q[j][m]: the two
+// operands are row-major with the reduction index m contiguous, which is how
+// the dictionary (atom-major) and the residuals (signal-major) are stored.
+// Storing both operands reduction-contiguous is the layout lesson of the
+// paper's Section 3.1; doing the whole batch in one product instead of one
+// matrix-vector product per signal is Section 3.2.
+//
+//   * the Gram matrix G = A^T A (Section 2.2, last paragraph), stored;
+//   * the correlation C = A^T R of every atom with every residual (Algorithm 1,
+//     argmax step), never stored: the epilogue turns each column into the
+//     packed key of its best atom, |c_n| / ||a_n|| over the atoms not yet
+//     selected (Section 3.4: argmax without the B x N intermediate).
+//
+// Tiling. A workgroup computes a TN x TB tile with WN x WB wavefronts; each
+// wavefront owns FN x FB fragments of 32 x 32 (v_mfma_f32_32x32x2f32 for FP32,
+// v_mfma_f32_32x32x16_bf16 for BF16). Operands are staged through LDS in
+// 128-byte K slices, double buffered; each lane reads 16-byte chunks. Lane l
+// of a fragment reads row (l mod 32) at chunk (2q + l/32) of the slice; the
+// two halves of the wavefront thus supply the two K sub-blocks an MFMA sums
+// over, and both operands use the same K assignment, so the product sums
+// every m exactly once (the order of summation inside an MFMA is the
+// hardware's).
+
+#include "omp_internal.h"
+
+namespace bomp {
+namespace {
+
+typedef __attribute__((ext_vector_type(16))) float f32x16;
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+
+struct OpF32 {
+  using elem = float;
+  // One 16-byte chunk holds 4 FP32 values of K: four 32x32x2 MFMAs.
+  __device__ static inline void mma(const uint4 &a, const uint4 &b, f32x16 &c) {
+    c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.x), __uint_as_float(b.x), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.y), __uint_as_float(b.y), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.z), __uint_as_float(b.z), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.w), __uint_as_float(b.w), c, 0, 0, 0);
+  }
+};
+
+struct OpBF16 {
+  using elem = uint16_t;
+  // One 16-byte chunk holds 8 BF16 values of K: one 32x32x16 MFMA.
+  __device__ static inline void mma(const uint4 &a, const uint4 &b, f32x16 &c) {
+    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
+                                                __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+  }
+};
+
+template <int TN_, int TB_, int WN_, int WB_>
+struct Tile {
+  static constexpr int TN = TN_, TB = TB_, WN = WN_, WB = WB_;
+  static constexpr int NTHR = WN * WB * 64;
+  static constexpr int FN = TN / (32 * WN);
+  static constexpr int FB = TB / (32 * WB);
+  static constexpr int CH = 8;       // 16-byte chunks per row per K slice (128 bytes)
+  static constexpr int RS = CH + 1;  // LDS row stride in chunks (one chunk of padding)
+  static constexpr int A_LD = TN * CH / NTHR;
+  static constexpr int B_LD = TB * CH / NTHR;
+  static constexpr int STAGE = (TN + TB) * RS;  // chunks per LDS buffer
+  static constexpr size_t LDS_BYTES = 2 * STAGE * 16;
+  static_assert(FN >= 1 && FB >= 1, "tile too small for the wavefront grid");
+  static_assert(TN * CH % NTHR == 0 && TB * CH % NTHR == 0, "loads must divide evenly");
+};
+
+// Main loop: acc += P_tile * Q_tile^T over `nslices` K slices of 128 bytes.
+// P points at the tile's first row, rows `prs` chunks apart; likewise Q.
+template <class Op, class T>
+__device__ inline void mainloop(const uint4 *__restrict__ P, int64_t prs, const uint4 *__restrict__ Q,
+                                int64_t qrs, int nslices, uint4 *lds, f32x16 (&acc)[T::FN][T::FB]) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wn = wave % T::WN, wb = wave / T::WN;
+  const int h = lane >> 5, r32 = lane & 31;
+
+#pragma unroll
+  for (int i = 0; i < T::FN; ++i)
+#pragma unroll
+    for (int j = 0; j < T::FB; ++j) acc[i][j] = f32x16{};
+
+  uint4 ra[T::A_LD], rb[T::B_LD];
+  auto gload = [&](int s) {
+#pragma unroll
+    for (int i = 0; i < T::A_LD; ++i) {
+      const int idx = tid + i * T::NTHR;
+      ra[i] = P[(int64_t)(idx / T::CH) * prs + (int64_t)s * T::CH + (idx % T::CH)];
+    }
+#pragma unroll
+    for (int i = 0; i < T::B_LD; ++i) {
+      const int idx = tid + i * T::NTHR;
+      rb[i] = Q[(int64_t)(idx / T::CH) * qrs + (int64_t)s * T::CH + (idx % T::CH)];
+    }
+  };
+  auto lstore = [&](int buf) {
+    uint4 *la = lds + buf * T::STAGE;
+    uint4 *lb = la + T::TN * T::RS;
+#pragma unroll
+    for (int i = 0; i < T::A_LD; ++i) {
+      const int idx = tid + i * T::NTHR;
+      la[(idx / T::CH) * T::RS + (idx % T::CH)] = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < T::B_LD; ++i) {
+      const int idx = tid + i * T::NTHR;
+      lb[(idx / T::CH) * T::RS + (idx % T::CH)] = rb[i];
+    }
+  };
+
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  for (int s = 0; s < nslices; ++s) {
+    const int buf = s & 1;
+    if (s + 1 < nslices) gload(s + 1);
+    const uint4 *la = lds + buf * T::STAGE + (wn * T::FN * 32 + r32) * T::RS + h;
+    const uint4 *lb = lds + buf * T::STAGE + T::TN * T::RS + (wb * T::FB * 32 + r32) * T::RS + h;
+#pragma unroll
+    for (int q = 0; q < T::CH / 2; ++q) {
+      uint4 af[T::FN], bf[T::FB];
+#pragma unroll
+      for (int i = 0; i < T::FN; ++i) af[i] = la[i * 32 * T::RS + 2 * q];
+#pragma unroll
+      for (int j = 0; j < T::FB; ++j) bf[j] = lb[j * 32 * T::RS + 2 * q];
+#pragma unroll
+      for (int i = 0; i < T::FN; ++i)
+#pragma unroll
+        for (int j = 0; j < T::FB; ++j) Op::mma(af[i], bf[j], acc[i][j]);
+    }
+    if (s + 1 < nslices) lstore(buf ^ 1);
+    __syncthreads();
+  }
+}
+
+// Row of a 32x32 MFMA result held by (lane, register r): the column is lane % 32.
+__device__ inline int frag_row(int lane, int r) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
+
+// ---------------------------------------------------------------------------
+// Gram matrix: G[n][m] = sum_k A32[n][k] A32[m][k], FP32 in and out.
+// ---------------------------------------------------------------------------
+using GramTile = Tile<128, 128, 2, 2>;
+
+__global__ __launch_bounds__(GramTile::NTHR) void k_gram(const float *__restrict__ A32, int64_t Mp,
+                                                         int64_t Np, float *__restrict__ G) {
+  using T = GramTile;
+  extern __shared__ uint4 lds[];
+  const int ntn = (int)(Np / T::TN);
+  const int tn = blockIdx.x % ntn, tm = blockIdx.x / ntn;
+  const int64_t rs = Mp / 4;  // row stride in 16-byte chunks
+  const uint4 *P = reinterpret_cast<const uint4 *>(A32) + (int64_t)tn * T::TN * rs;
+  const uint4 *Q = reinterpret_cast<const uint4 *>(A32) + (int64_t)tm * T::TB * rs;
+  f32x16 acc[T::FN][T::FB];
+  mainloop<OpF32, T>(P, rs, Q, rs, (int)(rs / T::CH), lds, acc);
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wn = wave % T::WN, wb = wave / T::WN;
+#pragma unroll
+  for (int i = 0; i < T::FN; ++i)
+#pragma unroll
+    for (int j = 0; j < T::FB; ++j) {
+      const int64_t col = (int64_t)tm * T::TB + wb * T::FB * 32 + j * 32 + (lane & 31);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t row = (int64_t)tn * T::TN + wn * T::FN * 32 + i * 32 + frag_row(lane, r);
+        G[row * Np + col] = acc[i][j][r];
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Correlation + select. For every signal j of the tile and every atom n of the
+// tile, score s = |c_nj| * inv_nu[n]; an atom is a candidate when inv_nu[n] > 0
+// (not a zero or padding atom) and its bit in the signal's selected-atom mask
+// is clear. The candidate with the largest score wins; equal scores go to the
+// lowest index. Both rules are carried by one 64-bit key,
+//   key = (bits(s) << 32) | (0xFFFFFFFF - n),
+// whose unsigned maximum is the winner (bits(s) is monotone for s >= 0); key 0
+// means "no candidate". The key of each (signal, atom tile) goes to part.
+// ---------------------------------------------------------------------------
+template <class Op, class T>
+__global__ __launch_bounds__(T::NTHR) void k_corr_select(
+    const typename Op::elem *__restrict__ Aop, const typename Op::elem *__restrict__ Rop, int64_t Mp,
+    int64_t Np, const float *__restrict__ inv_nu, const uint32_t *__restrict__ mask,
+    const int32_t *__restrict__ flags, uint64_t *__restrict__ part, int ntile) {
+  extern __shared__ uint4 lds[];
+  const int tn = blockIdx.x % ntile, tb = blockIdx.x / ntile;
+  const int64_t b0 = (int64_t)tb * T::TB;
+
+  // Skip the tile when every signal in it has stopped (keep-in-batch stopping,
+  // Section 3.5: finished signals stay in place and are simply not advanced).
+  int live = 0;
+  for (int t = threadIdx.x; t < T::TB; t += T::NTHR) live |= !(flags[b0 + t] & FLAG_DONE);
+  if (!__syncthreads_or(live)) return;
+
+  constexpr int EPC = 16 / sizeof(typename Op::elem);  // elements per 16-byte chunk
+  const int64_t rs = Mp / EPC;
+  const uint4 *P = reinterpret_cast<const uint4 *>(Aop) + (int64_t)tn * T::TN * rs;
+  const uint4 *Q = reinterpret_cast<const uint4 *>(Rop) + b0 * rs;
+  f32x16 acc[T::FN][T::FB];
+  mainloop<Op, T>(P, rs, Q, rs, (int)(rs / T::CH), lds, acc);
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wn = wave % T::WN, wb = wave / T::WN;
+  const int64_t mwords = Np / 32;
+  uint64_t *red = reinterpret_cast<uint64_t *>(lds);  // [WN][TB], LDS is free after the main loop
+#pragma unroll
+  for (int j = 0; j < T::FB; ++j) {
+    const int jt = wb * T::FB * 32 + j * 32 + (lane & 31);  // signal within the tile
+    const int64_t b = b0 + jt;
+    uint64_t best = 0;
+#pragma unroll
+    for (int i = 0; i < T::FN; ++i) {
+      const int64_t nf = (int64_t)tn * T::TN + wn * T::FN * 32 + i * 32;  // first atom of the fragment
+      const uint32_t word = mask[b * mwords + nf / 32];
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const float4 iv = *reinterpret_cast<const float4 *>(inv_nu + nf + 8 * g + 4 * (lane >> 5));
+        const float ivs[4] = {iv.x, iv.y, iv.z, iv.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int row = 8 * g + 4 * (lane >> 5) + e;
+          const float s = fabsf(acc[i][j][4 * g + e]) * ivs[e];
+          const bool cand = ivs[e] > 0.f && !((word >> row) & 1u) && s >= 0.f;
+          const uint64_t key = cand ? ((uint64_t)__float_as_uint(s) << 32) |
+                                          (uint64_t)(0xFFFFFFFFu - (uint32_t)(nf + row))
+                                    : 0ull;
+          best = key > best ? key : best;
+        }
+      }
+    }
+    const uint64_t other = __shfl_xor(best, 32);
+    best = other > best ? other : best;
+    if (lane < 32) red[wn * T::TB + jt] = best;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < T::TB; t += T::NTHR) {
+    uint64_t best = 0;
+#pragma unroll
+    for (int w = 0; w < T::WN; ++w) best = red[w * T::TB + t] > best ? red[w * T::TB + t] : best;
+    part[(b0 + t) * ntile + tn] = best;
+  }
+}
+
+using CorrTileF32 = Tile<128, 128, 2, 2>;
+using CorrTileBF16 = Tile<128, 128, 2, 2>;
+
+template <class K>
+hipError_t set_lds(K kernel, size_t bytes) {
+  static bool done = false;  // per kernel instantiation
+  if (done) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e == hipSuccess) done = true;
+  return e;
+}
+
+}  // namespace
+
+int corr_tile_atoms(int precision) { return precision == 1 ? CorrTileBF16::TN : CorrTileF32::TN; }
+int corr_candidates(int) { return 1; }
+
+hipError_t launch_gram(const DictView &d, hipStream_t st) {
+  using T = GramTile;
+  hipError_t e = set_lds(k_gram, T::LDS_BYTES);
+  if (e != hipSuccess) return e;
+  const int nt = (int)(d.Np / T::TN);
+  hipLaunchKernelGGL(k_gram, dim3(nt * nt), dim3(T::NTHR), T::LDS_BYTES, st, d.A32, d.Mp, d.Np, d.G);
+  return hipGetLastError();
+}
+
+hipError_t launch_corr_select(const DictView &d, const WorkView &w, int precision, hipStream_t st) {
+  if (precision == 1) {
+    using T = CorrTileBF16;
+    auto kern = k_corr_select<OpBF16, T>;
+    hipError_t e = set_lds(kern, T::LDS_BYTES);
+    if (e != hipSuccess) return e;
+    const int ntile = (int)(d.Np / T::TN);
+    hipLaunchKernelGGL(kern, dim3(ntile * (w.Bp / T::TB)), dim3(T::NTHR), T::LDS_BYTES, st, d.A16,
+                       w.R16, d.Mp, d.Np, d.inv_nu, w.mask, w.flags, w.part, ntile);
+  } else {
+    using T = CorrTileF32;
+    auto kern = k_corr_select<OpF32, T>;
+    hipError_t e = set_lds(kern, T::LDS_BYTES);
+    if (e != hipSuccess) return e;
+    const int ntile = (int)(d.Np / T::TN);
+    hipLaunchKernelGGL(kern, dim3(ntile * (w.Bp / T::TB)), dim3(T::NTHR), T::LDS_BYTES, st, d.A32,
+                       w.R32, d.Mp, d.Np, d.inv_nu, w.mask, w.flags, w.part, ntile);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace bomp

@@ -1,0 +1,353 @@
+// Host side of libbatched_omp.so: argument validation, the layouts of the
+// prepared dictionary and of the workspace, and the iteration driver that
+// enqueues the kernels of one batched OMP solve (Algorithm 1 for every signal).
+//
+// Every argument check runs on the host before anything is enqueued; a
+// negative return therefore leaves the stream untouched (OMP_EDEVICE aside).
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/batched_omp.h"
+#include "omp_internal.h"
+
+namespace bomp {
+namespace {
+
+thread_local int g_last_hip_error = 0;
+
+constexpr size_t ALIGN = 256;
+
+struct Carve {
+  size_t off = 0;
+  template <class T>
+  size_t take(size_t count) {
+    off = (off + ALIGN - 1) / ALIGN * ALIGN;
+    const size_t at = off;
+    off += count * sizeof(T);
+    return at;
+  }
+};
+
+struct DictLayout {
+  int64_t Mp, Np;
+  size_t nu2, inv_nu, A32, G, A16, total;
+};
+
+DictLayout dict_layout(int64_t M, int64_t N, int precision) {
+  DictLayout L;
+  L.Mp = round_up(M, KPAD);
+  L.Np = round_up(N, NPAD);
+  Carve c;
+  L.nu2 = c.take<double>(L.Np);
+  L.inv_nu = c.take<float>(L.Np);
+  L.A32 = c.take<float>((size_t)L.Np * L.Mp);
+  L.G = c.take<float>((size_t)L.Np * L.Np);
+  L.A16 = precision == OMP_PREC_BF16 ? c.take<uint16_t>((size_t)L.Np * L.Mp) : 0;
+  L.total = (c.off + ALIGN - 1) / ALIGN * ALIGN;
+  return L;
+}
+
+struct WorkLayout {
+  int64_t Mp, Np, Bp;
+  int ntile, ncand;
+  size_t Yp, R32, R16, part, mask, k, flags, rn, Sb, epsb, sup, u, xh, V, total;
+};
+
+WorkLayout work_layout(int64_t M, int64_t N, int64_t B, int S, int precision) {
+  WorkLayout L;
+  L.Mp = round_up(M, KPAD);
+  L.Np = round_up(N, NPAD);
+  L.Bp = round_up(B > 0 ? B : 1, BPAD);
+  L.ntile = (int)(L.Np / corr_tile_atoms(precision));
+  L.ncand = corr_candidates(precision);
+  const size_t Bp = (size_t)L.Bp, Sz = (size_t)S;
+  Carve c;
+  L.Yp = c.take<float>(Bp * L.Mp);
+  L.R32 = c.take<float>(Bp * L.Mp);
+  L.R16 = precision == OMP_PREC_BF16 ? c.take<uint16_t>(Bp * L.Mp) : 0;
+  L.part = c.take<uint64_t>(Bp * L.ntile * L.ncand);
+  L.mask = c.take<uint32_t>(Bp * (L.Np / 32));
+  L.k = c.take<int32_t>(Bp);
+  L.flags = c.take<int32_t>(Bp);
+  L.rn = c.take<float>(Bp);
+  L.Sb = c.take<int32_t>(Bp);
+  L.epsb = c.take<float>(Bp);
+  L.sup = c.take<int32_t>(Bp * Sz);
+  L.u = c.take<float>(Bp * Sz);
+  L.xh = c.take<float>(Bp * Sz);
+  L.V = c.take<float>(Bp * (Sz * (Sz + 1) / 2));
+  L.total = (c.off + ALIGN - 1) / ALIGN * ALIGN;
+  return L;
+}
+
+template <class T>
+T *at(void *base, size_t off) {
+  return reinterpret_cast<T *>(static_cast<char *>(base) + off);
+}
+
+bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+// Sizes whose padded buffers would overflow or exceed any real device are rejected.
+bool dims_ok(int64_t M, int64_t N) {
+  return M >= 1 && N >= 1 && M <= (int64_t)1 << 24 && N <= (int64_t)1 << 20;
+}
+
+int device_error(hipError_t e) {
+  g_last_hip_error = (int)e;
+  return OMP_EDEVICE;
+}
+
+// The library is built for gfx950 only; refuse any other device up front.
+int check_device() {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return device_error(e);
+  static std::mutex mu;
+  static std::vector<int> ok;  // per device: 0 unknown, 1 gfx950, -1 other
+  std::lock_guard<std::mutex> lock(mu);
+  if ((int)ok.size() <= dev) ok.resize(dev + 1, 0);
+  if (ok[dev] == 0) {
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) return device_error(e);
+    ok[dev] = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? 1 : -1;
+  }
+  if (ok[dev] < 0) {
+    g_last_hip_error = (int)hipErrorInvalidDeviceFunction;
+    return OMP_EDEVICE;
+  }
+  return OMP_OK;
+}
+
+// Optional profiling (omp_opts_t.phase_ms): brackets every launch with a pair
+// of hipEvents on the solve's stream and sums the elapsed times per phase.
+class PhaseTimer {
+ public:
+  PhaseTimer(float *ms, int32_t *launches, hipStream_t st) : ms_(ms), n_(launches), st_(st) {}
+  ~PhaseTimer() {
+    for (auto &r : recs_) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+  }
+  template <class F>
+  hipError_t run(int phase, F &&launch) {
+    if (!ms_) return launch();
+    Rec r{nullptr, nullptr, phase};
+    hipError_t e = hipEventCreate(&r.a);
+    if (e == hipSuccess) e = hipEventCreate(&r.b);
+    if (e == hipSuccess) e = hipEventRecord(r.a, st_);
+    if (e == hipSuccess) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(r.b, st_);
+    recs_.push_back(r);
+    return e;
+  }
+  hipError_t finish() {
+    if (!ms_) return hipSuccess;
+    hipError_t e = hipStreamSynchronize(st_);
+    for (int p = 0; p < OMP_NPHASE; ++p) {
+      ms_[p] = 0.f;
+      if (n_) n_[p] = 0;
+    }
+    for (auto &r : recs_) {
+      float t = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&t, r.a, r.b);
+      ms_[r.phase] += t;
+      if (n_) n_[r.phase] += 1;
+    }
+    return e;
+  }
+
+ private:
+  struct Rec {
+    hipEvent_t a, b;
+    int phase;
+  };
+  float *ms_;
+  int32_t *n_;
+  hipStream_t st_;
+  std::vector<Rec> recs_;
+};
+
+}  // namespace
+
+size_t dict_bytes(int64_t M, int64_t N, int precision) { return dict_layout(M, N, precision).total; }
+
+DictView dict_view(void *mem, int64_t M, int64_t N, int precision) {
+  const DictLayout L = dict_layout(M, N, precision);
+  DictView d;
+  d.M = M;
+  d.N = N;
+  d.Mp = L.Mp;
+  d.Np = L.Np;
+  d.nu2 = at<double>(mem, L.nu2);
+  d.inv_nu = at<float>(mem, L.inv_nu);
+  d.A32 = at<float>(mem, L.A32);
+  d.G = at<float>(mem, L.G);
+  d.A16 = precision == OMP_PREC_BF16 ? at<uint16_t>(mem, L.A16) : nullptr;
+  return d;
+}
+
+size_t work_bytes(int64_t M, int64_t N, int64_t B, int S, int precision) {
+  return work_layout(M, N, B, S, precision).total;
+}
+
+WorkView work_view(void *mem, int64_t M, int64_t N, int64_t B, int S, int precision) {
+  const WorkLayout L = work_layout(M, N, B, S, precision);
+  WorkView w;
+  w.B = B;
+  w.Bp = L.Bp;
+  w.Mp = L.Mp;
+  w.Np = L.Np;
+  w.S = S;
+  w.ntile = L.ntile;
+  w.ncand = L.ncand;
+  w.Yp = at<float>(mem, L.Yp);
+  w.R32 = at<float>(mem, L.R32);
+  w.R16 = precision == OMP_PREC_BF16 ? at<uint16_t>(mem, L.R16) : nullptr;
+  w.part = at<uint64_t>(mem, L.part);
+  w.mask = at<uint32_t>(mem, L.mask);
+  w.k = at<int32_t>(mem, L.k);
+  w.flags = at<int32_t>(mem, L.flags);
+  w.rn = at<float>(mem, L.rn);
+  w.Sb = at<int32_t>(mem, L.Sb);
+  w.epsb = at<float>(mem, L.epsb);
+  w.sup = at<int32_t>(mem, L.sup);
+  w.u = at<float>(mem, L.u);
+  w.xh = at<float>(mem, L.xh);
+  w.V = at<float>(mem, L.V);
+  return w;
+}
+
+}  // namespace bomp
+
+using namespace bomp;
+
+extern "C" {
+
+const char *omp_version(void) { return "0.1.0"; }
+
+const char *omp_status_string(int status) {
+  switch (status) {
+    case OMP_OK: return "ok";
+    case OMP_EINVAL: return "invalid argument";
+    case OMP_EWORKSPACE: return "workspace or dictionary memory missing, too small or misaligned";
+    case OMP_EDEVICE: return "HIP runtime error or unsupported device (needs gfx950)";
+    case OMP_ENOTSUPP: return "request exceeds this build's limits";
+    default: return "unknown status";
+  }
+}
+
+int omp_last_hip_error(void) { return g_last_hip_error; }
+
+void omp_opts_default(omp_opts_t *opts) {
+  if (!opts) return;
+  std::memset(opts, 0, sizeof(*opts));
+  opts->precision = OMP_PREC_FP32;
+}
+
+size_t omp_dict_size(int64_t M, int64_t N, int32_t precision) {
+  if (!dims_ok(M, N) || (precision != OMP_PREC_FP32 && precision != OMP_PREC_BF16)) return 0;
+  return dict_bytes(M, N, precision);
+}
+
+int omp_dict_init(omp_dict_t *dict, const float *A, int64_t M, int64_t N, int64_t lda, int32_t precision,
+                  void *mem, size_t bytes, void *stream) {
+  if (!dict || !A || !dims_ok(M, N) || lda < M) return OMP_EINVAL;
+  if (precision != OMP_PREC_FP32 && precision != OMP_PREC_BF16) return OMP_EINVAL;
+  if (!aligned(A, 4)) return OMP_EINVAL;
+  const size_t need = dict_bytes(M, N, precision);
+  if (!mem || bytes < need || !aligned(mem, ALIGN)) return OMP_EWORKSPACE;
+  int rc = check_device();
+  if (rc != OMP_OK) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const DictView d = dict_view(mem, M, N, precision);
+  hipError_t e = launch_dict_prep(A, lda, d, st);
+  if (e == hipSuccess) e = launch_gram(d, st);
+  if (e != hipSuccess) return device_error(e);
+  dict->magic = DICT_MAGIC;
+  dict->precision = precision;
+  dict->M = M;
+  dict->N = N;
+  dict->Mp = d.Mp;
+  dict->Np = d.Np;
+  dict->A = A;
+  dict->mem = mem;
+  dict->bytes = bytes;
+  return OMP_OK;
+}
+
+size_t omp_workspace_size(int64_t M, int64_t N, int64_t B, int32_t S, const omp_opts_t *opts) {
+  const int prec = opts ? opts->precision : OMP_PREC_FP32;
+  if (!dims_ok(M, N) || B < 0 || B > ((int64_t)1 << 26) || S < 1 || S > OMP_MAX_S) return 0;
+  if (prec != OMP_PREC_FP32 && prec != OMP_PREC_BF16) return 0;
+  size_t total = work_bytes(M, N, B, S, prec);
+  if (!opts || !opts->dict) total += dict_bytes(M, N, prec);
+  return total;
+}
+
+int omp_solve(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y, int64_t B, int64_t ldy,
+              int32_t S, float eps, float *X_out, int32_t *support_out, const omp_opts_t *opts,
+              void *stream) {
+  // ---- validation (host only) ----
+  if (!opts) return OMP_EINVAL;
+  const int prec = opts->precision;
+  if (prec != OMP_PREC_FP32 && prec != OMP_PREC_BF16) return OMP_EINVAL;
+  if (!dims_ok(M, N) || B < 0 || B > ((int64_t)1 << 26)) return OMP_EINVAL;
+  if (S < 1 || S > M || S > N) return OMP_EINVAL;
+  if (S > OMP_MAX_S) return OMP_ENOTSUPP;
+  if (std::isnan(eps)) return OMP_EINVAL;
+  if (!A || lda < M || !aligned(A, 4)) return OMP_EINVAL;
+  if (B > 0 && (!Y || ldy < M || !aligned(Y, 4) || !support_out)) return OMP_EINVAL;
+  if (opts->dict) {
+    const omp_dict_t *dd = opts->dict;
+    if (dd->magic != DICT_MAGIC || dd->M != M || dd->N != N || dd->A != A || dd->precision != prec ||
+        !dd->mem)
+      return OMP_EINVAL;
+  }
+  const size_t wneed = work_bytes(M, N, B, S, prec);
+  const size_t need = wneed + (opts->dict ? 0 : dict_bytes(M, N, prec));
+  if (!opts->workspace || opts->workspace_bytes < need || !aligned(opts->workspace, ALIGN))
+    return OMP_EWORKSPACE;
+  if (B == 0) return OMP_OK;
+  int rc = check_device();
+  if (rc != OMP_OK) return rc;
+
+  // ---- enqueue ----
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  PhaseTimer timer(opts->phase_ms, opts->phase_launches, st);
+  DictView d;
+  hipError_t e = hipSuccess;
+  if (opts->dict) {
+    d = dict_view(opts->dict->mem, M, N, prec);
+  } else {
+    void *dmem = static_cast<char *>(opts->workspace) + wneed;
+    d = dict_view(dmem, M, N, prec);
+    e = timer.run(OMP_PHASE_DICT, [&] { return launch_dict_prep(A, lda, d, st); });
+    if (e == hipSuccess) e = timer.run(OMP_PHASE_DICT, [&] { return launch_gram(d, st); });
+    if (e != hipSuccess) return device_error(e);
+  }
+  const WorkView w = work_view(opts->workspace, M, N, B, S, prec);
+  e = timer.run(OMP_PHASE_INIT, [&] {
+    return launch_init(Y, ldy, opts->S_per_signal, opts->eps_per_signal, eps, d, w, prec, st);
+  });
+  for (int it = 0; it < S && e == hipSuccess; ++it) {
+    e = timer.run(OMP_PHASE_CORR, [&] { return launch_corr_select(d, w, prec, st); });
+    if (e == hipSuccess) e = timer.run(OMP_PHASE_UPDATE, [&] { return launch_update(d, w, prec, st); });
+  }
+  if (e == hipSuccess)
+    e = timer.run(OMP_PHASE_OUTPUT, [&] {
+      return launch_finalize(d, w, X_out, support_out, opts->coef_out, opts->status_out, opts->rnorm_out, st);
+    });
+  if (e == hipSuccess) e = timer.finish();
+  if (e != hipSuccess) return device_error(e);
+  return OMP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,156 @@
+"""GPU path against the FP64 oracle, through the C ABI (needs an MI355X).
+
+Sizes: the oracle finishes each case in seconds; the cases span several GEMM
+tiles with ragged tails in every padded dimension. The full-size 1024x4096
+batch of 4096 runs in the same launch configuration as the benchmark and is
+checked on a sample of signals.
+"""
+import numpy as np
+import pytest
+
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def run_gpu(w, precision="fp32", dense=True, S_per=None, eps_per=None, dictionary=False, A_pad=0, Y_pad=0):
+    torch = _torch()
+    from paper_2407_06434_amd import omp
+    dev = torch.device("cuda:0")
+    A = torch.from_numpy(w.A).to(dev)
+    Y = torch.from_numpy(w.Y).to(dev)
+    if A_pad:
+        Ab = torch.zeros((w.N, w.M + A_pad), dtype=torch.float32, device=dev)
+        Ab[:, : w.M] = A
+        A = Ab[:, : w.M]
+    if Y_pad:
+        Yb = torch.full((w.B, w.M + Y_pad), float("nan"), dtype=torch.float32, device=dev)
+        Yb[:, : w.M] = Y
+        Y = Yb[:, : w.M]
+    kw = {}
+    if S_per is not None:
+        kw["S_per_signal"] = torch.from_numpy(np.asarray(S_per, np.int32)).to(dev)
+    if eps_per is not None:
+        kw["eps_per_signal"] = torch.from_numpy(np.asarray(eps_per, np.float32)).to(dev)
+    d = omp.Dictionary(A, precision) if dictionary else None
+    res = omp.solve(A, Y, w.S, w.eps, precision=precision, dictionary=d, dense=dense, **kw)
+    torch.cuda.synchronize()
+    out = dict(support=res.support.cpu().numpy(), coef=res.coef.cpu().numpy(),
+               status=res.status.cpu().numpy(), rnorm=res.rnorm.cpu().numpy())
+    if dense:
+        out["X"] = res.X.cpu().numpy()
+    return out
+
+
+def test_plain_64x256_full(orc):
+    from paper_2407_06434_amd import workloads
+    w = workloads.plain_64x256()
+    print("case plain_64x256 B=100", flush=True)
+    rep = parity.check(w, run_gpu(w), orc)
+    print(rep)
+    assert rep["exact_support"] >= 98
+
+
+def test_batched_256x1024_prefix(orc):
+    from paper_2407_06434_amd import workloads
+    w = workloads.batched_256x1024(B=512)
+    print("case batched_256x1024 B=512", flush=True)
+    rep = parity.check(w, run_gpu(w, dictionary=True), orc)
+    print(rep)
+
+
+@pytest.mark.parametrize("M,N,B,S", [(100, 300, 77, 10), (64, 129, 130, 16), (200, 520, 259, 33),
+                                     (31, 47, 5, 31), (384, 640, 64, 70)])
+def test_ragged_shapes(orc, M, N, B, S):
+    from paper_2407_06434_amd import workloads
+    w = workloads.custom(M, N, B, S, seed=M + N, k_true=min(S, max(1, M // 4)))
+    print(f"case ragged M={M} N={N} B={B} S={S}", flush=True)
+    rep = parity.check(w, run_gpu(w, A_pad=3, Y_pad=5), orc)
+    print(rep)
+
+
+def test_full_size_1024x4096_sampled(orc):
+    """The benchmark's workload at full size (B=4096), FP32 form, 24 sampled signals."""
+    from paper_2407_06434_amd import workloads
+    w = workloads.bf16_1024x4096()
+    print("case bf16_1024x4096 B=4096 fp32", flush=True)
+    out = run_gpu(w, dictionary=True)
+    idx = np.random.default_rng(0).choice(w.B, 24, replace=False)
+    idx = np.concatenate([idx, [0, w.B - 1]])
+    rep = parity.check(w, out, orc, idx=idx)
+    print(rep)
+    k = out["status"] >> 8
+    assert np.all(k == 64)
+    # whole-batch properties: distinct picks, coefficient scale
+    s = out["support"]
+    assert all(len(set(r.tolist())) == 64 for r in s)
+
+
+def test_edge_cases(orc):
+    """y = 0, non-finite y, eps >= ||y||, per-signal S and eps, a dependent atom, a zero atom."""
+    from paper_2407_06434_amd import workloads
+    w = workloads.custom(48, 160, 12, 8, seed=3, k_true=6)
+    w.A[17] = 0.0            # zero-norm atom: never selectable
+    w.A[20] = w.A[5]         # duplicated atom
+    w.Y[1] = 0.0             # empty support
+    w.Y[2, 7] = np.nan       # NONFINITE
+    w.Y[3] = w.A[5] * 2.0    # exactly one atom (atom 5 wins the tie with its duplicate 20)
+    S_per = np.array([8, 8, 8, 8, 0, 1, 3, 8, 8, 8, 8, 8], np.int32)
+    eps_per = np.zeros(12, np.float32)
+    eps_per[6] = 1e9                                   # eps >= ||y||: k = 0
+    eps_per[7] = 0.3 * np.linalg.norm(w.Y[7].astype(np.float64))
+    w.S_per_signal, w.eps_per_signal = S_per, eps_per
+    print("case edge cases", flush=True)
+    out = run_gpu(w, S_per=S_per, eps_per=eps_per)
+    rep = parity.check(w, out, orc)
+    print(rep)
+    st = out["status"]
+    assert st[1] >> 8 == 0 and st[1] & 1
+    assert st[2] & 8 and st[2] >> 8 == 0
+    assert out["support"][3, 0] == 5
+    assert st[4] >> 8 == 0 and st[5] >> 8 == 1 and st[6] >> 8 == 0
+    assert not np.any(out["support"] == 17)
+
+
+def test_dependent_atom_stops(orc):
+    """Two atoms 1e-4 rad apart: the second pick is dependent and is not appended."""
+    from paper_2407_06434_amd import workloads
+    a0 = np.zeros(64); a0[0] = 1.0
+    a1 = np.zeros(64); a1[0] = 1.0; a1[1] = 1e-4
+    a1 /= np.linalg.norm(a1)
+    A = np.zeros((128, 64)); A[0] = a0; A[1] = a1
+    y = a1 + 0.01 * np.eye(64)[2]
+    w = workloads.Workload("dep", A.astype(np.float32), y[None].astype(np.float32), 2, 0.0)
+    out = run_gpu(w)
+    rep = parity.check(w, out, orc)
+    print(rep)
+    assert out["status"][0] & 4 and out["status"][0] >> 8 == 1
+
+
+def test_determinism_and_dictionary_reuse():
+    from paper_2407_06434_amd import workloads
+    w = workloads.batched_256x1024(B=300)
+    a = run_gpu(w)
+    b = run_gpu(w)
+    c = run_gpu(w, dictionary=True)
+    for key in ("support", "coef", "status", "rnorm", "X"):
+        assert np.array_equal(a[key], b[key]), key
+        assert np.array_equal(a[key], c[key]), key
+
+
+def test_batch_composition_independence():
+    """A signal's result does not depend on the rest of the batch or its position."""
+    from paper_2407_06434_amd import workloads
+    w = workloads.batched_256x1024(B=260)
+    full = run_gpu(w)
+    sub = workloads.Workload(w.name, w.A, w.Y[130:137].copy(), w.S, w.eps)
+    part = run_gpu(sub)
+    for key in ("support", "coef", "status", "rnorm"):
+        assert np.array_equal(full[key][130:137], part[key]), key
