@@ -112,9 +112,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
-    ap.add_argument("--compare-fp32", action="store_true",
-                    help="also time the plain FP32 form and count identical supports")
+    ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16"])
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip timing the plain FP32 form beside the BF16 form")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -167,11 +167,18 @@ def main():
         "dict_prep_ms": round(g["dict_ms"], 3),
     }
 
-    if args.compare_fp32 and args.precision != "fp32":
-        f = run_gpu(w, "fp32", max(2, args.steps // 2), 1)
-        line["fp32_signals_per_s"] = round(w.B * max(2, args.steps // 2) / f["wall"], 1)
+    if not args.no_compare and args.precision != "fp32":
+        fs = max(2, args.steps // 2)
+        f = run_gpu(w, "fp32", fs, 1)
+        fsps = w.B * fs / f["wall"]
         same = [set(a.tolist()) == set(b.tolist()) for a, b in zip(g["res"]["support"], f["res"]["support"])]
+        line["plain_fp32"] = {"value": round(fsps, 1), "unit": "signals/s", "steps": fs,
+                              "corr_avg_ms": round(f["timing"]["corr"][0] / max(f["timing"]["corr"][1], 1), 5),
+                              "update_avg_ms": round(f["timing"]["update"][0] / max(f["timing"]["update"][1], 1), 5)}
+        line["speedup_vs_plain_fp32"] = round(sps / fsps, 3)
         line["same_supports_vs_fp32"] = f"{sum(same)}/{w.B}"
+        log(f"fp32: {fsps:.0f} signals/s; same supports {sum(same)}/{w.B}")
+    line["widened_signals"] = int(np.sum((g["res"]["status"] & 64) != 0))
 
     if not args.no_cpu_baseline:
         cb, first = cpu_baseline(w, args.cpu_seconds)

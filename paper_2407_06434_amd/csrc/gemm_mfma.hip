@@ -174,13 +174,18 @@ __global__ __launch_bounds__(GramTile::NTHR) void k_gram(const float *__restrict
 // Correlation + select. For every signal j of the tile and every atom n of the
 // tile, score s = |c_nj| * inv_nu[n]; an atom is a candidate when inv_nu[n] > 0
 // (not a zero or padding atom) and its bit in the signal's selected-atom mask
-// is clear. The candidate with the largest score wins; equal scores go to the
-// lowest index. Both rules are carried by one 64-bit key,
+// is clear. A candidate is carried by one 64-bit key,
 //   key = (bits(s) << 32) | (0xFFFFFFFF - n),
-// whose unsigned maximum is the winner (bits(s) is monotone for s >= 0); key 0
-// means "no candidate". The key of each (signal, atom tile) goes to part.
+// whose unsigned maximum is the largest score with ties going to the lowest
+// index (bits(s) is monotone for s >= 0); key 0 means "no candidate".
+//
+// TOP2 = false (FP32 form): one key per (signal, tile), the tile's winner.
+// TOP2 = true  (BF16 form): each lane keeps the best and second-best key of
+//   the atoms it holds for its signal (a "subgroup" of 16 * FN atoms) and
+//   writes both; the second key bounds every unlisted atom of the subgroup,
+//   which is what the FP32 re-score needs to certify its pick.
 // ---------------------------------------------------------------------------
-template <class Op, class T>
+template <class Op, class T, bool TOP2>
 __global__ __launch_bounds__(T::NTHR) void k_corr_select(
     const typename Op::elem *__restrict__ Aop, const typename Op::elem *__restrict__ Rop, int64_t Mp,
     int64_t Np, const float *__restrict__ inv_nu, const uint32_t *__restrict__ mask,
@@ -204,37 +209,54 @@ __global__ __launch_bounds__(T::NTHR) void k_corr_select(
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wn = wave % T::WN, wb = wave / T::WN;
+  const int h = lane >> 5;
   const int64_t mwords = Np / 32;
   uint64_t *red = reinterpret_cast<uint64_t *>(lds);  // [WN][TB], LDS is free after the main loop
 #pragma unroll
   for (int j = 0; j < T::FB; ++j) {
     const int jt = wb * T::FB * 32 + j * 32 + (lane & 31);  // signal within the tile
     const int64_t b = b0 + jt;
-    uint64_t best = 0;
+    uint64_t best = 0, second = 0;
 #pragma unroll
     for (int i = 0; i < T::FN; ++i) {
       const int64_t nf = (int64_t)tn * T::TN + wn * T::FN * 32 + i * 32;  // first atom of the fragment
       const uint32_t word = mask[b * mwords + nf / 32];
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
-        const float4 iv = *reinterpret_cast<const float4 *>(inv_nu + nf + 8 * g + 4 * (lane >> 5));
+        const float4 iv = *reinterpret_cast<const float4 *>(inv_nu + nf + 8 * g + 4 * h);
         const float ivs[4] = {iv.x, iv.y, iv.z, iv.w};
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const int row = 8 * g + 4 * (lane >> 5) + e;
+          const int row = 8 * g + 4 * h + e;
           const float s = fabsf(acc[i][j][4 * g + e]) * ivs[e];
           const bool cand = ivs[e] > 0.f && !((word >> row) & 1u) && s >= 0.f;
           const uint64_t key = cand ? ((uint64_t)__float_as_uint(s) << 32) |
                                           (uint64_t)(0xFFFFFFFFu - (uint32_t)(nf + row))
                                     : 0ull;
-          best = key > best ? key : best;
+          if (TOP2) {
+            if (key > best) {
+              second = best;
+              best = key;
+            } else if (key > second) {
+              second = key;
+            }
+          } else {
+            best = key > best ? key : best;
+          }
         }
       }
     }
-    const uint64_t other = __shfl_xor(best, 32);
-    best = other > best ? other : best;
-    if (lane < 32) red[wn * T::TB + jt] = best;
+    if (TOP2) {
+      uint64_t *dst = part + b * ((int64_t)ntile * T::WN * 4) + (int64_t)tn * T::WN * 4 + (wn * 2 + h) * 2;
+      dst[0] = best;
+      dst[1] = second;
+    } else {
+      const uint64_t other = __shfl_xor(best, 32);
+      best = other > best ? other : best;
+      if (lane < 32) red[wn * T::TB + jt] = best;
+    }
   }
+  if (TOP2) return;
   __syncthreads();
   for (int t = threadIdx.x; t < T::TB; t += T::NTHR) {
     uint64_t best = 0;
@@ -259,8 +281,21 @@ hipError_t set_lds(K kernel, size_t bytes) {
 
 }  // namespace
 
-int corr_tile_atoms(int precision) { return precision == 1 ? CorrTileBF16::TN : CorrTileF32::TN; }
-int corr_candidates(int) { return 1; }
+CorrGeom corr_geometry(int precision) {
+  CorrGeom g;
+  if (precision == 1) {
+    g.tile_atoms = CorrTileBF16::TN;
+    g.keys_per_tile = CorrTileBF16::WN * 4;
+    g.sub_atoms = CorrTileBF16::FN * 32;
+    g.sub_fn = CorrTileBF16::FN;
+  } else {
+    g.tile_atoms = CorrTileF32::TN;
+    g.keys_per_tile = 1;
+    g.sub_atoms = CorrTileF32::FN * 32;
+    g.sub_fn = CorrTileF32::FN;
+  }
+  return g;
+}
 
 hipError_t launch_gram(const DictView &d, hipStream_t st) {
   using T = GramTile;
@@ -274,7 +309,7 @@ hipError_t launch_gram(const DictView &d, hipStream_t st) {
 hipError_t launch_corr_select(const DictView &d, const WorkView &w, int precision, hipStream_t st) {
   if (precision == 1) {
     using T = CorrTileBF16;
-    auto kern = k_corr_select<OpBF16, T>;
+    auto kern = k_corr_select<OpBF16, T, true>;
     hipError_t e = set_lds(kern, T::LDS_BYTES);
     if (e != hipSuccess) return e;
     const int ntile = (int)(d.Np / T::TN);
@@ -282,7 +317,7 @@ hipError_t launch_corr_select(const DictView &d, const WorkView &w, int precisio
                        w.R16, d.Mp, d.Np, d.inv_nu, w.mask, w.flags, w.part, ntile);
   } else {
     using T = CorrTileF32;
-    auto kern = k_corr_select<OpF32, T>;
+    auto kern = k_corr_select<OpF32, T, false>;
     hipError_t e = set_lds(kern, T::LDS_BYTES);
     if (e != hipSuccess) return e;
     const int ntile = (int)(d.Np / T::TN);

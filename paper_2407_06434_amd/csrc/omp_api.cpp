@@ -55,7 +55,7 @@ DictLayout dict_layout(int64_t M, int64_t N, int precision) {
 
 struct WorkLayout {
   int64_t Mp, Np, Bp;
-  int ntile, ncand;
+  int ntile, ncand, sub_atoms, sub_fn, tile_atoms;
   size_t Yp, R32, R16, part, mask, k, flags, rn, Sb, epsb, sup, u, xh, V, total;
 };
 
@@ -64,8 +64,12 @@ WorkLayout work_layout(int64_t M, int64_t N, int64_t B, int S, int precision) {
   L.Mp = round_up(M, KPAD);
   L.Np = round_up(N, NPAD);
   L.Bp = round_up(B > 0 ? B : 1, BPAD);
-  L.ntile = (int)(L.Np / corr_tile_atoms(precision));
-  L.ncand = corr_candidates(precision);
+  const CorrGeom g = corr_geometry(precision);
+  L.ntile = (int)(L.Np / g.tile_atoms);
+  L.ncand = g.keys_per_tile;
+  L.sub_atoms = g.sub_atoms;
+  L.sub_fn = g.sub_fn;
+  L.tile_atoms = g.tile_atoms;
   const size_t Bp = (size_t)L.Bp, Sz = (size_t)S;
   Carve c;
   L.Yp = c.take<float>(Bp * L.Mp);
@@ -208,6 +212,9 @@ WorkView work_view(void *mem, int64_t M, int64_t N, int64_t B, int S, int precis
   w.S = S;
   w.ntile = L.ntile;
   w.ncand = L.ncand;
+  w.sub_atoms = L.sub_atoms;
+  w.sub_fn = L.sub_fn;
+  w.tile_atoms = L.tile_atoms;
   w.Yp = at<float>(mem, L.Yp);
   w.R32 = at<float>(mem, L.R32);
   w.R16 = precision == OMP_PREC_BF16 ? at<uint16_t>(mem, L.R16) : nullptr;

@@ -46,8 +46,11 @@ DictView dict_view(void *mem, int64_t M, int64_t N, int precision);
 struct WorkView {
   int64_t B, Bp, Mp, Np;
   int S;          // sparsity cap
-  int ntile;      // number of atom tiles (partial keys per signal)
-  int ncand;      // candidate keys per (signal, tile)
+  int ntile;      // number of atom tiles of the correlation product
+  int ncand;      // keys per (signal, tile) written by the select epilogue
+  int sub_atoms;  // BF16 form: wavefront atom stride inside a tile (FN * 32)
+  int sub_fn;     // BF16 form: 32-row fragments per wavefront along the atoms
+  int tile_atoms; // atoms per tile
   float *Yp;      // [Bp][Mp] zero-padded copy of Y
   float *R32;     // [Bp][Mp] residual, FP32
   uint16_t *R16;  // [Bp][Mp] residual, BF16 (BF16 form only)
@@ -87,8 +90,18 @@ hipError_t launch_finalize(const DictView &d, const WorkView &w, float *X_out,
                            int32_t *support_out, float *coef_out, int32_t *status_out,
                            float *rnorm_out, hipStream_t st);
 
-// GEMM tile shape of the correlation product for a precision.
-int corr_tile_atoms(int precision);
-int corr_candidates(int precision);
+// Shape of the correlation product's output for a precision.
+//   FP32: one key per (signal, tile): the tile's best atom.
+//   BF16: two keys per (signal, subgroup): the best and second best BF16 scores
+//         of the subgroup; subgroup (wn, h) of tile t holds the atoms
+//         t*tile_atoms + wn*sub_atoms + 32 i + 8 g + 4 h + e
+//         for i < sub_fn, g < 4, e < 4 (the rows one lane holds in the MFMA layout).
+struct CorrGeom {
+  int tile_atoms;
+  int keys_per_tile;
+  int sub_atoms;
+  int sub_fn;
+};
+CorrGeom corr_geometry(int precision);
 
 }  // namespace bomp

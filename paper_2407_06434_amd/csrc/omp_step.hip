@@ -69,6 +69,106 @@ __device__ inline float readlane(float v, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
+// Rigorous bound on |s_bf16 - s| for one atom, where s = |a^T r| / ||a|| is the
+// score of the FP32 residual r and s_bf16 the score computed from BF16-rounded
+// a and r with FP32 accumulation over K terms:
+//   |c_bf16 - c| <= ((2 u_b + u_b^2) + gamma_K (1 + u_b)^2) sum_m |a_m r_m|
+//                <= (...) ||a|| ||r||                      (Cauchy-Schwarz),
+// u_b = 2^-8 (BF16 unit roundoff), gamma_K = K u / (1 - K u), u = 2^-24, plus
+// one FP32 rounding for the scaling by 1/||a||; a 1% margin covers the
+// rounding of ||r|| itself.
+__device__ inline double bf16_tau(double rn, int64_t K) {
+  const double ub = 1.0 / 256.0;
+  const double u = 1.0 / 16777216.0;
+  const double gk = (double)K * u / (1.0 - (double)K * u);
+  return 1.01 * ((2.0 * ub + ub * ub) + gk * (1.0 + ub) * (1.0 + ub) + 2.0 * u) * rn;
+}
+
+// Score of atom n against the FP32 residual r, |a_n^T r| / ||a_n||, with exact
+// products and FP64 accumulation (the whole wavefront cooperates).
+__device__ inline double rescore(const DictView &d, const float4 *__restrict__ r4, int n, int lane) {
+  const int64_t nc4 = d.Mp / 4;
+  const float4 *a4 = reinterpret_cast<const float4 *>(d.A32) + (int64_t)n * nc4;
+  double acc = 0.0;
+  for (int64_t c = lane; c < nc4; c += 64) {
+    const float4 a = a4[c], r = r4[c];
+    acc += (double)a.x * r.x + (double)a.y * r.y + (double)a.z * r.z + (double)a.w * r.w;
+  }
+  acc = wave_sum(acc);
+  return fabs(acc) / sqrt(d.nu2[n]);
+}
+
+__device__ inline bool better(double s, int n, double bs, int bn) { return s > bs || (s == bs && n < bn); }
+
+// BF16 form of the pick. The epilogue left, per subgroup of atoms, the keys of
+// its best and second-best BF16 score. With tau the bound above:
+//   1. s_max = largest BF16 score; every listed atom with s_bf16 >= s_max - 2 tau
+//      is re-scored exactly; the best re-scored atom w is the provisional pick.
+//      (The atom holding s_max has s >= s_max - tau, so a listed atom below the
+//      window, s <= s_bf16 + tau < s_max - tau, cannot beat w.)
+//   2. an unlisted atom of a subgroup has s <= theta + tau, theta the
+//      subgroup's second BF16 score; when theta + tau >= s_w the whole
+//      subgroup is re-scored (and the signal is flagged OMP_SIG_WIDENED).
+// The result is the exact argmax of s over the selectable atoms, ties to the
+// lowest index. Returns -1 when no atom is selectable.
+__device__ int select_bf16(const DictView &d, const WorkView &w, int64_t b, int lane, int *widened) {
+  const int nkeys = w.ntile * w.ncand;
+  const uint64_t *keys = w.part + b * nkeys;
+  const float4 *r4 = reinterpret_cast<const float4 *>(w.R32) + b * (d.Mp / 4);
+  float smax = -1.f;
+  for (int t = lane; t < nkeys; t += 64) {
+    const uint64_t k = keys[t];
+    if (k) smax = fmaxf(smax, __uint_as_float((uint32_t)(k >> 32)));
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) smax = fmaxf(smax, __shfl_xor(smax, o));
+  if (smax < 0.f) return -1;
+  const double tau = bf16_tau((double)w.rn[b], d.Mp);
+  const double thr = (double)smax - 2.0 * tau;
+  double bs = -1.0;
+  int bn = 0x7fffffff;
+  for (int t0 = 0; t0 < nkeys; t0 += 64) {
+    const int t = t0 + lane;
+    const uint64_t k = t < nkeys ? keys[t] : 0ull;
+    const bool cand = k && (double)__uint_as_float((uint32_t)(k >> 32)) >= thr;
+    uint64_t m = __ballot(cand);
+    const int n_l = (int)(0xFFFFFFFFu - (uint32_t)(k & 0xFFFFFFFFull));
+    while (m) {
+      const int l = __ffsll((unsigned long long)m) - 1;
+      m &= m - 1;
+      const int n = __builtin_amdgcn_readlane(n_l, l);
+      const double sc = rescore(d, r4, n, lane);
+      if (better(sc, n, bs, bn)) { bs = sc; bn = n; }
+    }
+  }
+  const int64_t mwords = d.Np / 32;
+  const uint32_t *mk = w.mask + b * mwords;
+  for (int t0 = 0; t0 < nkeys; t0 += 64) {
+    const int t = t0 + lane;
+    const uint64_t k = (t < nkeys && (t & 1)) ? keys[t] : 0ull;
+    const bool open = k && (double)__uint_as_float((uint32_t)(k >> 32)) + tau >= bs;
+    uint64_t m = __ballot(open);
+    while (m) {
+      const int l = __ffsll((unsigned long long)m) - 1;
+      m &= m - 1;
+      const int slot = t0 + l;
+      const int tile = slot / w.ncand;
+      const int sg = (slot % w.ncand) >> 1;
+      const int wn = sg >> 1, hh = sg & 1;
+      *widened = 1;
+      for (int i = 0; i < w.sub_fn; ++i)
+        for (int g = 0; g < 4; ++g)
+          for (int e = 0; e < 4; ++e) {
+            const int n = tile * w.tile_atoms + wn * w.sub_atoms + 32 * i + 8 * g + 4 * hh + e;
+            if (d.inv_nu[n] <= 0.f || ((mk[n >> 5] >> (n & 31)) & 1u)) continue;
+            const double sc = rescore(d, r4, n, lane);
+            if (better(sc, n, bs, bn)) { bs = sc; bn = n; }
+          }
+    }
+  }
+  return bn;
+}
+
 // ---------------------------------------------------------------------------
 // Dictionary preparation: one wavefront per (padded) atom.
 // ---------------------------------------------------------------------------
@@ -141,8 +241,8 @@ __global__ __launch_bounds__(64) void k_init(const float *__restrict__ Y, int64_
 // (S <= 64 RPL; RPL in {1, 2, 4}).
 // LDS: V (S(S+1)/2 floats), coefficients (S floats), support (S ints).
 // ---------------------------------------------------------------------------
-template <int RPL>
-__global__ __launch_bounds__(64) void k_update(DictView d, WorkView w, int precision) {
+template <int RPL, bool BF16>
+__global__ __launch_bounds__(64) void k_update(DictView d, WorkView w) {
   extern __shared__ float smem[];
   const int64_t b = blockIdx.x;
   const int lane = threadIdx.x;
@@ -155,19 +255,27 @@ __global__ __launch_bounds__(64) void k_update(DictView d, WorkView w, int preci
   int *ss = reinterpret_cast<int *>(xs + S);
   const int k = w.k[b];
 
-  // 1. The winner over all atom tiles (largest score, then lowest index).
-  uint64_t best = 0;
-  const int nkeys = w.ntile * w.ncand;
-  for (int t = lane; t < nkeys; t += 64) {
-    const uint64_t v = w.part[b * nkeys + t];
-    best = v > best ? v : best;
+  // 1. The pick: the winner over all atom tiles (largest score, then lowest
+  //    index); in the BF16 form, the certified exact re-score of the candidates.
+  int nstar = -1;
+  int widened = 0;
+  if (BF16) {
+    nstar = select_bf16(d, w, b, lane, &widened);
+  } else {
+    uint64_t best = 0;
+    const int nkeys = w.ntile * w.ncand;
+    for (int t = lane; t < nkeys; t += 64) {
+      const uint64_t v = w.part[b * nkeys + t];
+      best = v > best ? v : best;
+    }
+    best = wave_max(best);
+    if (best != 0ull) nstar = (int)(0xFFFFFFFFu - (uint32_t)(best & 0xFFFFFFFFull));
   }
-  best = wave_max(best);
-  if (best == 0ull) {  // nothing selectable is left
+  if (nstar < 0) {  // nothing selectable is left
     if (lane == 0) w.flags[b] = fl0 | FLAG_DONE | OMP_SIG_EXHAUSTED;
     return;
   }
-  const int nstar = (int)(0xFFFFFFFFu - (uint32_t)(best & 0xFFFFFFFFull));
+  const int fl1 = fl0 | (widened ? OMP_SIG_WIDENED : 0);
 
   // 2. Support and packed factor into LDS.
   for (int t = lane; t < k; t += 64) ss[t] = w.sup[b * S + t];
@@ -205,7 +313,7 @@ __global__ __launch_bounds__(64) void k_update(DictView d, WorkView w, int preci
   const double nu2 = d.nu2[nstar];
   const double d2 = nu2 - zz;
   if (!(d2 > DEP_TOL2 * nu2)) {  // dependent atom: stop without appending
-    if (lane == 0) w.flags[b] = fl0 | FLAG_DONE | OMP_SIG_DEPENDENT;
+    if (lane == 0) w.flags[b] = fl1 | FLAG_DONE | OMP_SIG_DEPENDENT;
     return;
   }
   const float dk = (float)sqrt(d2);
@@ -316,7 +424,7 @@ __global__ __launch_bounds__(64) void k_update(DictView d, WorkView w, int preci
       const int64_t c = base + lane + 64 * cc;
       if (c < nc4) {
         R4[c] = r[cc];
-        if (precision == OMP_PREC_BF16) {
+        if (BF16) {
           ushort4 h;
           h.x = f32_to_bf16_rne(r[cc].x);
           h.y = f32_to_bf16_rne(r[cc].y);
@@ -334,7 +442,7 @@ __global__ __launch_bounds__(64) void k_update(DictView d, WorkView w, int preci
   // 10. Stop test.
   if (lane == 0) {
     const double rn = sqrt(nrm);
-    int fl = fl0;
+    int fl = fl1;
     if (rn <= (double)w.epsb[b]) fl |= FLAG_DONE | OMP_SIG_EPS;
     if (K >= w.Sb[b]) fl |= FLAG_DONE | OMP_SIG_SMAX;
     w.k[b] = K;
@@ -401,19 +509,24 @@ hipError_t launch_update(const DictView &d, const WorkView &w, int precision, hi
   const size_t lds = ((size_t)w.S * (w.S + 1) / 2 + 2 * (size_t)w.S) * 4;
   const dim3 grid((unsigned)w.B), block(64);
   if (w.B == 0) return hipSuccess;
+  const bool bf = precision == OMP_PREC_BF16;
   if (w.S <= 64) {
-    hipLaunchKernelGGL(k_update<1>, grid, block, lds, st, d, w, precision);
+    if (bf) hipLaunchKernelGGL((k_update<1, true>), grid, block, lds, st, d, w);
+    else hipLaunchKernelGGL((k_update<1, false>), grid, block, lds, st, d, w);
   } else if (w.S <= 128) {
-    hipLaunchKernelGGL(k_update<2>, grid, block, lds, st, d, w, precision);
+    if (bf) hipLaunchKernelGGL((k_update<2, true>), grid, block, lds, st, d, w);
+    else hipLaunchKernelGGL((k_update<2, false>), grid, block, lds, st, d, w);
   } else {
-    static bool attr = false;
-    if (!attr) {
-      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_update<4>),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    static bool attr[2] = {false, false};
+    const void *fn = bf ? reinterpret_cast<const void *>(k_update<4, true>)
+                        : reinterpret_cast<const void *>(k_update<4, false>);
+    if (!attr[bf]) {
+      hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
       if (e != hipSuccess) return e;
-      attr = true;
+      attr[bf] = true;
     }
-    hipLaunchKernelGGL(k_update<4>, grid, block, lds, st, d, w, precision);
+    if (bf) hipLaunchKernelGGL((k_update<4, true>), grid, block, lds, st, d, w);
+    else hipLaunchKernelGGL((k_update<4, false>), grid, block, lds, st, d, w);
   }
   return hipGetLastError();
 }
