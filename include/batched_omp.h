@@ -105,7 +105,9 @@ int omp_dict_init(omp_dict_t *dict, const float *A, int64_t M, int64_t N, int64_
 /* ---- options ------------------------------------------------------------ */
 typedef struct omp_opts {
   int32_t precision;            /* OMP_PREC_FP32 (default) or OMP_PREC_BF16 */
-  int32_t reserved0;
+  int32_t tile_config;          /* correlation tiles (atoms x signals): 0 = chosen by shape
+                                   (default), 1 = 128x128, 2 = 256x256 (4 wavefronts),
+                                   3 = 256x256 (8 wavefronts), 4 = 256x128 */
   const int32_t *S_per_signal;  /* device [B], optional: per-signal S_b in 0..S */
   const float *eps_per_signal;  /* device [B], optional: per-signal eps_b (replaces eps) */
   int32_t *status_out;          /* device [B], optional: (k_b << 8) | OMP_SIG_* bits */
@@ -128,9 +130,10 @@ typedef struct omp_opts {
 #define OMP_PHASE_DICT 0     /* dictionary preparation inside omp_solve (no prepared dictionary) */
 #define OMP_PHASE_INIT 1     /* padded copies of Y, norms, stop tests */
 #define OMP_PHASE_CORR 2     /* correlation product A^T R with the fused select epilogue */
-#define OMP_PHASE_UPDATE 3   /* Cholesky append, solves, residual, stop test */
+#define OMP_PHASE_UPDATE 3   /* stop test, pick (BF16: exact re-score), Cholesky append, solves */
 #define OMP_PHASE_OUTPUT 4   /* dense X, support, coefficients, status */
-#define OMP_NPHASE 5
+#define OMP_PHASE_RESIDUAL 5 /* residual r = y - A_S x, its BF16 copy and norm */
+#define OMP_NPHASE 6
 
 /* Fill `opts` with the defaults (FP32, no optional arrays, no workspace). */
 void omp_opts_default(omp_opts_t *opts);

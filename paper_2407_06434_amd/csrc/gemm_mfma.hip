@@ -30,11 +30,14 @@ namespace {
 
 typedef __attribute__((ext_vector_type(16))) float f32x16;
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+// 16-byte chunk as a native vector (HIP's uint4 is a union-based struct that
+// can keep arrays of it out of registers).
+typedef __attribute__((ext_vector_type(4))) unsigned int u32x4;
 
 struct OpF32 {
   using elem = float;
   // One 16-byte chunk holds 4 FP32 values of K: four 32x32x2 MFMAs.
-  __device__ static inline void mma(const uint4 &a, const uint4 &b, f32x16 &c) {
+  __device__ static inline void mma(const u32x4 &a, const u32x4 &b, f32x16 &c) {
     c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.x), __uint_as_float(b.x), c, 0, 0, 0);
     c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.y), __uint_as_float(b.y), c, 0, 0, 0);
     c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.z), __uint_as_float(b.z), c, 0, 0, 0);
@@ -45,7 +48,7 @@ struct OpF32 {
 struct OpBF16 {
   using elem = uint16_t;
   // One 16-byte chunk holds 8 BF16 values of K: one 32x32x16 MFMA.
-  __device__ static inline void mma(const uint4 &a, const uint4 &b, f32x16 &c) {
+  __device__ static inline void mma(const u32x4 &a, const u32x4 &b, f32x16 &c) {
     c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
                                                 __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
   }
@@ -70,8 +73,8 @@ struct Tile {
 // Main loop: acc += P_tile * Q_tile^T over `nslices` K slices of 128 bytes.
 // P points at the tile's first row, rows `prs` chunks apart; likewise Q.
 template <class Op, class T>
-__device__ inline void mainloop(const uint4 *__restrict__ P, int64_t prs, const uint4 *__restrict__ Q,
-                                int64_t qrs, int nslices, uint4 *lds, f32x16 (&acc)[T::FN][T::FB]) {
+__device__ inline void mainloop(const u32x4 *__restrict__ P, int64_t prs, const u32x4 *__restrict__ Q,
+                                int64_t qrs, int nslices, u32x4 *lds, f32x16 (&acc)[T::FN][T::FB]) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wn = wave % T::WN, wb = wave / T::WN;
@@ -82,45 +85,49 @@ __device__ inline void mainloop(const uint4 *__restrict__ P, int64_t prs, const 
 #pragma unroll
     for (int j = 0; j < T::FB; ++j) acc[i][j] = f32x16{};
 
-  uint4 ra[T::A_LD], rb[T::B_LD];
-  auto gload = [&](int s) {
+  u32x4 ra[T::A_LD], rb[T::B_LD];
+  // Stage 0: global -> registers -> LDS buffer 0.
 #pragma unroll
-    for (int i = 0; i < T::A_LD; ++i) {
-      const int idx = tid + i * T::NTHR;
-      ra[i] = P[(int64_t)(idx / T::CH) * prs + (int64_t)s * T::CH + (idx % T::CH)];
-    }
+  for (int i = 0; i < T::A_LD; ++i) {
+    const int idx = tid + i * T::NTHR;
+    ra[i] = P[(int64_t)(idx / T::CH) * prs + (idx % T::CH)];
+  }
 #pragma unroll
-    for (int i = 0; i < T::B_LD; ++i) {
-      const int idx = tid + i * T::NTHR;
-      rb[i] = Q[(int64_t)(idx / T::CH) * qrs + (int64_t)s * T::CH + (idx % T::CH)];
-    }
-  };
-  auto lstore = [&](int buf) {
-    uint4 *la = lds + buf * T::STAGE;
-    uint4 *lb = la + T::TN * T::RS;
+  for (int i = 0; i < T::B_LD; ++i) {
+    const int idx = tid + i * T::NTHR;
+    rb[i] = Q[(int64_t)(idx / T::CH) * qrs + (idx % T::CH)];
+  }
 #pragma unroll
-    for (int i = 0; i < T::A_LD; ++i) {
-      const int idx = tid + i * T::NTHR;
-      la[(idx / T::CH) * T::RS + (idx % T::CH)] = ra[i];
-    }
+  for (int i = 0; i < T::A_LD; ++i) {
+    const int idx = tid + i * T::NTHR;
+    lds[(idx / T::CH) * T::RS + (idx % T::CH)] = ra[i];
+  }
 #pragma unroll
-    for (int i = 0; i < T::B_LD; ++i) {
-      const int idx = tid + i * T::NTHR;
-      lb[(idx / T::CH) * T::RS + (idx % T::CH)] = rb[i];
-    }
-  };
-
-  gload(0);
-  lstore(0);
+  for (int i = 0; i < T::B_LD; ++i) {
+    const int idx = tid + i * T::NTHR;
+    lds[T::TN * T::RS + (idx / T::CH) * T::RS + (idx % T::CH)] = rb[i];
+  }
   __syncthreads();
   for (int s = 0; s < nslices; ++s) {
     const int buf = s & 1;
-    if (s + 1 < nslices) gload(s + 1);
-    const uint4 *la = lds + buf * T::STAGE + (wn * T::FN * 32 + r32) * T::RS + h;
-    const uint4 *lb = lds + buf * T::STAGE + T::TN * T::RS + (wb * T::FB * 32 + r32) * T::RS + h;
+    const bool more = s + 1 < nslices;
+    if (more) {  // prefetch slice s+1 into registers while slice s is multiplied
+#pragma unroll
+      for (int i = 0; i < T::A_LD; ++i) {
+        const int idx = tid + i * T::NTHR;
+        ra[i] = P[(int64_t)(idx / T::CH) * prs + (int64_t)(s + 1) * T::CH + (idx % T::CH)];
+      }
+#pragma unroll
+      for (int i = 0; i < T::B_LD; ++i) {
+        const int idx = tid + i * T::NTHR;
+        rb[i] = Q[(int64_t)(idx / T::CH) * qrs + (int64_t)(s + 1) * T::CH + (idx % T::CH)];
+      }
+    }
+    const u32x4 *la = lds + buf * T::STAGE + (wn * T::FN * 32 + r32) * T::RS + h;
+    const u32x4 *lb = lds + buf * T::STAGE + T::TN * T::RS + (wb * T::FB * 32 + r32) * T::RS + h;
 #pragma unroll
     for (int q = 0; q < T::CH / 2; ++q) {
-      uint4 af[T::FN], bf[T::FB];
+      u32x4 af[T::FN], bf[T::FB];
 #pragma unroll
       for (int i = 0; i < T::FN; ++i) af[i] = la[i * 32 * T::RS + 2 * q];
 #pragma unroll
@@ -130,7 +137,19 @@ __device__ inline void mainloop(const uint4 *__restrict__ P, int64_t prs, const 
 #pragma unroll
         for (int j = 0; j < T::FB; ++j) Op::mma(af[i], bf[j], acc[i][j]);
     }
-    if (s + 1 < nslices) lstore(buf ^ 1);
+    if (more) {
+      u32x4 *nb = lds + (buf ^ 1) * T::STAGE;
+#pragma unroll
+      for (int i = 0; i < T::A_LD; ++i) {
+        const int idx = tid + i * T::NTHR;
+        nb[(idx / T::CH) * T::RS + (idx % T::CH)] = ra[i];
+      }
+#pragma unroll
+      for (int i = 0; i < T::B_LD; ++i) {
+        const int idx = tid + i * T::NTHR;
+        nb[T::TN * T::RS + (idx / T::CH) * T::RS + (idx % T::CH)] = rb[i];
+      }
+    }
     __syncthreads();
   }
 }
@@ -146,12 +165,12 @@ using GramTile = Tile<128, 128, 2, 2>;
 __global__ __launch_bounds__(GramTile::NTHR) void k_gram(const float *__restrict__ A32, int64_t Mp,
                                                          int64_t Np, float *__restrict__ G) {
   using T = GramTile;
-  extern __shared__ uint4 lds[];
+  extern __shared__ u32x4 lds[];
   const int ntn = (int)(Np / T::TN);
   const int tn = blockIdx.x % ntn, tm = blockIdx.x / ntn;
   const int64_t rs = Mp / 4;  // row stride in 16-byte chunks
-  const uint4 *P = reinterpret_cast<const uint4 *>(A32) + (int64_t)tn * T::TN * rs;
-  const uint4 *Q = reinterpret_cast<const uint4 *>(A32) + (int64_t)tm * T::TB * rs;
+  const u32x4 *P = reinterpret_cast<const u32x4 *>(A32) + (int64_t)tn * T::TN * rs;
+  const u32x4 *Q = reinterpret_cast<const u32x4 *>(A32) + (int64_t)tm * T::TB * rs;
   f32x16 acc[T::FN][T::FB];
   mainloop<OpF32, T>(P, rs, Q, rs, (int)(rs / T::CH), lds, acc);
 
@@ -190,7 +209,7 @@ __global__ __launch_bounds__(T::NTHR) void k_corr_select(
     const typename Op::elem *__restrict__ Aop, const typename Op::elem *__restrict__ Rop, int64_t Mp,
     int64_t Np, const float *__restrict__ inv_nu, const uint32_t *__restrict__ mask,
     const int32_t *__restrict__ flags, uint64_t *__restrict__ part, int ntile) {
-  extern __shared__ uint4 lds[];
+  extern __shared__ u32x4 lds[];
   const int tn = blockIdx.x % ntile, tb = blockIdx.x / ntile;
   const int64_t b0 = (int64_t)tb * T::TB;
 
@@ -202,8 +221,8 @@ __global__ __launch_bounds__(T::NTHR) void k_corr_select(
 
   constexpr int EPC = 16 / sizeof(typename Op::elem);  // elements per 16-byte chunk
   const int64_t rs = Mp / EPC;
-  const uint4 *P = reinterpret_cast<const uint4 *>(Aop) + (int64_t)tn * T::TN * rs;
-  const uint4 *Q = reinterpret_cast<const uint4 *>(Rop) + b0 * rs;
+  const u32x4 *P = reinterpret_cast<const u32x4 *>(Aop) + (int64_t)tn * T::TN * rs;
+  const u32x4 *Q = reinterpret_cast<const u32x4 *>(Rop) + b0 * rs;
   f32x16 acc[T::FN][T::FB];
   mainloop<Op, T>(P, rs, Q, rs, (int)(rs / T::CH), lds, acc);
 
@@ -211,6 +230,9 @@ __global__ __launch_bounds__(T::NTHR) void k_corr_select(
   const int wn = wave % T::WN, wb = wave / T::WN;
   const int h = lane >> 5;
   const int64_t mwords = Np / 32;
+  constexpr int SUBF = T::FN >= 2 ? 2 : 1;  // fragments per subgroup (TOP2)
+  constexpr int SPH = T::FN / SUBF;         // subgroups per lane
+  constexpr int KPT = T::WN * SPH * 4;      // keys per (signal, tile) (TOP2)
   uint64_t *red = reinterpret_cast<uint64_t *>(lds);  // [WN][TB], LDS is free after the main loop
 #pragma unroll
   for (int j = 0; j < T::FB; ++j) {
@@ -245,12 +267,15 @@ __global__ __launch_bounds__(T::NTHR) void k_corr_select(
           }
         }
       }
+      if (TOP2 && (i % SUBF) == SUBF - 1) {
+        const int ig = i / SUBF;
+        uint64_t *dst = part + b * ((int64_t)ntile * KPT) + (int64_t)tn * KPT + ((wn * SPH + ig) * 2 + h) * 2;
+        dst[0] = best;
+        dst[1] = second;
+        best = second = 0;
+      }
     }
-    if (TOP2) {
-      uint64_t *dst = part + b * ((int64_t)ntile * T::WN * 4) + (int64_t)tn * T::WN * 4 + (wn * 2 + h) * 2;
-      dst[0] = best;
-      dst[1] = second;
-    } else {
+    if (!TOP2) {
       const uint64_t other = __shfl_xor(best, 32);
       best = other > best ? other : best;
       if (lane < 32) red[wn * T::TB + jt] = best;
@@ -266,8 +291,15 @@ __global__ __launch_bounds__(T::NTHR) void k_corr_select(
   }
 }
 
-using CorrTileF32 = Tile<128, 128, 2, 2>;
-using CorrTileBF16 = Tile<128, 128, 2, 2>;
+// Tile configurations (atoms x signals, wavefront grid):
+//   1: 128 x 128, 2 x 2 wavefronts of 64 x 64
+//   2: 256 x 256, 2 x 2 wavefronts of 128 x 128 (accumulators in AGPRs)
+//   3: 256 x 256, 2 x 4 wavefronts of 128 x 64
+//   4: 256 x 128, 2 x 2 wavefronts of 128 x 64
+using Cfg1 = Tile<128, 128, 2, 2>;
+using Cfg2 = Tile<256, 256, 2, 2>;
+using Cfg3 = Tile<256, 256, 2, 4>;
+using Cfg4 = Tile<256, 128, 2, 2>;
 
 template <class K>
 hipError_t set_lds(K kernel, size_t bytes) {
@@ -279,22 +311,42 @@ hipError_t set_lds(K kernel, size_t bytes) {
   return e;
 }
 
+template <class Op, class T, bool TOP2>
+hipError_t launch_corr_t(const typename Op::elem *Aop, const typename Op::elem *Rop, const DictView &d,
+                         const WorkView &w, hipStream_t st) {
+  auto kern = k_corr_select<Op, T, TOP2>;
+  hipError_t e = set_lds(kern, T::LDS_BYTES);
+  if (e != hipSuccess) return e;
+  const int ntile = (int)(d.Np / T::TN);
+  hipLaunchKernelGGL(kern, dim3((unsigned)(ntile * (w.Bp / T::TB))), dim3(T::NTHR), T::LDS_BYTES, st, Aop, Rop,
+                     d.Mp, d.Np, d.inv_nu, w.mask, w.flags, w.part, ntile);
+  return hipGetLastError();
+}
+
+template <class T>
+CorrGeom geom(int precision, int cfg) {
+  CorrGeom g;
+  constexpr int SUBF = T::FN >= 2 ? 2 : 1;
+  g.cfg = cfg;
+  g.tile_atoms = T::TN;
+  g.tile_signals = T::TB;
+  g.keys_per_tile = precision == 1 ? T::WN * (T::FN / SUBF) * 4 : 1;
+  g.wave_atoms = T::FN * 32;
+  g.sub_frags = SUBF;
+  g.subs_per_half = T::FN / SUBF;
+  return g;
+}
+
 }  // namespace
 
-CorrGeom corr_geometry(int precision) {
-  CorrGeom g;
-  if (precision == 1) {
-    g.tile_atoms = CorrTileBF16::TN;
-    g.keys_per_tile = CorrTileBF16::WN * 4;
-    g.sub_atoms = CorrTileBF16::FN * 32;
-    g.sub_fn = CorrTileBF16::FN;
-  } else {
-    g.tile_atoms = CorrTileF32::TN;
-    g.keys_per_tile = 1;
-    g.sub_atoms = CorrTileF32::FN * 32;
-    g.sub_fn = CorrTileF32::FN;
+CorrGeom corr_geometry(int precision, int64_t Np, int64_t Bp, int cfg) {
+  if (cfg == 0) cfg = (Np / 256) * (Bp / 256) >= 192 ? 3 : 1;
+  switch (cfg) {
+    case 2: return geom<Cfg2>(precision, 2);
+    case 3: return geom<Cfg3>(precision, 3);
+    case 4: return geom<Cfg4>(precision, 4);
+    default: return geom<Cfg1>(precision, 1);
   }
-  return g;
 }
 
 hipError_t launch_gram(const DictView &d, hipStream_t st) {
@@ -306,25 +358,19 @@ hipError_t launch_gram(const DictView &d, hipStream_t st) {
   return hipGetLastError();
 }
 
+template <class T>
+hipError_t launch_corr_cfg(const DictView &d, const WorkView &w, int precision, hipStream_t st) {
+  if (precision == 1) return launch_corr_t<OpBF16, T, true>(d.A16, w.R16, d, w, st);
+  return launch_corr_t<OpF32, T, false>(d.A32, w.R32, d, w, st);
+}
+
 hipError_t launch_corr_select(const DictView &d, const WorkView &w, int precision, hipStream_t st) {
-  if (precision == 1) {
-    using T = CorrTileBF16;
-    auto kern = k_corr_select<OpBF16, T, true>;
-    hipError_t e = set_lds(kern, T::LDS_BYTES);
-    if (e != hipSuccess) return e;
-    const int ntile = (int)(d.Np / T::TN);
-    hipLaunchKernelGGL(kern, dim3(ntile * (w.Bp / T::TB)), dim3(T::NTHR), T::LDS_BYTES, st, d.A16,
-                       w.R16, d.Mp, d.Np, d.inv_nu, w.mask, w.flags, w.part, ntile);
-  } else {
-    using T = CorrTileF32;
-    auto kern = k_corr_select<OpF32, T, false>;
-    hipError_t e = set_lds(kern, T::LDS_BYTES);
-    if (e != hipSuccess) return e;
-    const int ntile = (int)(d.Np / T::TN);
-    hipLaunchKernelGGL(kern, dim3(ntile * (w.Bp / T::TB)), dim3(T::NTHR), T::LDS_BYTES, st, d.A32,
-                       w.R32, d.Mp, d.Np, d.inv_nu, w.mask, w.flags, w.part, ntile);
+  switch (w.tile_cfg) {
+    case 2: return launch_corr_cfg<Cfg2>(d, w, precision, st);
+    case 3: return launch_corr_cfg<Cfg3>(d, w, precision, st);
+    case 4: return launch_corr_cfg<Cfg4>(d, w, precision, st);
+    default: return launch_corr_cfg<Cfg1>(d, w, precision, st);
   }
-  return hipGetLastError();
 }
 
 }  // namespace bomp

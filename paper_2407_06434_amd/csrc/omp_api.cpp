@@ -36,7 +36,7 @@ struct Carve {
 
 struct DictLayout {
   int64_t Mp, Np;
-  size_t nu2, inv_nu, A32, G, A16, total;
+  size_t nu2, inv_nu, A32, G, A16, aerr, aerr_max, total;
 };
 
 DictLayout dict_layout(int64_t M, int64_t N, int precision) {
@@ -49,43 +49,49 @@ DictLayout dict_layout(int64_t M, int64_t N, int precision) {
   L.A32 = c.take<float>((size_t)L.Np * L.Mp);
   L.G = c.take<float>((size_t)L.Np * L.Np);
   L.A16 = precision == OMP_PREC_BF16 ? c.take<uint16_t>((size_t)L.Np * L.Mp) : 0;
+  L.aerr = c.take<float>(L.Np);
+  L.aerr_max = c.take<float>(1);
   L.total = (c.off + ALIGN - 1) / ALIGN * ALIGN;
   return L;
 }
 
 struct WorkLayout {
   int64_t Mp, Np, Bp;
-  int ntile, ncand, sub_atoms, sub_fn, tile_atoms;
-  size_t Yp, R32, R16, part, mask, k, flags, rn, Sb, epsb, sup, u, xh, V, total;
+  CorrGeom g;
+  int ntile;
+  int nslice, slice_len;
+  int64_t vstride;
+  size_t Yp, R32, R16, part, mask, k, flags, pnorm, pdelta, Sb, epsb, sup, u, xh, V, total;
 };
 
-WorkLayout work_layout(int64_t M, int64_t N, int64_t B, int S, int precision) {
+WorkLayout work_layout(int64_t M, int64_t N, int64_t B, int S, int precision, int cfg) {
   WorkLayout L;
   L.Mp = round_up(M, KPAD);
   L.Np = round_up(N, NPAD);
   L.Bp = round_up(B > 0 ? B : 1, BPAD);
-  const CorrGeom g = corr_geometry(precision);
-  L.ntile = (int)(L.Np / g.tile_atoms);
-  L.ncand = g.keys_per_tile;
-  L.sub_atoms = g.sub_atoms;
-  L.sub_fn = g.sub_fn;
-  L.tile_atoms = g.tile_atoms;
+  L.g = corr_geometry(precision, L.Np, L.Bp, cfg);
+  L.ntile = (int)(L.Np / L.g.tile_atoms);
+  // Slice the residual over the XCDs when the FP32 dictionary outgrows one L2.
+  L.nslice = (L.Np * L.Mp * 4 > (int64_t)2 << 20) ? NSLICE_MAX : 1;
+  L.slice_len = (int)(L.Mp / L.nslice);
   const size_t Bp = (size_t)L.Bp, Sz = (size_t)S;
   Carve c;
   L.Yp = c.take<float>(Bp * L.Mp);
   L.R32 = c.take<float>(Bp * L.Mp);
   L.R16 = precision == OMP_PREC_BF16 ? c.take<uint16_t>(Bp * L.Mp) : 0;
-  L.part = c.take<uint64_t>(Bp * L.ntile * L.ncand);
+  L.part = c.take<uint64_t>(Bp * L.ntile * L.g.keys_per_tile);
   L.mask = c.take<uint32_t>(Bp * (L.Np / 32));
   L.k = c.take<int32_t>(Bp);
   L.flags = c.take<int32_t>(Bp);
-  L.rn = c.take<float>(Bp);
+  L.pnorm = c.take<double>(Bp * NSLICE_MAX);
+  L.pdelta = c.take<double>(Bp * NSLICE_MAX);
   L.Sb = c.take<int32_t>(Bp);
   L.epsb = c.take<float>(Bp);
   L.sup = c.take<int32_t>(Bp * Sz);
   L.u = c.take<float>(Bp * Sz);
   L.xh = c.take<float>(Bp * Sz);
-  L.V = c.take<float>(Bp * (Sz * (Sz + 1) / 2));
+  L.vstride = round_up((int64_t)(Sz * (Sz + 1) / 2), 4);
+  L.V = c.take<float>(Bp * (size_t)L.vstride);
   L.total = (c.off + ALIGN - 1) / ALIGN * ALIGN;
   return L;
 }
@@ -195,26 +201,30 @@ DictView dict_view(void *mem, int64_t M, int64_t N, int precision) {
   d.A32 = at<float>(mem, L.A32);
   d.G = at<float>(mem, L.G);
   d.A16 = precision == OMP_PREC_BF16 ? at<uint16_t>(mem, L.A16) : nullptr;
+  d.aerr = at<float>(mem, L.aerr);
+  d.aerr_max = at<float>(mem, L.aerr_max);
   return d;
 }
 
-size_t work_bytes(int64_t M, int64_t N, int64_t B, int S, int precision) {
-  return work_layout(M, N, B, S, precision).total;
+size_t work_bytes(int64_t M, int64_t N, int64_t B, int S, int precision, int cfg) {
+  return work_layout(M, N, B, S, precision, cfg).total;
 }
 
-WorkView work_view(void *mem, int64_t M, int64_t N, int64_t B, int S, int precision) {
-  const WorkLayout L = work_layout(M, N, B, S, precision);
+WorkView work_view(void *mem, int64_t M, int64_t N, int64_t B, int S, int precision, int cfg) {
+  const WorkLayout L = work_layout(M, N, B, S, precision, cfg);
   WorkView w;
   w.B = B;
   w.Bp = L.Bp;
   w.Mp = L.Mp;
   w.Np = L.Np;
   w.S = S;
+  w.tile_cfg = L.g.cfg;
   w.ntile = L.ntile;
-  w.ncand = L.ncand;
-  w.sub_atoms = L.sub_atoms;
-  w.sub_fn = L.sub_fn;
-  w.tile_atoms = L.tile_atoms;
+  w.ncand = L.g.keys_per_tile;
+  w.tile_atoms = L.g.tile_atoms;
+  w.wave_atoms = L.g.wave_atoms;
+  w.sub_frags = L.g.sub_frags;
+  w.subs_per_half = L.g.subs_per_half;
   w.Yp = at<float>(mem, L.Yp);
   w.R32 = at<float>(mem, L.R32);
   w.R16 = precision == OMP_PREC_BF16 ? at<uint16_t>(mem, L.R16) : nullptr;
@@ -222,7 +232,11 @@ WorkView work_view(void *mem, int64_t M, int64_t N, int64_t B, int S, int precis
   w.mask = at<uint32_t>(mem, L.mask);
   w.k = at<int32_t>(mem, L.k);
   w.flags = at<int32_t>(mem, L.flags);
-  w.rn = at<float>(mem, L.rn);
+  w.pnorm = at<double>(mem, L.pnorm);
+  w.pdelta = at<double>(mem, L.pdelta);
+  w.vstride = L.vstride;
+  w.nslice = L.nslice;
+  w.slice_len = L.slice_len;
   w.Sb = at<int32_t>(mem, L.Sb);
   w.epsb = at<float>(mem, L.epsb);
   w.sup = at<int32_t>(mem, L.sup);
@@ -294,7 +308,9 @@ size_t omp_workspace_size(int64_t M, int64_t N, int64_t B, int32_t S, const omp_
   const int prec = opts ? opts->precision : OMP_PREC_FP32;
   if (!dims_ok(M, N) || B < 0 || B > ((int64_t)1 << 26) || S < 1 || S > OMP_MAX_S) return 0;
   if (prec != OMP_PREC_FP32 && prec != OMP_PREC_BF16) return 0;
-  size_t total = work_bytes(M, N, B, S, prec);
+  const int cfg = opts ? opts->tile_config : 0;
+  if (cfg < 0 || cfg > 4) return 0;
+  size_t total = work_bytes(M, N, B, S, prec, cfg);
   if (!opts || !opts->dict) total += dict_bytes(M, N, prec);
   return total;
 }
@@ -306,6 +322,8 @@ int omp_solve(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y,
   if (!opts) return OMP_EINVAL;
   const int prec = opts->precision;
   if (prec != OMP_PREC_FP32 && prec != OMP_PREC_BF16) return OMP_EINVAL;
+  const int cfg = opts->tile_config;
+  if (cfg < 0 || cfg > 4) return OMP_EINVAL;
   if (!dims_ok(M, N) || B < 0 || B > ((int64_t)1 << 26)) return OMP_EINVAL;
   if (S < 1 || S > M || S > N) return OMP_EINVAL;
   if (S > OMP_MAX_S) return OMP_ENOTSUPP;
@@ -318,7 +336,7 @@ int omp_solve(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y,
         !dd->mem)
       return OMP_EINVAL;
   }
-  const size_t wneed = work_bytes(M, N, B, S, prec);
+  const size_t wneed = work_bytes(M, N, B, S, prec, cfg);
   const size_t need = wneed + (opts->dict ? 0 : dict_bytes(M, N, prec));
   if (!opts->workspace || opts->workspace_bytes < need || !aligned(opts->workspace, ALIGN))
     return OMP_EWORKSPACE;
@@ -340,13 +358,14 @@ int omp_solve(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y,
     if (e == hipSuccess) e = timer.run(OMP_PHASE_DICT, [&] { return launch_gram(d, st); });
     if (e != hipSuccess) return device_error(e);
   }
-  const WorkView w = work_view(opts->workspace, M, N, B, S, prec);
+  const WorkView w = work_view(opts->workspace, M, N, B, S, prec, cfg);
   e = timer.run(OMP_PHASE_INIT, [&] {
     return launch_init(Y, ldy, opts->S_per_signal, opts->eps_per_signal, eps, d, w, prec, st);
   });
   for (int it = 0; it < S && e == hipSuccess; ++it) {
     e = timer.run(OMP_PHASE_CORR, [&] { return launch_corr_select(d, w, prec, st); });
-    if (e == hipSuccess) e = timer.run(OMP_PHASE_UPDATE, [&] { return launch_update(d, w, prec, st); });
+    if (e == hipSuccess) e = timer.run(OMP_PHASE_UPDATE, [&] { return launch_solve(d, w, prec, st); });
+    if (e == hipSuccess) e = timer.run(OMP_PHASE_RESIDUAL, [&] { return launch_residual(d, w, prec, st); });
   }
   if (e == hipSuccess)
     e = timer.run(OMP_PHASE_OUTPUT, [&] {

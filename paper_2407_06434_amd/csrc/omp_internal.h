@@ -15,15 +15,19 @@ namespace bomp {
 //   Np  atoms, multiple of the GEMM atom tile
 //   Bp  signals, multiple of the GEMM signal tile
 constexpr int KPAD = 64;
-constexpr int NPAD = 128;
-constexpr int BPAD = 128;
+constexpr int NPAD = 256;
+constexpr int BPAD = 256;
 
 // Squared dependency threshold on the Cholesky pivot: an atom whose distance to
 // the span of the support is at most 1e-3 of its norm is not appended.
 constexpr double DEP_TOL2 = 1e-6;
 
 // Internal per-signal flag bits (the low byte holds the public OMP_SIG_* bits).
-constexpr int FLAG_DONE = 1 << 16;
+constexpr int FLAG_DONE = 1 << 16;  // the signal takes no further picks
+constexpr int FLAG_NEWX = 1 << 17;  // coefficients changed: the residual kernel must run
+
+// The residual is computed in up to this many slices of M (one per XCD).
+constexpr int NSLICE_MAX = 8;
 
 constexpr uint32_t DICT_MAGIC = 0x4f4d5044u;  // "OMPD"
 
@@ -37,6 +41,8 @@ struct DictView {
   float *A32;      // [Np][Mp] zero-padded FP32 copy of A, atom-major
   float *G;        // [Np][Np] Gram matrix A^T A, FP32, row-major
   uint16_t *A16;   // [Np][Mp] BF16 (round to nearest even) copy of A, or nullptr
+  float *aerr;     // [Np]   ||a_n - bf16(a_n)|| / ||a_n|| (BF16 form), 0 for zero atoms
+  float *aerr_max; // [1]    max_n aerr[n] (BF16 form)
 };
 
 size_t dict_bytes(int64_t M, int64_t N, int precision);
@@ -46,11 +52,13 @@ DictView dict_view(void *mem, int64_t M, int64_t N, int precision);
 struct WorkView {
   int64_t B, Bp, Mp, Np;
   int S;          // sparsity cap
-  int ntile;      // number of atom tiles of the correlation product
-  int ncand;      // keys per (signal, tile) written by the select epilogue
-  int sub_atoms;  // BF16 form: wavefront atom stride inside a tile (FN * 32)
-  int sub_fn;     // BF16 form: 32-row fragments per wavefront along the atoms
-  int tile_atoms; // atoms per tile
+  int tile_cfg;      // correlation tile configuration (CorrGeom::cfg)
+  int ntile;         // number of atom tiles of the correlation product
+  int ncand;         // keys per (signal, tile) written by the select epilogue
+  int tile_atoms;    // atoms per tile
+  int wave_atoms;    // atom stride between the wavefront rows of a tile (FN * 32)
+  int sub_frags;     // BF16 form: 32-row fragments per subgroup
+  int subs_per_half; // BF16 form: subgroups per wavefront half
   float *Yp;      // [Bp][Mp] zero-padded copy of Y
   float *R32;     // [Bp][Mp] residual, FP32
   uint16_t *R16;  // [Bp][Mp] residual, BF16 (BF16 form only)
@@ -58,17 +66,21 @@ struct WorkView {
   uint32_t *mask; // [Bp][Np/32] selected-atom bitmask
   int32_t *k;     // [Bp] atoms selected so far
   int32_t *flags; // [Bp] FLAG_DONE | OMP_SIG_* bits
-  float *rn;      // [Bp] current ||r||
+  double *pnorm; // [Bp][NSLICE_MAX] ||r||^2 of each slice of the current residual
+  double *pdelta;// [Bp][NSLICE_MAX] ||r - bf16(r)||^2 of each slice (BF16 form)
+  int nslice;     // slices of M used by the residual kernel (1 or NSLICE_MAX)
+  int slice_len;  // floats per slice (Mp / nslice, a multiple of 4)
   int32_t *Sb;    // [Bp] per-signal sparsity cap
   float *epsb;    // [Bp] per-signal tolerance (>= 0)
   int32_t *sup;   // [Bp][S] support in selection order
   float *u;       // [Bp][S] forward-solve vector V^{-1} A_S^T y
   float *xh;      // [Bp][S] current coefficients
-  float *V;       // [Bp][S(S+1)/2] packed lower-triangular Cholesky factor, row by row
+  int64_t vstride; // floats per signal in V: S(S+1)/2 rounded up to a multiple of 4
+  float *V;       // [Bp][vstride] packed lower-triangular Cholesky factor, row by row
 };
 
-size_t work_bytes(int64_t M, int64_t N, int64_t B, int S, int precision);
-WorkView work_view(void *mem, int64_t M, int64_t N, int64_t B, int S, int precision);
+size_t work_bytes(int64_t M, int64_t N, int64_t B, int S, int precision, int cfg);
+WorkView work_view(void *mem, int64_t M, int64_t N, int64_t B, int S, int precision, int cfg);
 
 // ---- launchers (all enqueue on `st`, return the launch status) -------------
 
@@ -83,25 +95,32 @@ hipError_t launch_init(const float *Y, int64_t ldy, const int32_t *S_per, const 
                        hipStream_t st);
 // Correlation A^T R with the fused select epilogue -> w.part.
 hipError_t launch_corr_select(const DictView &d, const WorkView &w, int precision, hipStream_t st);
-// One OMP step per active signal: merge, Cholesky append, solves, residual, stop test.
-hipError_t launch_update(const DictView &d, const WorkView &w, int precision, hipStream_t st);
+// One OMP step per live signal: stop test, pick, Cholesky append, both solves.
+hipError_t launch_solve(const DictView &d, const WorkView &w, int precision, hipStream_t st);
+// Residual r = y - A_S x (and its BF16 copy and per-slice norms) for the signals just updated.
+hipError_t launch_residual(const DictView &d, const WorkView &w, int precision, hipStream_t st);
 // Outputs: dense X, support, coefficients, status, residual norm.
 hipError_t launch_finalize(const DictView &d, const WorkView &w, float *X_out,
                            int32_t *support_out, float *coef_out, int32_t *status_out,
                            float *rnorm_out, hipStream_t st);
 
-// Shape of the correlation product's output for a precision.
+// Tile configuration and output structure of the correlation product.
 //   FP32: one key per (signal, tile): the tile's best atom.
-//   BF16: two keys per (signal, subgroup): the best and second best BF16 scores
-//         of the subgroup; subgroup (wn, h) of tile t holds the atoms
-//         t*tile_atoms + wn*sub_atoms + 32 i + 8 g + 4 h + e
-//         for i < sub_fn, g < 4, e < 4 (the rows one lane holds in the MFMA layout).
+//   BF16: two keys (best, second best BF16 score) per (signal, subgroup). The
+//         lane holding signal j in wavefront row wn, half h (lane / 32) owns,
+//         for fragment i, the atoms 32 i + 8 g + 4 h + e (g, e < 4) of its rows;
+//         subgroup ig of that lane is fragments ig*sub_frags .. +sub_frags-1.
+//         Key slot in the tile: ((wn * subs_per_half + ig) * 2 + h) * 2 + {0, 1};
+//         atom: t*tile_atoms + wn*wave_atoms + 32 (ig*sub_frags + i') + 8 g + 4 h + e.
 struct CorrGeom {
-  int tile_atoms;
+  int cfg;  // tile configuration 1..4 (see the correlation kernels)
+  int tile_atoms, tile_signals;
   int keys_per_tile;
-  int sub_atoms;
-  int sub_fn;
+  int wave_atoms;
+  int sub_frags;
+  int subs_per_half;
 };
-CorrGeom corr_geometry(int precision);
+// cfg 0 picks by shape: 256 x 256 tiles when that still gives about one tile per CU.
+CorrGeom corr_geometry(int precision, int64_t Np, int64_t Bp, int cfg);
 
 }  // namespace bomp

@@ -1,19 +1,27 @@
 // Per-signal kernels of the OMP iteration for gfx950: dictionary preparation,
-// solve set-up, the update step after each correlation product, and the output
-// scatter. One 64-lane wavefront owns one signal in the update step.
+// solve set-up, the two kernels that follow each correlation product, and the
+// output scatter.
 //
-// The update step is the least-squares half of Algorithm 1 done by the
-// progressive Cholesky factorisation of Section 2.2 (Eqs. 4-5), with the Gram
-// row taken from the precomputed A^T A:
+// After the correlation product has scored every atom, one iteration of
+// Algorithm 1 finishes in two kernels:
 //
-//   g   = G[n*, support]                  (A_{k-1}^T a_n*, Eq. 3 via the Gram)
-//   z   = V_{k-1}^{-1} g                  (forward solve, Eq. 5)
-//   d   = sqrt(||a_n*||^2 - ||z||^2)      (new pivot, Eq. 5; FP64 subtraction)
-//   V_k = [[V_{k-1}, 0], [z^T, d]]        (append one row)
+// k_solve (one 64-lane wavefront per signal): the pick and the least-squares
+// update by the progressive Cholesky factorisation of Section 2.2 (Eqs. 4-5),
+// with the Gram row taken from the precomputed A^T A:
+//
+//   g    = G[n*, support]                 (A_{k-1}^T a_n*, Eq. 3 via the Gram)
+//   z    = V_{k-1}^{-1} g                 (forward solve, Eq. 5)
+//   d    = sqrt(||a_n*||^2 - ||z||^2)     (new pivot, Eq. 5; FP64 subtraction)
+//   V_k  = [[V_{k-1}, 0], [z^T, d]]       (append one row)
 //   beta = a_n*^T y                       (append to A_k^T y, Eq. 2)
-//   u_k = (beta - z^T u_{k-1}) / d        (forward solve V_k u = A_k^T y, one new entry)
-//   x   = V_k^{-T} u                      (back solve)
-//   r   = y - A_k x                       (recomputed from y, no drift)
+//   u_k  = (beta - z^T u_{k-1}) / d       (forward solve V_k u = A_k^T y, one new entry)
+//   x    = V_k^{-T} u                     (back solve)
+//
+// k_residual: r = y - A_k x, recomputed from y at every step (no drift), with
+// ||r||^2 accumulated in FP64 per slice of the signal. The signal is cut into
+// up to 8 slices of M and workgroup i works on slice i mod 8: workgroups are
+// dispatched round-robin over the 8 XCDs, so every XCD only ever gathers its
+// own eighth of the dictionary's columns, which then stays in its L2.
 //
 // The paper's code re-factorised A_k^T A_k at every step and names the
 // Cholesky update as its next step (Section 3.6); this file implements that
@@ -69,64 +77,137 @@ __device__ inline float readlane(float v, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
-// Rigorous bound on |s_bf16 - s| for one atom, where s = |a^T r| / ||a|| is the
-// score of the FP32 residual r and s_bf16 the score computed from BF16-rounded
-// a and r with FP32 accumulation over K terms:
-//   |c_bf16 - c| <= ((2 u_b + u_b^2) + gamma_K (1 + u_b)^2) sum_m |a_m r_m|
-//                <= (...) ||a|| ||r||                      (Cauchy-Schwarz),
-// u_b = 2^-8 (BF16 unit roundoff), gamma_K = K u / (1 - K u), u = 2^-24, plus
-// one FP32 rounding for the scaling by 1/||a||; a 1% margin covers the
-// rounding of ||r|| itself.
-__device__ inline double bf16_tau(double rn, int64_t K) {
-  const double ub = 1.0 / 256.0;
-  const double u = 1.0 / 16777216.0;
-  const double gk = (double)K * u / (1.0 - (double)K * u);
-  return 1.01 * ((2.0 * ub + ub * ub) + gk * (1.0 + ub) * (1.0 + ub) + 2.0 * u) * rn;
+// Current ||r|| of signal b from its per-slice partial sums of squares.
+__device__ inline double residual_norm(const WorkView &w, int64_t b) {
+  double s = 0.0;
+  for (int i = 0; i < NSLICE_MAX; ++i) s += w.pnorm[b * NSLICE_MAX + i];
+  return sqrt(s);
 }
 
-// Score of atom n against the FP32 residual r, |a_n^T r| / ||a_n||, with exact
-// products and FP64 accumulation (the whole wavefront cooperates).
-__device__ inline double rescore(const DictView &d, const float4 *__restrict__ r4, int n, int lane) {
-  const int64_t nc4 = d.Mp / 4;
-  const float4 *a4 = reinterpret_cast<const float4 *>(d.A32) + (int64_t)n * nc4;
-  double acc = 0.0;
-  for (int64_t c = lane; c < nc4; c += 64) {
-    const float4 a = a4[c], r = r4[c];
-    acc += (double)a.x * r.x + (double)a.y * r.y + (double)a.z * r.z + (double)a.w * r.w;
-  }
-  acc = wave_sum(acc);
-  return fabs(acc) / sqrt(d.nu2[n]);
+// Rigorous bound on |s_bf16 - s| for every atom, where s = |a^T r| / ||a|| is
+// the exact score of the FP32 residual r and s_bf16 the score the BF16 product
+// computed from a~ = bf16(a), r~ = bf16(r). With e = a - a~, delta = r - r~:
+//   a^T r - a~^T r~ = a~^T delta + e^T r~ + e^T delta
+//   |a^T r - a~^T r~| <= ||a|| ((1 + 2 E) D + E R~)       (Cauchy-Schwarz)
+// where E = max_n ||e_n|| / ||a_n|| (measured once per dictionary), D = ||delta||
+// (measured with each residual) and R~ = ||r~|| <= ||r|| + D. The BF16 products
+// are exact in FP32; their FP32 accumulation over K terms adds at most
+// gamma_K ||a~|| ||r~|| <= gamma_K (1 + E) ||a|| R~, gamma_K = K u / (1 - K u),
+// u = 2^-24; scaling by the FP32 1/||a|| adds 2 u (s + T) <= 2 u (||r|| + T).
+// This is far tighter than the worst case u_bf16 ||a|| ||r||: rounding errors
+// have norm ~ 2^-8 / sqrt(3) relative, not 2^-8.
+__device__ inline double bf16_tau(double rn, double dn, double E, int64_t K) {
+  const double u = 1.0 / 16777216.0;
+  const double gk = (double)K * u / (1.0 - (double)K * u);
+  const double Rt = rn + dn;
+  const double T = (1.0 + 2.0 * E) * dn + E * Rt + gk * (1.0 + E) * Rt;
+  return (T * (1.0 + 4.0 * u) + 2.0 * u * (rn + T)) * (1.0 + 1e-9) + 1e-30;
 }
 
 __device__ inline bool better(double s, int n, double bs, int bn) { return s > bs || (s == bs && n < bn); }
 
+__device__ inline double dot4d(const float4 &a, const float4 &v) {
+  return (double)a.x * v.x + (double)a.y * v.y + (double)a.z * v.z + (double)a.w * v.w;
+}
+
+// FP64 dot products of up to NA atoms (n[i] < 0: unused) with the vector v
+// and, when TWO, also with y: exact products, FP64 accumulation. The whole
+// wavefront cooperates; each lane keeps four 16-byte chunks of every operand
+// in flight per pass, and the reductions run interleaved.
+template <int NA, bool TWO>
+__device__ __attribute__((always_inline)) inline void atom_dots(const DictView &d, const int (&n)[NA], const float4 *__restrict__ v4,
+                                 const float4 *__restrict__ y4, int lane, double (&av)[NA], double (&ay)[NA]) {
+  const int64_t nc4 = d.Mp / 4;
+  const float4 *A4 = reinterpret_cast<const float4 *>(d.A32);
+  const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+  for (int i = 0; i < NA; ++i) av[i] = ay[i] = 0.0;
+  for (int64_t c0 = 0; c0 < nc4; c0 += 256) {
+    float4 vv[4], yy[4], aa[NA][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t c = c0 + lane + 64 * q;
+      const bool ok = c < nc4;
+      vv[q] = ok ? v4[c] : zero;
+      yy[q] = (TWO && ok) ? y4[c] : zero;
+#pragma unroll
+      for (int i = 0; i < NA; ++i) aa[i][q] = (ok && n[i] >= 0) ? A4[(int64_t)n[i] * nc4 + c] : zero;
+    }
+#pragma unroll
+    for (int i = 0; i < NA; ++i)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        av[i] += dot4d(aa[i][q], vv[q]);
+        if (TWO) ay[i] += dot4d(aa[i][q], yy[q]);
+      }
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1)
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      av[i] += __shfl_xor(av[i], o);
+      if (TWO) ay[i] += __shfl_xor(ay[i], o);
+    }
+}
+
+// Queue of atoms to re-score against r, flushed two at a time (all values
+// wave-uniform; a pick has about two candidates on the benchmark workload);
+// keeps the best exact score, its atom, and that atom's a^T y.
+struct RescoreQueue {
+  int n0 = -1, n1 = -1;
+  double bs = -1.0;
+  double by = 0.0;
+  int bn = 0x7fffffff;
+  __device__ __attribute__((always_inline)) void flush(const DictView &d, const float4 *r4, const float4 *y4,
+                                                       int lane) {
+    if (n0 < 0) return;
+    const int n[2] = {n0, n1};
+    double ar[2], ay[2];
+    atom_dots<2, true>(d, n, r4, y4, lane, ar, ay);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      if (n[i] < 0) continue;
+      const double sc = fabs(ar[i]) / sqrt(d.nu2[n[i]]);
+      if (better(sc, n[i], bs, bn)) {
+        bs = sc;
+        bn = n[i];
+        by = ay[i];
+      }
+    }
+    n0 = n1 = -1;
+  }
+  __device__ __attribute__((always_inline)) void push(int atom, const DictView &d, const float4 *r4,
+                                                      const float4 *y4, int lane) {
+    if (n0 < 0) {
+      n0 = atom;
+    } else {
+      n1 = atom;
+      flush(d, r4, y4, lane);
+    }
+  }
+};
+
 // BF16 form of the pick. The epilogue left, per subgroup of atoms, the keys of
-// its best and second-best BF16 score. With tau the bound above:
-//   1. s_max = largest BF16 score; every listed atom with s_bf16 >= s_max - 2 tau
-//      is re-scored exactly; the best re-scored atom w is the provisional pick.
-//      (The atom holding s_max has s >= s_max - tau, so a listed atom below the
-//      window, s <= s_bf16 + tau < s_max - tau, cannot beat w.)
+// its best and second-best BF16 score. With tau the bound above and s_max the
+// largest BF16 score:
+//   1. every listed atom with s_bf16 >= s_max - 2 tau is re-scored exactly; the
+//      best re-scored atom w is the provisional pick. (The atom holding s_max has
+//      s >= s_max - tau, so a listed atom below the window, s <= s_bf16 + tau <
+//      s_max - tau, cannot beat w.)
 //   2. an unlisted atom of a subgroup has s <= theta + tau, theta the
 //      subgroup's second BF16 score; when theta + tau >= s_w the whole
 //      subgroup is re-scored (and the signal is flagged OMP_SIG_WIDENED).
 // The result is the exact argmax of s over the selectable atoms, ties to the
-// lowest index. Returns -1 when no atom is selectable.
-__device__ int select_bf16(const DictView &d, const WorkView &w, int64_t b, int lane, int *widened) {
+// lowest index; *beta receives a_n*^T y of the pick (computed in the same pass
+// as its score) and *nu2 its ||a_n*||^2.
+__device__ int select_bf16(const DictView &d, const WorkView &w, int64_t b, float smax, double tau, int lane,
+                           int *widened, double *beta) {
   const int nkeys = w.ntile * w.ncand;
   const uint64_t *keys = w.part + b * nkeys;
   const float4 *r4 = reinterpret_cast<const float4 *>(w.R32) + b * (d.Mp / 4);
-  float smax = -1.f;
-  for (int t = lane; t < nkeys; t += 64) {
-    const uint64_t k = keys[t];
-    if (k) smax = fmaxf(smax, __uint_as_float((uint32_t)(k >> 32)));
-  }
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) smax = fmaxf(smax, __shfl_xor(smax, o));
-  if (smax < 0.f) return -1;
-  const double tau = bf16_tau((double)w.rn[b], d.Mp);
+  const float4 *y4 = reinterpret_cast<const float4 *>(w.Yp) + b * (d.Mp / 4);
   const double thr = (double)smax - 2.0 * tau;
-  double bs = -1.0;
-  int bn = 0x7fffffff;
+  RescoreQueue q;
   for (int t0 = 0; t0 < nkeys; t0 += 64) {
     const int t = t0 + lane;
     const uint64_t k = t < nkeys ? keys[t] : 0ull;
@@ -136,37 +217,47 @@ __device__ int select_bf16(const DictView &d, const WorkView &w, int64_t b, int 
     while (m) {
       const int l = __ffsll((unsigned long long)m) - 1;
       m &= m - 1;
-      const int n = __builtin_amdgcn_readlane(n_l, l);
-      const double sc = rescore(d, r4, n, lane);
-      if (better(sc, n, bs, bn)) { bs = sc; bn = n; }
+      q.push(__builtin_amdgcn_readlane(n_l, l), d, r4, y4, lane);
     }
   }
+  q.flush(d, r4, y4, lane);
   const int64_t mwords = d.Np / 32;
   const uint32_t *mk = w.mask + b * mwords;
   for (int t0 = 0; t0 < nkeys; t0 += 64) {
     const int t = t0 + lane;
     const uint64_t k = (t < nkeys && (t & 1)) ? keys[t] : 0ull;
-    const bool open = k && (double)__uint_as_float((uint32_t)(k >> 32)) + tau >= bs;
+    const bool open = k && (double)__uint_as_float((uint32_t)(k >> 32)) + tau >= q.bs;
     uint64_t m = __ballot(open);
     while (m) {
       const int l = __ffsll((unsigned long long)m) - 1;
       m &= m - 1;
       const int slot = t0 + l;
       const int tile = slot / w.ncand;
-      const int sg = (slot % w.ncand) >> 1;
-      const int wn = sg >> 1, hh = sg & 1;
+      const int sgl = (slot % w.ncand) >> 1;  // ((wn * subs_per_half + ig) * 2 + h)
+      const int hh = sgl & 1;
+      const int ig = (sgl >> 1) % w.subs_per_half;
+      const int wn = (sgl >> 1) / w.subs_per_half;
       *widened = 1;
-      for (int i = 0; i < w.sub_fn; ++i)
+      for (int i = 0; i < w.sub_frags; ++i)
         for (int g = 0; g < 4; ++g)
           for (int e = 0; e < 4; ++e) {
-            const int n = tile * w.tile_atoms + wn * w.sub_atoms + 32 * i + 8 * g + 4 * hh + e;
+            const int n = tile * w.tile_atoms + wn * w.wave_atoms + 32 * (ig * w.sub_frags + i) + 8 * g + 4 * hh + e;
             if (d.inv_nu[n] <= 0.f || ((mk[n >> 5] >> (n & 31)) & 1u)) continue;
-            const double sc = rescore(d, r4, n, lane);
-            if (better(sc, n, bs, bn)) { bs = sc; bn = n; }
+            q.push(n, d, r4, y4, lane);
           }
+      q.flush(d, r4, y4, lane);
     }
   }
-  return bn;
+  *beta = q.by;
+  return q.bn == 0x7fffffff ? -1 : q.bn;
+}
+
+// Intra-wavefront LDS ordering: one wavefront's LDS instructions execute in
+// order, so it suffices that the compiler keeps them in program order.
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // ---------------------------------------------------------------------------
@@ -175,21 +266,44 @@ __device__ int select_bf16(const DictView &d, const WorkView &w, int64_t b, int 
 __global__ __launch_bounds__(64) void k_dict_prep(const float *__restrict__ A, int64_t lda, int64_t M,
                                                   int64_t N, int64_t Mp, double *__restrict__ nu2,
                                                   float *__restrict__ inv_nu, float *__restrict__ A32,
-                                                  uint16_t *__restrict__ A16) {
+                                                  uint16_t *__restrict__ A16, float *__restrict__ aerr) {
   const int64_t n = blockIdx.x;
   const int lane = threadIdx.x;
-  double s = 0.0;
+  double s = 0.0, e = 0.0;
   for (int64_t m = lane; m < Mp; m += 64) {
     const float v = (n < N && m < M) ? A[n * lda + m] : 0.f;
     A32[n * Mp + m] = v;
-    if (A16) A16[n * Mp + m] = f32_to_bf16_rne(v);
+    if (A16) {
+      const uint16_t h = f32_to_bf16_rne(v);
+      A16[n * Mp + m] = h;
+      const double dv = (double)v - (double)__uint_as_float((uint32_t)h << 16);
+      e += dv * dv;
+    }
     s += (double)v * (double)v;
   }
   s = wave_sum(s);
+  e = wave_sum(e);
   if (lane == 0) {
     nu2[n] = s;
     inv_nu[n] = s > 0.0 ? (float)(1.0 / sqrt(s)) : 0.f;
+    // rounded up so that the float is an upper bound of the ratio
+    aerr[n] = s > 0.0 ? __double2float_ru(sqrt(e / s) * (1.0 + 1e-12)) : 0.f;
   }
+}
+
+// max_n aerr[n] over the dictionary (one block).
+__global__ __launch_bounds__(1024) void k_dict_aerr_max(const float *__restrict__ aerr, int64_t Np,
+                                                        float *__restrict__ out) {
+  __shared__ float red[1024];
+  float m = 0.f;
+  for (int64_t n = threadIdx.x; n < Np; n += 1024) m = fmaxf(m, aerr[n]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = 512; o >= 1; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -202,7 +316,7 @@ __global__ __launch_bounds__(64) void k_init(const float *__restrict__ Y, int64_
   const int64_t b = blockIdx.x;
   const int lane = threadIdx.x;
   const bool real = b < w.B;
-  double s = 0.0;
+  double s = 0.0, dl = 0.0;
   int finite = 1;
   for (int64_t m = lane; m < w.Mp; m += 64) {
     const float v = (real && m < M) ? Y[b * ldy + m] : 0.f;
@@ -210,13 +324,23 @@ __global__ __launch_bounds__(64) void k_init(const float *__restrict__ Y, int64_
     const float vz = isfinite(v) ? v : 0.f;
     w.Yp[b * w.Mp + m] = vz;
     w.R32[b * w.Mp + m] = vz;
-    if (w.R16) w.R16[b * w.Mp + m] = f32_to_bf16_rne(vz);
+    if (w.R16) {
+      const uint16_t h = f32_to_bf16_rne(vz);
+      w.R16[b * w.Mp + m] = h;
+      const double dv = (double)vz - (double)__uint_as_float((uint32_t)h << 16);
+      dl += dv * dv;
+    }
     s += (double)vz * (double)vz;
   }
   const int64_t mwords = w.Np / 32;
   for (int64_t t = lane; t < mwords; t += 64) w.mask[b * mwords + t] = 0u;
   s = wave_sum(s);
+  dl = wave_sum(dl);
   const bool all_finite = __all(finite);
+  if (lane < NSLICE_MAX) {
+    w.pnorm[b * NSLICE_MAX + lane] = (lane == 0 && all_finite) ? s : 0.0;
+    w.pdelta[b * NSLICE_MAX + lane] = (lane == 0 && all_finite) ? dl : 0.0;
+  }
   if (lane == 0) {
     int Sb = w.S;
     if (S_per && real) Sb = min(max(S_per[b], 0), w.S);
@@ -226,82 +350,150 @@ __global__ __launch_bounds__(64) void k_init(const float *__restrict__ Y, int64_
     int fl = 0;
     if (!real) fl = FLAG_DONE;
     else if (!all_finite) fl = FLAG_DONE | OMP_SIG_NONFINITE;
-    else if (rn <= (double)eb) fl = FLAG_DONE | OMP_SIG_EPS | (Sb == 0 ? OMP_SIG_SMAX : 0);
-    else if (Sb == 0) fl = FLAG_DONE | OMP_SIG_SMAX;
+    else if (rn <= (double)eb || Sb == 0) fl = FLAG_DONE;
     w.flags[b] = fl;
     w.k[b] = 0;
-    w.rn[b] = real && all_finite ? (float)rn : 0.f;
     w.Sb[b] = Sb;
     w.epsb[b] = eb;
   }
 }
 
 // ---------------------------------------------------------------------------
-// Update step. One 64-lane block per signal; RPL = rows of V per lane
-// (S <= 64 RPL; RPL in {1, 2, 4}).
-// LDS: V (S(S+1)/2 floats), coefficients (S floats), support (S ints).
+// Solve step. One 64-lane wavefront per signal, SOLVE_WAVES signals per block
+// (the wavefronts share nothing; each has its own LDS region). RPL = rows of V
+// per lane (S <= 64 RPL; RPL in {1, 2, 4}).
+// LDS per wavefront: V (vstride floats), support (S ints).
+// Memory is read in three rounds: what depends on the signal only (state,
+// norms, the epilogue's keys), then what depends on the state (support,
+// factor, u) together with what depends on the keys (the re-score of the
+// candidates, or a_n*^T y), and last the Gram row of the pick.
+// The triangular solves run column by column; the reciprocal diagonal is
+// computed up front in parallel and the next column is read from LDS while
+// the current one is applied, so the sequential chain holds no division and
+// no LDS latency.
 // ---------------------------------------------------------------------------
-template <int RPL, bool BF16>
-__global__ __launch_bounds__(64) void k_update(DictView d, WorkView w) {
-  extern __shared__ float smem[];
-  const int64_t b = blockIdx.x;
-  const int lane = threadIdx.x;
-  const int fl0 = w.flags[b];
-  if (fl0 & FLAG_DONE) return;  // whole block exits together
-  const int S = w.S;
-  const int64_t VS = (int64_t)S * (S + 1) / 2;
-  float *Vs = smem;
-  float *xs = Vs + VS;
-  int *ss = reinterpret_cast<int *>(xs + S);
-  const int k = w.k[b];
+constexpr int SOLVE_WAVES = 4;
 
-  // 1. The pick: the winner over all atom tiles (largest score, then lowest
-  //    index); in the BF16 form, the certified exact re-score of the candidates.
-  int nstar = -1;
-  int widened = 0;
-  if (BF16) {
-    nstar = select_bf16(d, w, b, lane, &widened);
-  } else {
-    uint64_t best = 0;
-    const int nkeys = w.ntile * w.ncand;
-    for (int t = lane; t < nkeys; t += 64) {
-      const uint64_t v = w.part[b * nkeys + t];
-      best = v > best ? v : best;
-    }
-    best = wave_max(best);
-    if (best != 0ull) nstar = (int)(0xFFFFFFFFu - (uint32_t)(best & 0xFFFFFFFFull));
+template <int RPL, bool BF16>
+__global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView w) {
+  extern __shared__ float smem[];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t b = (int64_t)blockIdx.x * SOLVE_WAVES + wv;
+  if (b >= w.B) return;
+  const int S = w.S;
+  const int64_t VS = w.vstride;
+  float *Vs = smem + (size_t)wv * (VS + S);
+  int *ss = reinterpret_cast<int *>(Vs + VS);
+
+  // ---- round 1: state, residual norms, keys
+  int fl = w.flags[b];
+  const int k = w.k[b];
+  const double pn = lane < NSLICE_MAX ? w.pnorm[b * NSLICE_MAX + lane] : 0.0;
+  const double pd = (BF16 && lane < NSLICE_MAX) ? w.pdelta[b * NSLICE_MAX + lane] : 0.0;
+  const int nkeys = w.ntile * w.ncand;
+  const uint64_t *keys = w.part + b * nkeys;
+  uint64_t kmax = 0;
+#pragma unroll 4
+  for (int t = lane; t < nkeys; t += 64) {
+    const uint64_t v = keys[t];
+    kmax = v > kmax ? v : kmax;
   }
-  if (nstar < 0) {  // nothing selectable is left
-    if (lane == 0) w.flags[b] = fl0 | FLAG_DONE | OMP_SIG_EXHAUSTED;
+  if (fl & FLAG_NEWX) {
+    fl &= ~FLAG_NEWX;
+    if (lane == 0) w.flags[b] = fl;
+  }
+  if (fl & FLAG_DONE) return;  // the wavefront exits as a whole
+
+  // 0. Stop test on the current residual (Algorithm 1 stops once ||r|| <= eps).
+  const double rn = sqrt(wave_sum(pn));
+  if (rn <= (double)w.epsb[b]) {
+    if (lane == 0) w.flags[b] = fl | FLAG_DONE;
     return;
   }
-  const int fl1 = fl0 | (widened ? OMP_SIG_WIDENED : 0);
+  kmax = wave_max(kmax);
+  if (kmax == 0ull) {  // nothing selectable is left
+    if (lane == 0) w.flags[b] = fl | FLAG_DONE | OMP_SIG_EXHAUSTED;
+    return;
+  }
 
-  // 2. Support and packed factor into LDS.
+  // ---- round 2: support and packed factor into LDS, u into registers ...
   for (int t = lane; t < k; t += 64) ss[t] = w.sup[b * S + t];
-  const int64_t vlen = (int64_t)k * (k + 1) / 2;
-  for (int64_t t = lane; t < vlen; t += 64) Vs[t] = w.V[b * VS + t];
-  __syncthreads();
-
-  // 3. Gram row g_i = G[n*, support_i]; lane holds rows i = lane + 64 p.
-  float g[RPL], z[RPL];
+  {
+    const int64_t nv4 = ((int64_t)k * (k + 1) / 2 + 3) / 4;
+    const float4 *V4 = reinterpret_cast<const float4 *>(w.V + b * VS);
+    float4 *Vs4 = reinterpret_cast<float4 *>(Vs);
+#pragma unroll 4
+    for (int64_t t = lane; t < nv4; t += 64) Vs4[t] = V4[t];
+  }
+  float uo[RPL];
 #pragma unroll
   for (int p = 0; p < RPL; ++p) {
     const int i = lane + 64 * p;
+    uo[p] = i < k ? w.u[b * S + i] : 0.f;
+  }
+
+  // ... and, beside them, the pick: the best key over all atom tiles (largest
+  // score, then lowest index), or in the BF16 form the certified exact
+  // re-score of the candidates; beta = a_n*^T y (exact products, FP64 sum).
+  int nstar;
+  int widened = 0;
+  double beta = 0.0;
+  if (BF16) {
+    const double tau = bf16_tau(rn, sqrt(wave_sum(pd)), (double)d.aerr_max[0], d.Mp);
+    nstar = select_bf16(d, w, b, __uint_as_float((uint32_t)(kmax >> 32)), tau, lane, &widened, &beta);
+    if (nstar < 0) {
+      if (lane == 0) w.flags[b] = fl | FLAG_DONE | OMP_SIG_EXHAUSTED;
+      return;
+    }
+  } else {
+    nstar = (int)(0xFFFFFFFFu - (uint32_t)(kmax & 0xFFFFFFFFull));
+    const int na[1] = {nstar};
+    double ay[1], unused[1];
+    atom_dots<1, false>(d, na, reinterpret_cast<const float4 *>(w.Yp) + b * (d.Mp / 4), nullptr, lane, ay,
+                        unused);
+    beta = ay[0];
+  }
+  if (widened) fl |= OMP_SIG_WIDENED;
+  const double nu2 = d.nu2[nstar];
+  wave_lds_sync();  // support and factor are in LDS
+
+  // ---- round 3: Gram row g_i = G[n*, support_i]; lane holds rows i = lane + 64 p.
+  float g[RPL], z[RPL], rd[RPL];
+  int tri[RPL];  // i (i + 1) / 2: start of row i in the packed factor
+#pragma unroll
+  for (int p = 0; p < RPL; ++p) {
+    const int i = lane + 64 * p;
+    tri[p] = i * (i + 1) / 2;
     g[p] = i < k ? d.G[(int64_t)nstar * d.Np + ss[i]] : 0.f;
+    rd[p] = i < k ? 1.0f / Vs[tri[p] + i] : 0.f;  // reciprocal diagonal, all rows at once
     z[p] = 0.f;
   }
 
-  // 4. Forward solve V_{k-1} z = g, column by column.
-  for (int j = 0; j < k; ++j) {
-    const int pj = j >> 6, jl = j & 63;
-    const int64_t rj = (int64_t)j * (j + 1) / 2;
-    const float zj = readlane(pick(g, pj), jl) / Vs[rj + j];
-    if (lane == jl) put(z, pj, zj);
+  // 4. Forward solve V_{k-1} z = g, column by column; column j+1 is read
+  //    while column j is applied.
+  {
+    float vn[RPL];
 #pragma unroll
     for (int p = 0; p < RPL; ++p) {
       const int i = lane + 64 * p;
-      if (i > j && i < k) g[p] = fmaf(-Vs[(int64_t)i * (i + 1) / 2 + j], zj, g[p]);
+      vn[p] = (i > 0 && i < k) ? Vs[tri[p]] : 0.f;
+    }
+    for (int j = 0; j < k; ++j) {
+      float vc[RPL];
+#pragma unroll
+      for (int p = 0; p < RPL; ++p) {
+        vc[p] = vn[p];
+        const int i = lane + 64 * p;
+        vn[p] = (i > j + 1 && i < k) ? Vs[tri[p] + j + 1] : 0.f;
+      }
+      const int pj = j >> 6, jl = j & 63;
+      const float zj = readlane(pick(g, pj), jl) * readlane(pick(rd, pj), jl);
+      if (lane == jl) put(z, pj, zj);
+#pragma unroll
+      for (int p = 0; p < RPL; ++p) {
+        const int i = lane + 64 * p;
+        if (i > j && i < k) g[p] = fmaf(-vc[p], zj, g[p]);
+      }
     }
   }
 
@@ -310,36 +502,17 @@ __global__ __launch_bounds__(64) void k_update(DictView d, WorkView w) {
 #pragma unroll
   for (int p = 0; p < RPL; ++p) zz += (double)z[p] * (double)z[p];
   zz = wave_sum(zz);
-  const double nu2 = d.nu2[nstar];
   const double d2 = nu2 - zz;
   if (!(d2 > DEP_TOL2 * nu2)) {  // dependent atom: stop without appending
-    if (lane == 0) w.flags[b] = fl1 | FLAG_DONE | OMP_SIG_DEPENDENT;
+    if (lane == 0) w.flags[b] = fl | FLAG_DONE | OMP_SIG_DEPENDENT;
     return;
   }
   const float dk = (float)sqrt(d2);
 
-  // 6. beta = a_n*^T y; u_k = (beta - z^T u_{k-1}) / d.
-  const int64_t nc4 = d.Mp / 4;
-  const float4 *A4 = reinterpret_cast<const float4 *>(d.A32);
-  const float4 *Y4 = reinterpret_cast<const float4 *>(w.Yp) + b * nc4;
-  const float4 *an = A4 + (int64_t)nstar * nc4;
-  float bp = 0.f;
-  for (int64_t c = lane; c < nc4; c += 64) {
-    const float4 a = an[c], y = Y4[c];
-    bp = fmaf(a.x, y.x, bp);
-    bp = fmaf(a.y, y.y, bp);
-    bp = fmaf(a.z, y.z, bp);
-    bp = fmaf(a.w, y.w, bp);
-  }
-  const double beta = wave_sum((double)bp);
-  float uo[RPL];
+  // 6. u_k = (beta - z^T u_{k-1}) / d, beta = a_n*^T y (Eq. 2).
   double zu = 0.0;
 #pragma unroll
-  for (int p = 0; p < RPL; ++p) {
-    const int i = lane + 64 * p;
-    uo[p] = i < k ? w.u[b * S + i] : 0.f;
-    zu += (double)z[p] * (double)uo[p];
-  }
+  for (int p = 0; p < RPL; ++p) zu += (double)z[p] * (double)uo[p];
   zu = wave_sum(zu);
   const float uk = (float)((beta - zu) / (double)dk);
 
@@ -352,20 +525,21 @@ __global__ __launch_bounds__(64) void k_update(DictView d, WorkView w) {
       Vs[rk + i] = z[p];
       w.V[b * VS + rk + i] = z[p];
     }
+    if (i == k) rd[p] = 1.0f / dk;
   }
   if (lane == 0) {
     Vs[rk + k] = dk;
     w.V[b * VS + rk + k] = dk;
-    ss[k] = nstar;
     w.sup[b * S + k] = nstar;
     w.u[b * S + k] = uk;
     const int64_t mwords = d.Np / 32;
     w.mask[b * mwords + nstar / 32] |= 1u << (nstar & 31);
   }
-  __syncthreads();
+  wave_lds_sync();
   const int K = k + 1;
 
-  // 8. Back solve V_K^T x = u, last unknown first.
+  // 8. Back solve V_K^T x = u, last unknown first; row j-1 is read while row j
+  //    is applied.
   float t[RPL], x[RPL];
 #pragma unroll
   for (int p = 0; p < RPL; ++p) {
@@ -373,86 +547,135 @@ __global__ __launch_bounds__(64) void k_update(DictView d, WorkView w) {
     t[p] = i < k ? uo[p] : (i == k ? uk : 0.f);
     x[p] = 0.f;
   }
-  for (int j = K - 1; j >= 0; --j) {
-    const int pj = j >> 6, jl = j & 63;
-    const int64_t rj = (int64_t)j * (j + 1) / 2;
-    const float xj = readlane(pick(t, pj), jl) / Vs[rj + j];
-    if (lane == jl) put(x, pj, xj);
+  {
+    float vn[RPL];
+    const int j0 = K - 1;
 #pragma unroll
     for (int p = 0; p < RPL; ++p) {
       const int i = lane + 64 * p;
-      if (i < j) t[p] = fmaf(-Vs[rj + i], xj, t[p]);
+      vn[p] = i < j0 ? Vs[j0 * (j0 + 1) / 2 + i] : 0.f;
+    }
+    for (int j = K - 1; j >= 0; --j) {
+      float vc[RPL];
+      const int jn = j - 1;
+#pragma unroll
+      for (int p = 0; p < RPL; ++p) {
+        vc[p] = vn[p];
+        const int i = lane + 64 * p;
+        vn[p] = (jn >= 0 && i < jn) ? Vs[jn * (jn + 1) / 2 + i] : 0.f;
+      }
+      const int pj = j >> 6, jl = j & 63;
+      const float xj = readlane(pick(t, pj), jl) * readlane(pick(rd, pj), jl);
+      if (lane == jl) put(x, pj, xj);
+#pragma unroll
+      for (int p = 0; p < RPL; ++p) {
+        const int i = lane + 64 * p;
+        if (i < j) t[p] = fmaf(-vc[p], xj, t[p]);
+      }
     }
   }
 #pragma unroll
   for (int p = 0; p < RPL; ++p) {
     const int i = lane + 64 * p;
-    if (i < K) {
-      xs[i] = x[p];
-      w.xh[b * S + i] = x[p];
-    }
+    if (i < K) w.xh[b * S + i] = x[p];
   }
-  __syncthreads();
 
-  // 9. Residual r = y - sum_j x_j a_{s_j}, recomputed from y; ||r||^2 in FP64.
-  float4 *R4 = reinterpret_cast<float4 *>(w.R32) + b * nc4;
-  double nrm = 0.0;
-  for (int64_t base = 0; base < nc4; base += 256) {
-    float4 r[4];
-#pragma unroll
-    for (int cc = 0; cc < 4; ++cc) {
-      const int64_t c = base + lane + 64 * cc;
-      r[cc] = c < nc4 ? Y4[c] : make_float4(0.f, 0.f, 0.f, 0.f);
-    }
-#pragma unroll 4
-    for (int j = 0; j < K; ++j) {
-      const float xj = -xs[j];
-      const float4 *a = A4 + (int64_t)ss[j] * nc4 + base + lane;
-#pragma unroll
-      for (int cc = 0; cc < 4; ++cc) {
-        if (base + lane + 64 * cc < nc4) {
-          const float4 av = a[64 * cc];
-          r[cc].x = fmaf(xj, av.x, r[cc].x);
-          r[cc].y = fmaf(xj, av.y, r[cc].y);
-          r[cc].z = fmaf(xj, av.z, r[cc].z);
-          r[cc].w = fmaf(xj, av.w, r[cc].w);
-        }
-      }
-    }
-#pragma unroll
-    for (int cc = 0; cc < 4; ++cc) {
-      const int64_t c = base + lane + 64 * cc;
-      if (c < nc4) {
-        R4[c] = r[cc];
-        if (BF16) {
-          ushort4 h;
-          h.x = f32_to_bf16_rne(r[cc].x);
-          h.y = f32_to_bf16_rne(r[cc].y);
-          h.z = f32_to_bf16_rne(r[cc].z);
-          h.w = f32_to_bf16_rne(r[cc].w);
-          reinterpret_cast<ushort4 *>(w.R16)[b * nc4 + c] = h;
-        }
-        nrm += (double)r[cc].x * r[cc].x + (double)r[cc].y * r[cc].y + (double)r[cc].z * r[cc].z +
-               (double)r[cc].w * r[cc].w;
-      }
-    }
-  }
-  nrm = wave_sum(nrm);
-
-  // 10. Stop test.
+  // 9. New state; the residual kernel picks the signal up through FLAG_NEWX.
   if (lane == 0) {
-    const double rn = sqrt(nrm);
-    int fl = fl1;
-    if (rn <= (double)w.epsb[b]) fl |= FLAG_DONE | OMP_SIG_EPS;
-    if (K >= w.Sb[b]) fl |= FLAG_DONE | OMP_SIG_SMAX;
+    fl |= FLAG_NEWX;
+    if (K >= w.Sb[b]) fl |= FLAG_DONE;
     w.k[b] = K;
-    w.rn[b] = (float)rn;
     w.flags[b] = fl;
   }
 }
 
 // ---------------------------------------------------------------------------
-// Outputs: one 256-thread block per signal.
+// Residual: r = y - sum_j x_j a_{s_j} on one slice of M for every signal whose
+// coefficients changed in this iteration, and that slice's ||r||^2 (FP64).
+// Block of 256 lanes; an item (signal, slice) takes LP lanes, 64 / LP items per
+// wavefront. Workgroup i handles slice i mod nslice.
+// ---------------------------------------------------------------------------
+template <bool BF16>
+__global__ __launch_bounds__(256) void k_residual(DictView d, WorkView w, int LP) {
+  extern __shared__ int rsm[];
+  const int IPW = 64 / LP;
+  const int items = 4 * IPW;
+  const int S = w.S;
+  float *xs = reinterpret_cast<float *>(rsm);  // [items][S]: -x
+  int *ss = rsm + items * S;                   // [items][S]: support
+  const int slice = blockIdx.x % w.nslice;
+  const int64_t group = blockIdx.x / w.nslice;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int item = wave * IPW + lane / LP;
+  const int sl = lane % LP;
+  const int64_t b = group * items + item;
+  int kk = 0;
+  if (b < w.B && (w.flags[b] & FLAG_NEWX)) kk = w.k[b];
+  for (int j = sl; j < kk; j += LP) {
+    xs[item * S + j] = -w.xh[b * S + j];
+    ss[item * S + j] = w.sup[b * S + j];
+  }
+  __syncthreads();
+  if (kk == 0) return;  // after the only barrier
+
+  const int64_t nc4 = d.Mp / 4;
+  const int64_t sl4 = w.slice_len / 4;
+  const int64_t c0 = (int64_t)slice * sl4;
+  const float4 *A4 = reinterpret_cast<const float4 *>(d.A32) + c0;
+  const float4 *Y4 = reinterpret_cast<const float4 *>(w.Yp) + b * nc4 + c0;
+  float4 *R4 = reinterpret_cast<float4 *>(w.R32) + b * nc4 + c0;
+  const float *xi = xs + item * S;
+  const int *si = ss + item * S;
+  double nrm = 0.0, dlt = 0.0;
+  for (int64_t c = sl; c < sl4; c += LP) {
+    float4 r = Y4[c];
+    int j = 0;
+    for (; j + 4 <= kk; j += 4) {
+      const float4 a0 = A4[(int64_t)si[j] * nc4 + c];
+      const float4 a1 = A4[(int64_t)si[j + 1] * nc4 + c];
+      const float4 a2 = A4[(int64_t)si[j + 2] * nc4 + c];
+      const float4 a3 = A4[(int64_t)si[j + 3] * nc4 + c];
+      const float x0 = xi[j], x1 = xi[j + 1], x2 = xi[j + 2], x3 = xi[j + 3];
+      r.x = fmaf(x0, a0.x, r.x); r.y = fmaf(x0, a0.y, r.y); r.z = fmaf(x0, a0.z, r.z); r.w = fmaf(x0, a0.w, r.w);
+      r.x = fmaf(x1, a1.x, r.x); r.y = fmaf(x1, a1.y, r.y); r.z = fmaf(x1, a1.z, r.z); r.w = fmaf(x1, a1.w, r.w);
+      r.x = fmaf(x2, a2.x, r.x); r.y = fmaf(x2, a2.y, r.y); r.z = fmaf(x2, a2.z, r.z); r.w = fmaf(x2, a2.w, r.w);
+      r.x = fmaf(x3, a3.x, r.x); r.y = fmaf(x3, a3.y, r.y); r.z = fmaf(x3, a3.z, r.z); r.w = fmaf(x3, a3.w, r.w);
+    }
+    for (; j < kk; ++j) {
+      const float4 a = A4[(int64_t)si[j] * nc4 + c];
+      const float x0 = xi[j];
+      r.x = fmaf(x0, a.x, r.x); r.y = fmaf(x0, a.y, r.y); r.z = fmaf(x0, a.z, r.z); r.w = fmaf(x0, a.w, r.w);
+    }
+    R4[c] = r;
+    if (BF16) {
+      ushort4 h;
+      h.x = f32_to_bf16_rne(r.x);
+      h.y = f32_to_bf16_rne(r.y);
+      h.z = f32_to_bf16_rne(r.z);
+      h.w = f32_to_bf16_rne(r.w);
+      reinterpret_cast<ushort4 *>(w.R16)[b * nc4 + c0 + c] = h;
+      const double e0 = (double)r.x - (double)__uint_as_float((uint32_t)h.x << 16);
+      const double e1 = (double)r.y - (double)__uint_as_float((uint32_t)h.y << 16);
+      const double e2 = (double)r.z - (double)__uint_as_float((uint32_t)h.z << 16);
+      const double e3 = (double)r.w - (double)__uint_as_float((uint32_t)h.w << 16);
+      dlt += e0 * e0 + e1 * e1 + e2 * e2 + e3 * e3;
+    }
+    nrm += (double)r.x * r.x + (double)r.y * r.y + (double)r.z * r.z + (double)r.w * r.w;
+  }
+  for (int o = LP / 2; o >= 1; o >>= 1) {
+    nrm += __shfl_xor(nrm, o);
+    if (BF16) dlt += __shfl_xor(dlt, o);
+  }
+  if (sl == 0) {
+    w.pnorm[b * NSLICE_MAX + slice] = nrm;
+    if (BF16) w.pdelta[b * NSLICE_MAX + slice] = dlt;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Outputs: one 256-thread block per signal. The stop reason follows the
+// oracle's order: a NONFINITE, DEPENDENT or EXHAUSTED stop is reported alone;
+// otherwise EPS when ||r|| <= eps and SMAX when k reached S.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_finalize(WorkView w, int64_t N, float *__restrict__ X_out,
                                                   int32_t *__restrict__ support_out,
@@ -485,16 +708,42 @@ __global__ __launch_bounds__(256) void k_finalize(WorkView w, int64_t N, float *
     }
   }
   if (threadIdx.x == 0) {
-    if (status_out) status_out[b] = (k << 8) | (w.flags[b] & 0xff);
-    if (rnorm_out) rnorm_out[b] = w.rn[b];
+    const int fl = w.flags[b];
+    const double rn = residual_norm(w, b);
+    int st = fl & (OMP_SIG_NONFINITE | OMP_SIG_DEPENDENT | OMP_SIG_EXHAUSTED);
+    if (st == 0) {
+      if (rn <= (double)w.epsb[b]) st |= OMP_SIG_EPS;
+      if (k >= w.Sb[b]) st |= OMP_SIG_SMAX;
+    }
+    st |= fl & OMP_SIG_WIDENED;
+    if (status_out) status_out[b] = (k << 8) | st;
+    if (rnorm_out) rnorm_out[b] = (float)rn;
   }
+}
+
+template <class K>
+hipError_t allow_lds(K kernel, size_t bytes) {
+  if (bytes <= 64 * 1024) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)bytes);
+}
+
+template <int RPL, bool BF16>
+hipError_t launch_solve_t(const DictView &d, const WorkView &w, hipStream_t st) {
+  const size_t lds = ((size_t)w.vstride + (size_t)w.S) * 4 * SOLVE_WAVES;
+  hipError_t e = allow_lds(k_solve<RPL, BF16>, lds);
+  if (e != hipSuccess) return e;
+  const unsigned blocks = (unsigned)((w.B + SOLVE_WAVES - 1) / SOLVE_WAVES);
+  hipLaunchKernelGGL((k_solve<RPL, BF16>), dim3(blocks), dim3(64 * SOLVE_WAVES), lds, st, d, w);
+  return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_dict_prep(const float *A, int64_t lda, const DictView &d, hipStream_t st) {
   hipLaunchKernelGGL(k_dict_prep, dim3((unsigned)d.Np), dim3(64), 0, st, A, lda, d.M, d.N, d.Mp, d.nu2,
-                     d.inv_nu, d.A32, d.A16);
+                     d.inv_nu, d.A32, d.A16, d.aerr);
+  hipLaunchKernelGGL(k_dict_aerr_max, dim3(1), dim3(1024), 0, st, d.aerr, d.Np, d.aerr_max);
   return hipGetLastError();
 }
 
@@ -505,28 +754,31 @@ hipError_t launch_init(const float *Y, int64_t ldy, const int32_t *S_per, const 
   return hipGetLastError();
 }
 
-hipError_t launch_update(const DictView &d, const WorkView &w, int precision, hipStream_t st) {
-  const size_t lds = ((size_t)w.S * (w.S + 1) / 2 + 2 * (size_t)w.S) * 4;
-  const dim3 grid((unsigned)w.B), block(64);
+hipError_t launch_solve(const DictView &d, const WorkView &w, int precision, hipStream_t st) {
   if (w.B == 0) return hipSuccess;
   const bool bf = precision == OMP_PREC_BF16;
-  if (w.S <= 64) {
-    if (bf) hipLaunchKernelGGL((k_update<1, true>), grid, block, lds, st, d, w);
-    else hipLaunchKernelGGL((k_update<1, false>), grid, block, lds, st, d, w);
-  } else if (w.S <= 128) {
-    if (bf) hipLaunchKernelGGL((k_update<2, true>), grid, block, lds, st, d, w);
-    else hipLaunchKernelGGL((k_update<2, false>), grid, block, lds, st, d, w);
+  if (w.S <= 64) return bf ? launch_solve_t<1, true>(d, w, st) : launch_solve_t<1, false>(d, w, st);
+  if (w.S <= 128) return bf ? launch_solve_t<2, true>(d, w, st) : launch_solve_t<2, false>(d, w, st);
+  return bf ? launch_solve_t<4, true>(d, w, st) : launch_solve_t<4, false>(d, w, st);
+}
+
+hipError_t launch_residual(const DictView &d, const WorkView &w, int precision, hipStream_t st) {
+  if (w.B == 0) return hipSuccess;
+  const int sl4 = w.slice_len / 4;
+  int LP = 1;
+  while (LP < sl4 && LP < 64) LP *= 2;
+  const int items = 4 * (64 / LP);
+  const int64_t groups = (w.B + items - 1) / items;
+  const size_t lds = (size_t)items * w.S * 8;
+  const dim3 grid((unsigned)(groups * w.nslice)), block(256);
+  if (precision == OMP_PREC_BF16) {
+    hipError_t e = allow_lds(k_residual<true>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_residual<true>, grid, block, lds, st, d, w, LP);
   } else {
-    static bool attr[2] = {false, false};
-    const void *fn = bf ? reinterpret_cast<const void *>(k_update<4, true>)
-                        : reinterpret_cast<const void *>(k_update<4, false>);
-    if (!attr[bf]) {
-      hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-      if (e != hipSuccess) return e;
-      attr[bf] = true;
-    }
-    if (bf) hipLaunchKernelGGL((k_update<4, true>), grid, block, lds, st, d, w);
-    else hipLaunchKernelGGL((k_update<4, false>), grid, block, lds, st, d, w);
+    hipError_t e = allow_lds(k_residual<false>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_residual<false>, grid, block, lds, st, d, w, LP);
   }
   return hipGetLastError();
 }

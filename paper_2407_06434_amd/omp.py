@@ -21,8 +21,8 @@ LIB_PATH = os.path.join(_PKG, "libbatched_omp.so")
 OMP_OK, OMP_EINVAL, OMP_EWORKSPACE, OMP_EDEVICE, OMP_ENOTSUPP = 0, -1, -2, -3, -4
 OMP_MAX_S = 256
 PREC = {"fp32": 0, "bf16": 1}
-NPHASE = 5
-PHASES = ("dict", "init", "corr", "update", "output")
+NPHASE = 6
+PHASES = ("dict", "init", "corr", "update", "output", "residual")
 SIG_EPS, SIG_SMAX, SIG_DEPENDENT, SIG_NONFINITE, SIG_EXHAUSTED, SIG_WIDENED = 1, 2, 4, 8, 32, 64
 
 EXPORTED = ("omp_dict_size", "omp_dict_init", "omp_opts_default", "omp_workspace_size", "omp_solve",
@@ -46,7 +46,7 @@ class OmpDictStruct(ctypes.Structure):
 
 
 class OmpOptsStruct(ctypes.Structure):
-    _fields_ = [("precision", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+    _fields_ = [("precision", ctypes.c_int32), ("tile_config", ctypes.c_int32),
                 ("S_per_signal", ctypes.c_void_p), ("eps_per_signal", ctypes.c_void_p),
                 ("status_out", ctypes.c_void_p), ("rnorm_out", ctypes.c_void_p),
                 ("coef_out", ctypes.c_void_p), ("dict", ctypes.POINTER(OmpDictStruct)),
@@ -132,11 +132,13 @@ class Dictionary:
 Result = namedtuple("Result", "X support coef status rnorm")
 
 
-def workspace_bytes(M: int, N: int, B: int, S: int, precision: str = "fp32", with_dict: bool = False) -> int:
+def workspace_bytes(M: int, N: int, B: int, S: int, precision: str = "fp32", with_dict: bool = False,
+                    tile_config: int = 0) -> int:
     lib = load()
     o = OmpOptsStruct()
     lib.omp_opts_default(ctypes.byref(o))
     o.precision = PREC[precision]
+    o.tile_config = int(tile_config)
     d = OmpDictStruct()
     if with_dict:
         o.dict = ctypes.pointer(d)
@@ -147,7 +149,7 @@ def solve(A: torch.Tensor, Y: torch.Tensor, S: int, eps: float = 0.0, *, precisi
           dictionary: Optional[Dictionary] = None, S_per_signal: Optional[torch.Tensor] = None,
           eps_per_signal: Optional[torch.Tensor] = None, dense: bool = True,
           workspace: Optional[torch.Tensor] = None, out: Optional[Result] = None, stream=None,
-          timing: Optional[dict] = None) -> Result:
+          timing: Optional[dict] = None, tile_config: int = 0) -> Result:
     """Batched OMP (Algorithm 1) on the GPU.
 
     A: (N, M) float32 atom-major dictionary; Y: (B, M) float32 signals.
@@ -167,6 +169,7 @@ def solve(A: torch.Tensor, Y: torch.Tensor, S: int, eps: float = 0.0, *, precisi
     o = OmpOptsStruct()
     lib.omp_opts_default(ctypes.byref(o))
     o.precision = PREC[precision]
+    o.tile_config = int(tile_config)
     if dictionary is not None:
         if dictionary.A is not A or dictionary.precision != precision:
             raise ValueError("dictionary was prepared for another A or precision")
