@@ -199,10 +199,15 @@ __global__ __launch_bounds__(GramTile::NTHR) void k_gram(const float *__restrict
 // index (bits(s) is monotone for s >= 0); key 0 means "no candidate".
 //
 // TOP2 = false (FP32 form): one key per (signal, tile), the tile's winner.
-// TOP2 = true  (BF16 form): each lane keeps the best and second-best key of
-//   the atoms it holds for its signal (a "subgroup" of 16 * FN atoms) and
-//   writes both; the second key bounds every unlisted atom of the subgroup,
-//   which is what the FP32 re-score needs to certify its pick.
+// TOP2 = true  (BF16 form): each lane keeps, for each "subgroup" of the atoms
+//   it holds for its signal (16 atoms per fragment, SUBF fragments), the three
+//   best scores and writes them as three keys. Inside the loop a candidate is
+//   a 32-bit key (bits(s) with its low 5 bits replaced by 31 - local index),
+//   so keeping the best three is a min/max sorting network; the dropped bits
+//   change s by less than 2^-18 relative, which the certificate accounts for.
+//   All atoms of the subgroup compete; only when the keys are written are
+//   selected, zero-norm and padding atoms marked invalid (low word 0), so the
+//   third key still bounds every atom of the subgroup that is not listed.
 // ---------------------------------------------------------------------------
 template <class Op, class T, bool TOP2>
 __global__ __launch_bounds__(T::NTHR) void k_corr_select(
@@ -230,18 +235,71 @@ __global__ __launch_bounds__(T::NTHR) void k_corr_select(
   const int wn = wave % T::WN, wb = wave / T::WN;
   const int h = lane >> 5;
   const int64_t mwords = Np / 32;
-  constexpr int SUBF = T::FN >= 2 ? 2 : 1;  // fragments per subgroup (TOP2)
-  constexpr int SPH = T::FN / SUBF;         // subgroups per lane
-  constexpr int KPT = T::WN * SPH * 4;      // keys per (signal, tile) (TOP2)
+  const int64_t nw0 = (int64_t)tn * T::TN + wn * T::FN * 32;  // first atom of this wavefront's rows
+
+  if (TOP2) {
+    constexpr int SUBF = T::FN >= 2 ? 2 : 1;  // fragments per subgroup
+    constexpr int SPH = T::FN / SUBF;         // subgroups per lane
+    constexpr int KPT = T::WN * SPH * 2 * NKEEP;
+    // 1/||a|| of the lane's rows (the same for every signal column).
+    float iv[T::FN][16];
+#pragma unroll
+    for (int i = 0; i < T::FN; ++i)
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const float4 v = *reinterpret_cast<const float4 *>(inv_nu + nw0 + i * 32 + 8 * g + 4 * h);
+        iv[i][4 * g + 0] = v.x;
+        iv[i][4 * g + 1] = v.y;
+        iv[i][4 * g + 2] = v.z;
+        iv[i][4 * g + 3] = v.w;
+      }
+#pragma unroll
+    for (int j = 0; j < T::FB; ++j) {
+      const int64_t b = b0 + wb * T::FB * 32 + j * 32 + (lane & 31);
+      uint64_t *dst = part + b * ((int64_t)ntile * KPT) + (int64_t)tn * KPT;
+#pragma unroll
+      for (int ig = 0; ig < SPH; ++ig) {
+        uint32_t k1 = 0, k2 = 0, k3 = 0;
+#pragma unroll
+        for (int ii = 0; ii < SUBF; ++ii) {
+          const int i = ig * SUBF + ii;
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const float sc = fabsf(acc[i][j][r]) * iv[i][r];
+            const uint32_t key = (__float_as_uint(sc) & ~31u) | (uint32_t)(31 - (ii * 16 + r));
+            const uint32_t lo1 = min(k1, key);
+            k1 = max(k1, key);
+            const uint32_t lo2 = min(k2, lo1);
+            k2 = max(k2, lo1);
+            k3 = max(k3, lo2);
+          }
+        }
+        const uint32_t ks[3] = {k1, k2, k3};
+#pragma unroll
+        for (int q = 0; q < NKEEP; ++q) {
+          const int loc = 31 - (int)(ks[q] & 31u);   // ii * 16 + r
+          const int ii = loc >> 4, r = loc & 15;
+          const int row = 8 * (r >> 2) + 4 * h + (r & 3);
+          const int64_t n = nw0 + (ig * SUBF + ii) * 32 + row;
+          const bool valid = inv_nu[n] > 0.f && !((mask[b * mwords + (n >> 5)] >> (n & 31)) & 1u);
+          const uint64_t score = (uint64_t)(ks[q] & ~31u) << 32;
+          dst[((wn * SPH + ig) * 2 + h) * NKEEP + q] =
+              score | (valid ? (uint64_t)(0xFFFFFFFFu - (uint32_t)n) : 0ull);
+        }
+      }
+    }
+    return;
+  }
+
   uint64_t *red = reinterpret_cast<uint64_t *>(lds);  // [WN][TB], LDS is free after the main loop
 #pragma unroll
   for (int j = 0; j < T::FB; ++j) {
     const int jt = wb * T::FB * 32 + j * 32 + (lane & 31);  // signal within the tile
     const int64_t b = b0 + jt;
-    uint64_t best = 0, second = 0;
+    uint64_t best = 0;
 #pragma unroll
     for (int i = 0; i < T::FN; ++i) {
-      const int64_t nf = (int64_t)tn * T::TN + wn * T::FN * 32 + i * 32;  // first atom of the fragment
+      const int64_t nf = nw0 + i * 32;  // first atom of the fragment
       const uint32_t word = mask[b * mwords + nf / 32];
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
@@ -255,33 +313,14 @@ __global__ __launch_bounds__(T::NTHR) void k_corr_select(
           const uint64_t key = cand ? ((uint64_t)__float_as_uint(s) << 32) |
                                           (uint64_t)(0xFFFFFFFFu - (uint32_t)(nf + row))
                                     : 0ull;
-          if (TOP2) {
-            if (key > best) {
-              second = best;
-              best = key;
-            } else if (key > second) {
-              second = key;
-            }
-          } else {
-            best = key > best ? key : best;
-          }
+          best = key > best ? key : best;
         }
       }
-      if (TOP2 && (i % SUBF) == SUBF - 1) {
-        const int ig = i / SUBF;
-        uint64_t *dst = part + b * ((int64_t)ntile * KPT) + (int64_t)tn * KPT + ((wn * SPH + ig) * 2 + h) * 2;
-        dst[0] = best;
-        dst[1] = second;
-        best = second = 0;
-      }
     }
-    if (!TOP2) {
-      const uint64_t other = __shfl_xor(best, 32);
-      best = other > best ? other : best;
-      if (lane < 32) red[wn * T::TB + jt] = best;
-    }
+    const uint64_t other = __shfl_xor(best, 32);
+    best = other > best ? other : best;
+    if (lane < 32) red[wn * T::TB + jt] = best;
   }
-  if (TOP2) return;
   __syncthreads();
   for (int t = threadIdx.x; t < T::TB; t += T::NTHR) {
     uint64_t best = 0;
@@ -330,7 +369,7 @@ CorrGeom geom(int precision, int cfg) {
   g.cfg = cfg;
   g.tile_atoms = T::TN;
   g.tile_signals = T::TB;
-  g.keys_per_tile = precision == 1 ? T::WN * (T::FN / SUBF) * 4 : 1;
+  g.keys_per_tile = precision == 1 ? T::WN * (T::FN / SUBF) * 2 * NKEEP : 1;
   g.wave_atoms = T::FN * 32;
   g.sub_frags = SUBF;
   g.subs_per_half = T::FN / SUBF;

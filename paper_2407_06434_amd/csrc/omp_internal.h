@@ -104,13 +104,16 @@ hipError_t launch_finalize(const DictView &d, const WorkView &w, float *X_out,
                            int32_t *support_out, float *coef_out, int32_t *status_out,
                            float *rnorm_out, hipStream_t st);
 
+// Keys kept per subgroup by the BF16 epilogue (best, second, third).
+constexpr int NKEEP = 3;
+
 // Tile configuration and output structure of the correlation product.
 //   FP32: one key per (signal, tile): the tile's best atom.
-//   BF16: two keys (best, second best BF16 score) per (signal, subgroup). The
+//   BF16: NKEEP keys (best BF16 scores, descending) per (signal, subgroup). The
 //         lane holding signal j in wavefront row wn, half h (lane / 32) owns,
 //         for fragment i, the atoms 32 i + 8 g + 4 h + e (g, e < 4) of its rows;
 //         subgroup ig of that lane is fragments ig*sub_frags .. +sub_frags-1.
-//         Key slot in the tile: ((wn * subs_per_half + ig) * 2 + h) * 2 + {0, 1};
+//         Key slot in the tile: ((wn * subs_per_half + ig) * 2 + h) * NKEEP + {0..NKEEP-1};
 //         atom: t*tile_atoms + wn*wave_atoms + 32 (ig*sub_frags + i') + 8 g + 4 h + e.
 struct CorrGeom {
   int cfg;  // tile configuration 1..4 (see the correlation kernels)

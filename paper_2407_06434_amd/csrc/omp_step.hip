@@ -112,9 +112,9 @@ __device__ inline double dot4d(const float4 &a, const float4 &v) {
 
 // FP64 dot products of up to NA atoms (n[i] < 0: unused) with the vector v
 // and, when TWO, also with y: exact products, FP64 accumulation. The whole
-// wavefront cooperates; each lane keeps four 16-byte chunks of every operand
-// in flight per pass, and the reductions run interleaved.
-template <int NA, bool TWO>
+// wavefront cooperates; each lane keeps CP 16-byte chunks of every operand in
+// flight per pass, and the reductions run interleaved.
+template <int NA, bool TWO, int CP>
 __device__ __attribute__((always_inline)) inline void atom_dots(const DictView &d, const int (&n)[NA], const float4 *__restrict__ v4,
                                  const float4 *__restrict__ y4, int lane, double (&av)[NA], double (&ay)[NA]) {
   const int64_t nc4 = d.Mp / 4;
@@ -122,10 +122,10 @@ __device__ __attribute__((always_inline)) inline void atom_dots(const DictView &
   const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
   for (int i = 0; i < NA; ++i) av[i] = ay[i] = 0.0;
-  for (int64_t c0 = 0; c0 < nc4; c0 += 256) {
-    float4 vv[4], yy[4], aa[NA][4];
+  for (int64_t c0 = 0; c0 < nc4; c0 += 64 * CP) {
+    float4 vv[CP], yy[CP], aa[NA][CP];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < CP; ++q) {
       const int64_t c = c0 + lane + 64 * q;
       const bool ok = c < nc4;
       vv[q] = ok ? v4[c] : zero;
@@ -136,7 +136,7 @@ __device__ __attribute__((always_inline)) inline void atom_dots(const DictView &
 #pragma unroll
     for (int i = 0; i < NA; ++i)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < CP; ++q) {
         av[i] += dot4d(aa[i][q], vv[q]);
         if (TWO) ay[i] += dot4d(aa[i][q], yy[q]);
       }
@@ -163,7 +163,7 @@ struct RescoreQueue {
     if (n0 < 0) return;
     const int n[2] = {n0, n1};
     double ar[2], ay[2];
-    atom_dots<2, true>(d, n, r4, y4, lane, ar, ay);
+    atom_dots<2, true, 2>(d, n, r4, y4, lane, ar, ay);
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       if (n[i] < 0) continue;
@@ -187,31 +187,34 @@ struct RescoreQueue {
   }
 };
 
-// BF16 form of the pick. The epilogue left, per subgroup of atoms, the keys of
-// its best and second-best BF16 score. With tau the bound above and s_max the
-// largest BF16 score:
-//   1. every listed atom with s_bf16 >= s_max - 2 tau is re-scored exactly; the
-//      best re-scored atom w is the provisional pick. (The atom holding s_max has
-//      s >= s_max - tau, so a listed atom below the window, s <= s_bf16 + tau <
-//      s_max - tau, cannot beat w.)
-//   2. an unlisted atom of a subgroup has s <= theta + tau, theta the
-//      subgroup's second BF16 score; when theta + tau >= s_w the whole
+// BF16 form of the pick. The epilogue left, per subgroup of atoms, keys for
+// its NKEEP best BF16 scores, each score rounded down by less than 2^-18
+// relative (et below); keys of selected, zero or padding atoms carry their
+// score but no index. With tau the bound above and s_max the largest score of
+// a valid listed key:
+//   1. every valid listed atom with s >= s_max - 2 tau - et s_max is re-scored
+//      exactly; the best re-scored atom w is the provisional pick. (The atom
+//      holding s_max has exact score >= s_max - tau, and a listed atom below
+//      the window has exact score <= s (1 + et) + tau < s_max - tau.)
+//   2. an unlisted atom of a subgroup has exact score <= theta (1 + et) + tau,
+//      theta the subgroup's last kept score; when that reaches s_w the whole
 //      subgroup is re-scored (and the signal is flagged OMP_SIG_WIDENED).
 // The result is the exact argmax of s over the selectable atoms, ties to the
 // lowest index; *beta receives a_n*^T y of the pick (computed in the same pass
-// as its score) and *nu2 its ||a_n*||^2.
+// as its score).
 __device__ int select_bf16(const DictView &d, const WorkView &w, int64_t b, float smax, double tau, int lane,
                            int *widened, double *beta) {
   const int nkeys = w.ntile * w.ncand;
   const uint64_t *keys = w.part + b * nkeys;
   const float4 *r4 = reinterpret_cast<const float4 *>(w.R32) + b * (d.Mp / 4);
   const float4 *y4 = reinterpret_cast<const float4 *>(w.Yp) + b * (d.Mp / 4);
-  const double thr = (double)smax - 2.0 * tau;
+  const double et = 1.0 / 262144.0;  // 2^-18: the epilogue's rounding of listed scores
+  const double thr = (double)smax - 2.0 * tau - et * (double)smax;
   RescoreQueue q;
   for (int t0 = 0; t0 < nkeys; t0 += 64) {
     const int t = t0 + lane;
     const uint64_t k = t < nkeys ? keys[t] : 0ull;
-    const bool cand = k && (double)__uint_as_float((uint32_t)(k >> 32)) >= thr;
+    const bool cand = (k & 0xFFFFFFFFull) && (double)__uint_as_float((uint32_t)(k >> 32)) >= thr;
     uint64_t m = __ballot(cand);
     const int n_l = (int)(0xFFFFFFFFu - (uint32_t)(k & 0xFFFFFFFFull));
     while (m) {
@@ -225,15 +228,16 @@ __device__ int select_bf16(const DictView &d, const WorkView &w, int64_t b, floa
   const uint32_t *mk = w.mask + b * mwords;
   for (int t0 = 0; t0 < nkeys; t0 += 64) {
     const int t = t0 + lane;
-    const uint64_t k = (t < nkeys && (t & 1)) ? keys[t] : 0ull;
-    const bool open = k && (double)__uint_as_float((uint32_t)(k >> 32)) + tau >= q.bs;
+    const bool third = t < nkeys && (t % NKEEP) == NKEEP - 1;  // the subgroup's bounding key
+    const uint64_t k = third ? keys[t] : 0ull;
+    const bool open = third && (double)__uint_as_float((uint32_t)(k >> 32)) * (1.0 + et) + tau >= q.bs;
     uint64_t m = __ballot(open);
     while (m) {
       const int l = __ffsll((unsigned long long)m) - 1;
       m &= m - 1;
       const int slot = t0 + l;
       const int tile = slot / w.ncand;
-      const int sgl = (slot % w.ncand) >> 1;  // ((wn * subs_per_half + ig) * 2 + h)
+      const int sgl = (slot % w.ncand) / NKEEP;  // ((wn * subs_per_half + ig) * 2 + h)
       const int hh = sgl & 1;
       const int ig = (sgl >> 1) % w.subs_per_half;
       const int wn = (sgl >> 1) / w.subs_per_half;
@@ -250,6 +254,20 @@ __device__ int select_bf16(const DictView &d, const WorkView &w, int64_t b, floa
   }
   *beta = q.by;
   return q.bn == 0x7fffffff ? -1 : q.bn;
+}
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+// Asynchronous global-to-LDS loads (gfx950 global_load_lds): lane l's element
+// lands at dst + l (lane order), dst being wave-uniform. Completion is awaited
+// with s_waitcnt before the LDS data is read.
+__device__ inline void lds_load16(const float4 *src, float4 *dst_wave) {
+  __builtin_amdgcn_global_load_lds(reinterpret_cast<const void *>(src), (lds_void_t *)(dst_wave), 16, 0,
+                                   0);
+}
+__device__ inline void lds_load4(const int32_t *src, int *dst_wave) {
+  __builtin_amdgcn_global_load_lds(reinterpret_cast<const void *>(src), (lds_void_t *)(dst_wave), 4, 0,
+                                   0);
 }
 
 // Intra-wavefront LDS ordering: one wavefront's LDS instructions execute in
@@ -382,7 +400,7 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
   if (b >= w.B) return;
   const int S = w.S;
   const int64_t VS = w.vstride;
-  float *Vs = smem + (size_t)wv * (VS + S);
+  float *Vs = smem + (size_t)wv * (VS + ((S + 3) & ~3));
   int *ss = reinterpret_cast<int *>(Vs + VS);
 
   // ---- round 1: state, residual norms, keys
@@ -392,11 +410,11 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
   const double pd = (BF16 && lane < NSLICE_MAX) ? w.pdelta[b * NSLICE_MAX + lane] : 0.0;
   const int nkeys = w.ntile * w.ncand;
   const uint64_t *keys = w.part + b * nkeys;
-  uint64_t kmax = 0;
+  uint64_t kmax = 0;  // largest valid key (a valid key has a non-zero index word)
 #pragma unroll 4
   for (int t = lane; t < nkeys; t += 64) {
     const uint64_t v = keys[t];
-    kmax = v > kmax ? v : kmax;
+    kmax = ((v & 0xFFFFFFFFull) && v > kmax) ? v : kmax;
   }
   if (fl & FLAG_NEWX) {
     fl &= ~FLAG_NEWX;
@@ -416,14 +434,16 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
     return;
   }
 
-  // ---- round 2: support and packed factor into LDS, u into registers ...
-  for (int t = lane; t < k; t += 64) ss[t] = w.sup[b * S + t];
+  // ---- round 2: support and packed factor straight into LDS (asynchronous
+  // global-to-LDS loads, no registers, no wait until they are read) ...
+  for (int t0 = 0; t0 < k; t0 += 64)
+    if (t0 + lane < k) lds_load4(w.sup + b * S + t0 + lane, ss + t0);
   {
-    const int64_t nv4 = ((int64_t)k * (k + 1) / 2 + 3) / 4;
+    const int nv4 = (k * (k + 1) / 2 + 3) / 4;
     const float4 *V4 = reinterpret_cast<const float4 *>(w.V + b * VS);
     float4 *Vs4 = reinterpret_cast<float4 *>(Vs);
-#pragma unroll 4
-    for (int64_t t = lane; t < nv4; t += 64) Vs4[t] = V4[t];
+    for (int t0 = 0; t0 < nv4; t0 += 64)
+      if (t0 + lane < nv4) lds_load16(V4 + t0 + lane, Vs4 + t0);
   }
   float uo[RPL];
 #pragma unroll
@@ -449,13 +469,14 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
     nstar = (int)(0xFFFFFFFFu - (uint32_t)(kmax & 0xFFFFFFFFull));
     const int na[1] = {nstar};
     double ay[1], unused[1];
-    atom_dots<1, false>(d, na, reinterpret_cast<const float4 *>(w.Yp) + b * (d.Mp / 4), nullptr, lane, ay,
+    atom_dots<1, false, 4>(d, na, reinterpret_cast<const float4 *>(w.Yp) + b * (d.Mp / 4), nullptr, lane, ay,
                         unused);
     beta = ay[0];
   }
   if (widened) fl |= OMP_SIG_WIDENED;
   const double nu2 = d.nu2[nstar];
-  wave_lds_sync();  // support and factor are in LDS
+  __builtin_amdgcn_s_waitcnt(0);  // the global-to-LDS loads have landed
+  wave_lds_sync();
 
   // ---- round 3: Gram row g_i = G[n*, support_i]; lane holds rows i = lane + 64 p.
   float g[RPL], z[RPL], rd[RPL];
@@ -469,30 +490,39 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
     z[p] = 0.f;
   }
 
-  // 4. Forward solve V_{k-1} z = g, column by column; column j+1 is read
-  //    while column j is applied.
+  // 4. Forward solve V_{k-1} z = g, column by column. Columns are read from
+  //    LDS four at a time, one block ahead of the columns being applied.
   {
-    float vn[RPL];
+    constexpr int QB = 4;
+    float vb[2][QB][RPL];
 #pragma unroll
-    for (int p = 0; p < RPL; ++p) {
-      const int i = lane + 64 * p;
-      vn[p] = (i > 0 && i < k) ? Vs[tri[p]] : 0.f;
-    }
-    for (int j = 0; j < k; ++j) {
-      float vc[RPL];
+    for (int q = 0; q < QB; ++q)
 #pragma unroll
       for (int p = 0; p < RPL; ++p) {
-        vc[p] = vn[p];
         const int i = lane + 64 * p;
-        vn[p] = (i > j + 1 && i < k) ? Vs[tri[p] + j + 1] : 0.f;
+        vb[0][q][p] = (i > q && i < k) ? Vs[tri[p] + q] : 0.f;
       }
-      const int pj = j >> 6, jl = j & 63;
-      const float zj = readlane(pick(g, pj), jl) * readlane(pick(rd, pj), jl);
-      if (lane == jl) put(z, pj, zj);
+    for (int j0 = 0; j0 < k; j0 += QB) {
+      const int cur = (j0 / QB) & 1;
 #pragma unroll
-      for (int p = 0; p < RPL; ++p) {
-        const int i = lane + 64 * p;
-        if (i > j && i < k) g[p] = fmaf(-vc[p], zj, g[p]);
+      for (int q = 0; q < QB; ++q)
+#pragma unroll
+        for (int p = 0; p < RPL; ++p) {
+          const int i = lane + 64 * p, j = j0 + QB + q;
+          vb[cur ^ 1][q][p] = (i > j && i < k) ? Vs[tri[p] + j] : 0.f;
+        }
+#pragma unroll
+      for (int q = 0; q < QB; ++q) {
+        const int j = j0 + q;
+        if (j >= k) break;
+        const int pj = j >> 6, jl = j & 63;
+        const float zj = readlane(pick(g, pj), jl) * readlane(pick(rd, pj), jl);
+        if (lane == jl) put(z, pj, zj);
+#pragma unroll
+        for (int p = 0; p < RPL; ++p) {
+          const int i = lane + 64 * p;
+          if (i > j && i < k) g[p] = fmaf(-vb[cur][q][p], zj, g[p]);
+        }
       }
     }
   }
@@ -548,29 +578,37 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
     x[p] = 0.f;
   }
   {
-    float vn[RPL];
-    const int j0 = K - 1;
+    // rows are read from LDS four at a time, one block ahead of those applied
+    constexpr int QB = 4;
+    float vb[2][QB][RPL];
 #pragma unroll
-    for (int p = 0; p < RPL; ++p) {
-      const int i = lane + 64 * p;
-      vn[p] = i < j0 ? Vs[j0 * (j0 + 1) / 2 + i] : 0.f;
-    }
-    for (int j = K - 1; j >= 0; --j) {
-      float vc[RPL];
-      const int jn = j - 1;
+    for (int q = 0; q < QB; ++q)
 #pragma unroll
       for (int p = 0; p < RPL; ++p) {
-        vc[p] = vn[p];
-        const int i = lane + 64 * p;
-        vn[p] = (jn >= 0 && i < jn) ? Vs[jn * (jn + 1) / 2 + i] : 0.f;
+        const int i = lane + 64 * p, j = K - 1 - q;
+        vb[0][q][p] = (j >= 0 && i < j) ? Vs[j * (j + 1) / 2 + i] : 0.f;
       }
-      const int pj = j >> 6, jl = j & 63;
-      const float xj = readlane(pick(t, pj), jl) * readlane(pick(rd, pj), jl);
-      if (lane == jl) put(x, pj, xj);
+    for (int j0 = K - 1; j0 >= 0; j0 -= QB) {
+      const int cur = ((K - 1 - j0) / QB) & 1;
 #pragma unroll
-      for (int p = 0; p < RPL; ++p) {
-        const int i = lane + 64 * p;
-        if (i < j) t[p] = fmaf(-vc[p], xj, t[p]);
+      for (int q = 0; q < QB; ++q)
+#pragma unroll
+        for (int p = 0; p < RPL; ++p) {
+          const int i = lane + 64 * p, j = j0 - QB - q;
+          vb[cur ^ 1][q][p] = (j >= 0 && i < j) ? Vs[j * (j + 1) / 2 + i] : 0.f;
+        }
+#pragma unroll
+      for (int q = 0; q < QB; ++q) {
+        const int j = j0 - q;
+        if (j < 0) break;
+        const int pj = j >> 6, jl = j & 63;
+        const float xj = readlane(pick(t, pj), jl) * readlane(pick(rd, pj), jl);
+        if (lane == jl) put(x, pj, xj);
+#pragma unroll
+        for (int p = 0; p < RPL; ++p) {
+          const int i = lane + 64 * p;
+          if (i < j) t[p] = fmaf(-vb[cur][q][p], xj, t[p]);
+        }
       }
     }
   }
@@ -730,7 +768,7 @@ hipError_t allow_lds(K kernel, size_t bytes) {
 
 template <int RPL, bool BF16>
 hipError_t launch_solve_t(const DictView &d, const WorkView &w, hipStream_t st) {
-  const size_t lds = ((size_t)w.vstride + (size_t)w.S) * 4 * SOLVE_WAVES;
+  const size_t lds = ((size_t)w.vstride + (size_t)((w.S + 3) & ~3)) * 4 * SOLVE_WAVES;
   hipError_t e = allow_lds(k_solve<RPL, BF16>, lds);
   if (e != hipSuccess) return e;
   const unsigned blocks = (unsigned)((w.B + SOLVE_WAVES - 1) / SOLVE_WAVES);
