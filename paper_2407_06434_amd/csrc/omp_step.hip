@@ -380,11 +380,12 @@ __global__ __launch_bounds__(64) void k_init(const float *__restrict__ Y, int64_
 // Solve step. One 64-lane wavefront per signal, SOLVE_WAVES signals per block
 // (the wavefronts share nothing; each has its own LDS region). RPL = rows of V
 // per lane (S <= 64 RPL; RPL in {1, 2, 4}).
-// LDS per wavefront: V (vstride floats), support (S ints).
-// Memory is read in three rounds: what depends on the signal only (state,
-// norms, the epilogue's keys), then what depends on the state (support,
-// factor, u) together with what depends on the keys (the re-score of the
-// candidates, or a_n*^T y), and last the Gram row of the pick.
+// LDS per wavefront: V (vstride floats).
+// Memory is read in as few dependent rounds as possible: first everything
+// whose address depends on the signal only (state, norms, the epilogue's
+// keys, support, u), then the packed factor together with what depends on
+// the pick (FP32 form: Gram row, ||a_n*||^2, a_n*^T y; BF16 form: the exact
+// re-score of the candidates, followed by the Gram row of the winner).
 // The triangular solves run column by column; the reciprocal diagonal is
 // computed up front in parallel and the next column is read from LDS while
 // the current one is applied, so the sequential chain holds no division and
@@ -400,14 +401,22 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
   if (b >= w.B) return;
   const int S = w.S;
   const int64_t VS = w.vstride;
-  float *Vs = smem + (size_t)wv * (VS + ((S + 3) & ~3));
-  int *ss = reinterpret_cast<int *>(Vs + VS);
+  float *Vs = smem + (size_t)wv * VS;
 
-  // ---- round 1: state, residual norms, keys
+  // ---- round 1: state, residual norms, keys, support, u (none of these
+  // addresses depends on another load)
   int fl = w.flags[b];
   const int k = w.k[b];
   const double pn = lane < NSLICE_MAX ? w.pnorm[b * NSLICE_MAX + lane] : 0.0;
   const double pd = (BF16 && lane < NSLICE_MAX) ? w.pdelta[b * NSLICE_MAX + lane] : 0.0;
+  int si[RPL];
+  float uo[RPL];
+#pragma unroll
+  for (int p = 0; p < RPL; ++p) {
+    const int i = lane + 64 * p;
+    si[p] = i < S ? w.sup[b * S + i] : 0;  // only entries below k are meaningful
+    uo[p] = i < S ? w.u[b * S + i] : 0.f;
+  }
   const int nkeys = w.ntile * w.ncand;
   const uint64_t *keys = w.part + b * nkeys;
   uint64_t kmax = 0;  // largest valid key (a valid key has a non-zero index word)
@@ -433,11 +442,12 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
     if (lane == 0) w.flags[b] = fl | FLAG_DONE | OMP_SIG_EXHAUSTED;
     return;
   }
+#pragma unroll
+  for (int p = 0; p < RPL; ++p)
+    if (lane + 64 * p >= k) uo[p] = 0.f;
 
-  // ---- round 2: support and packed factor straight into LDS (asynchronous
-  // global-to-LDS loads, no registers, no wait until they are read) ...
-  for (int t0 = 0; t0 < k; t0 += 64)
-    if (t0 + lane < k) lds_load4(w.sup + b * S + t0 + lane, ss + t0);
+  // ---- round 2: the packed factor straight into LDS (asynchronous
+  // global-to-LDS loads: no registers, no wait until it is read) ...
   {
     const int nv4 = (k * (k + 1) / 2 + 3) / 4;
     const float4 *V4 = reinterpret_cast<const float4 *>(w.V + b * VS);
@@ -445,19 +455,16 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
     for (int t0 = 0; t0 < nv4; t0 += 64)
       if (t0 + lane < nv4) lds_load16(V4 + t0 + lane, Vs4 + t0);
   }
-  float uo[RPL];
-#pragma unroll
-  for (int p = 0; p < RPL; ++p) {
-    const int i = lane + 64 * p;
-    uo[p] = i < k ? w.u[b * S + i] : 0.f;
-  }
 
-  // ... and, beside them, the pick: the best key over all atom tiles (largest
-  // score, then lowest index), or in the BF16 form the certified exact
-  // re-score of the candidates; beta = a_n*^T y (exact products, FP64 sum).
+  // ... and the pick: the best key over all atom tiles (largest score, then
+  // lowest index), or in the BF16 form the certified exact re-score of the
+  // candidates; beta = a_n*^T y (exact products, FP64 sum). In the FP32 form
+  // the Gram row of the pick, g_i = G[n*, support_i] (lane holds rows
+  // i = lane + 64 p), and ||a_n*||^2 are fetched in this same round.
   int nstar;
   int widened = 0;
-  double beta = 0.0;
+  double beta = 0.0, nu2 = 0.0;
+  float g[RPL];
   if (BF16) {
     const double tau = bf16_tau(rn, sqrt(wave_sum(pd)), (double)d.aerr_max[0], d.Mp);
     nstar = select_bf16(d, w, b, __uint_as_float((uint32_t)(kmax >> 32)), tau, lane, &widened, &beta);
@@ -465,27 +472,37 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
       if (lane == 0) w.flags[b] = fl | FLAG_DONE | OMP_SIG_EXHAUSTED;
       return;
     }
+    // ---- round 3: Gram row and ||a_n*||^2 of the pick
+    nu2 = d.nu2[nstar];
+#pragma unroll
+    for (int p = 0; p < RPL; ++p) {
+      const int i = lane + 64 * p;
+      g[p] = i < k ? d.G[(int64_t)nstar * d.Np + si[p]] : 0.f;
+    }
   } else {
     nstar = (int)(0xFFFFFFFFu - (uint32_t)(kmax & 0xFFFFFFFFull));
+    nu2 = d.nu2[nstar];
+#pragma unroll
+    for (int p = 0; p < RPL; ++p) {
+      const int i = lane + 64 * p;
+      g[p] = i < k ? d.G[(int64_t)nstar * d.Np + si[p]] : 0.f;
+    }
     const int na[1] = {nstar};
     double ay[1], unused[1];
     atom_dots<1, false, 4>(d, na, reinterpret_cast<const float4 *>(w.Yp) + b * (d.Mp / 4), nullptr, lane, ay,
-                        unused);
+                           unused);
     beta = ay[0];
   }
   if (widened) fl |= OMP_SIG_WIDENED;
-  const double nu2 = d.nu2[nstar];
   __builtin_amdgcn_s_waitcnt(0);  // the global-to-LDS loads have landed
   wave_lds_sync();
 
-  // ---- round 3: Gram row g_i = G[n*, support_i]; lane holds rows i = lane + 64 p.
-  float g[RPL], z[RPL], rd[RPL];
+  float z[RPL], rd[RPL];
   int tri[RPL];  // i (i + 1) / 2: start of row i in the packed factor
 #pragma unroll
   for (int p = 0; p < RPL; ++p) {
     const int i = lane + 64 * p;
     tri[p] = i * (i + 1) / 2;
-    g[p] = i < k ? d.G[(int64_t)nstar * d.Np + ss[i]] : 0.f;
     rd[p] = i < k ? 1.0f / Vs[tri[p] + i] : 0.f;  // reciprocal diagonal, all rows at once
     z[p] = 0.f;
   }
@@ -494,36 +511,40 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
   //    LDS four at a time, one block ahead of the columns being applied.
   {
     constexpr int QB = 4;
-    float vb[2][QB][RPL];
+    float va[QB][RPL], vx[QB][RPL];
 #pragma unroll
     for (int q = 0; q < QB; ++q)
 #pragma unroll
       for (int p = 0; p < RPL; ++p) {
         const int i = lane + 64 * p;
-        vb[0][q][p] = (i > q && i < k) ? Vs[tri[p] + q] : 0.f;
+        va[q][p] = (i > q && i < k) ? Vs[tri[p] + q] : 0.f;
       }
     for (int j0 = 0; j0 < k; j0 += QB) {
-      const int cur = (j0 / QB) & 1;
 #pragma unroll
       for (int q = 0; q < QB; ++q)
 #pragma unroll
         for (int p = 0; p < RPL; ++p) {
           const int i = lane + 64 * p, j = j0 + QB + q;
-          vb[cur ^ 1][q][p] = (i > j && i < k) ? Vs[tri[p] + j] : 0.f;
+          vx[q][p] = (i > j && i < k) ? Vs[tri[p] + j] : 0.f;
         }
 #pragma unroll
       for (int q = 0; q < QB; ++q) {
         const int j = j0 + q;
-        if (j >= k) break;
-        const int pj = j >> 6, jl = j & 63;
-        const float zj = readlane(pick(g, pj), jl) * readlane(pick(rd, pj), jl);
-        if (lane == jl) put(z, pj, zj);
+        if (j < k) {
+          const int pj = j >> 6, jl = j & 63;
+          const float zj = readlane(pick(g, pj), jl) * readlane(pick(rd, pj), jl);
+          if (lane == jl) put(z, pj, zj);
 #pragma unroll
-        for (int p = 0; p < RPL; ++p) {
-          const int i = lane + 64 * p;
-          if (i > j && i < k) g[p] = fmaf(-vb[cur][q][p], zj, g[p]);
+          for (int p = 0; p < RPL; ++p) {
+            const int i = lane + 64 * p;
+            if (i > j && i < k) g[p] = fmaf(-va[q][p], zj, g[p]);
+          }
         }
       }
+#pragma unroll
+      for (int q = 0; q < QB; ++q)
+#pragma unroll
+        for (int p = 0; p < RPL; ++p) va[q][p] = vx[q][p];
     }
   }
 
@@ -580,36 +601,40 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
   {
     // rows are read from LDS four at a time, one block ahead of those applied
     constexpr int QB = 4;
-    float vb[2][QB][RPL];
+    float va[QB][RPL], vx[QB][RPL];
 #pragma unroll
     for (int q = 0; q < QB; ++q)
 #pragma unroll
       for (int p = 0; p < RPL; ++p) {
         const int i = lane + 64 * p, j = K - 1 - q;
-        vb[0][q][p] = (j >= 0 && i < j) ? Vs[j * (j + 1) / 2 + i] : 0.f;
+        va[q][p] = (j >= 0 && i < j) ? Vs[j * (j + 1) / 2 + i] : 0.f;
       }
     for (int j0 = K - 1; j0 >= 0; j0 -= QB) {
-      const int cur = ((K - 1 - j0) / QB) & 1;
 #pragma unroll
       for (int q = 0; q < QB; ++q)
 #pragma unroll
         for (int p = 0; p < RPL; ++p) {
           const int i = lane + 64 * p, j = j0 - QB - q;
-          vb[cur ^ 1][q][p] = (j >= 0 && i < j) ? Vs[j * (j + 1) / 2 + i] : 0.f;
+          vx[q][p] = (j >= 0 && i < j) ? Vs[j * (j + 1) / 2 + i] : 0.f;
         }
 #pragma unroll
       for (int q = 0; q < QB; ++q) {
         const int j = j0 - q;
-        if (j < 0) break;
-        const int pj = j >> 6, jl = j & 63;
-        const float xj = readlane(pick(t, pj), jl) * readlane(pick(rd, pj), jl);
-        if (lane == jl) put(x, pj, xj);
+        if (j >= 0) {
+          const int pj = j >> 6, jl = j & 63;
+          const float xj = readlane(pick(t, pj), jl) * readlane(pick(rd, pj), jl);
+          if (lane == jl) put(x, pj, xj);
 #pragma unroll
-        for (int p = 0; p < RPL; ++p) {
-          const int i = lane + 64 * p;
-          if (i < j) t[p] = fmaf(-vb[cur][q][p], xj, t[p]);
+          for (int p = 0; p < RPL; ++p) {
+            const int i = lane + 64 * p;
+            if (i < j) t[p] = fmaf(-va[q][p], xj, t[p]);
+          }
         }
       }
+#pragma unroll
+      for (int q = 0; q < QB; ++q)
+#pragma unroll
+        for (int p = 0; p < RPL; ++p) va[q][p] = vx[q][p];
     }
   }
 #pragma unroll
@@ -768,7 +793,7 @@ hipError_t allow_lds(K kernel, size_t bytes) {
 
 template <int RPL, bool BF16>
 hipError_t launch_solve_t(const DictView &d, const WorkView &w, hipStream_t st) {
-  const size_t lds = ((size_t)w.vstride + (size_t)((w.S + 3) & ~3)) * 4 * SOLVE_WAVES;
+  const size_t lds = (size_t)w.vstride * 4 * SOLVE_WAVES;
   hipError_t e = allow_lds(k_solve<RPL, BF16>, lds);
   if (e != hipSuccess) return e;
   const unsigned blocks = (unsigned)((w.B + SOLVE_WAVES - 1) / SOLVE_WAVES);
