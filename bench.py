@@ -42,15 +42,90 @@ def corr_flops_per_launch(M, N, B):
     return 2.0 * M * N * B
 
 
-def update_bytes_per_launch(M, S, B):
-    """Algorithmic bytes of one update launch, averaged over the S iterations:
-    per signal at support size K: K gathered atoms (4 M K), y read and r written
-    (8 M), the atom n* read for beta (4 M), the packed factor read and one row
-    appended (~2 K^2 + 4 K)."""
+def solve_bytes_per_launch(M, S, B):
+    """Algorithmic bytes of one solve launch, averaged over the S iterations. Per
+    signal at support size K: the atom n* and y for beta (8 M), the packed factor
+    read (2 K (K+1)), the Gram row G[n*, support] (4 K), u and the support read
+    (8 K), one factor row and x appended or rewritten (~4 (K+1) + 4 (K+1))."""
     tot = 0.0
-    for K in range(1, S + 1):
-        tot += 4.0 * M * K + 12.0 * M + 2.0 * K * K + 4.0 * K
+    for K in range(S):
+        tot += 8.0 * M + 2.0 * K * (K + 1) + 12.0 * K + 8.0 * (K + 1)
     return B * tot / S
+
+
+def residual_bytes_per_launch(M, N, S, B, bf16):
+    """HBM-minimum bytes of one residual launch, averaged over the S iterations:
+    per signal y read and r written (8 M, plus 2 M for the BF16 copy of r), x and
+    the support read (8 K); the gathered atoms at most once per launch (4 M N).
+    The per-signal gathers (4 M K) are served by L2 and are reported apart."""
+    per = 0.0
+    for K in range(1, S + 1):
+        per += (10.0 if bf16 else 8.0) * M + 8.0 * K
+    return B * per / S + 4.0 * M * N
+
+
+def residual_gather_bytes_per_launch(M, S, B):
+    return B * sum(4.0 * M * K for K in range(1, S + 1)) / S
+
+
+def kernel_rooflines(w, precision, tim):
+    """Per-kernel algorithmic rate against its roofline, from the library's own HIP
+    events (recorded around every launch on the solve's stream)."""
+    bf16 = precision == "bf16"
+    out = {}
+
+    def entry(name, phase, bound, work, unit_scale, peak, unit, extra=None):
+        ms, n = tim[phase]
+        avg = ms / max(n, 1)
+        ach = work / (avg * 1e-3) / unit_scale
+        e = dict(bound=bound, achieved=round(ach, 2), peak=peak, unit=unit, frac=round(ach / peak, 4),
+                 avg_launch_ms=round(avg, 5), launches=n, total_ms=round(ms, 4),
+                 algorithmic_per_launch=float(f"{work:.5e}"))
+        if extra:
+            e.update(extra)
+        out[name] = e
+
+    entry("k_corr_select", "corr", "mfma", corr_flops_per_launch(w.M, w.N, w.B), 1e12,
+          PEAK["bf16_mfma"] if bf16 else PEAK["fp32_mfma"], "TFLOP/s")
+    entry("k_solve", "update", "hbm", solve_bytes_per_launch(w.M, w.S, w.B), 1e9, PEAK["hbm"], "GB/s")
+    gb = residual_gather_bytes_per_launch(w.M, w.S, w.B)
+    ms, n = tim["residual"]
+    entry("k_residual", "residual", "hbm", residual_bytes_per_launch(w.M, w.N, w.S, w.B, bf16), 1e9,
+          PEAK["hbm"], "GB/s",
+          extra=dict(l2_gather_bytes_per_launch=float(f"{gb:.5e}"),
+                     l2_gather_GBps=round(gb / (ms / max(n, 1) * 1e-3) / 1e9, 1)))
+    return out
+
+
+def source_digest():
+    """Digest of the kernel sources; a traffic figure measured on other sources is stale."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2407_06434_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".cpp", ".h")):
+            h.update(f.encode())
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, precision):
+    """HBM bytes per launch of `kernel` from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE passes, each scaled by a copy kernel of known size), or None when the
+    summary is missing or was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"omp_{precision}_1024x4096_B4096_hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    digest, val = None, None
+    for ln in open(path):
+        ln = ln.strip().strip("`")
+        if ln.startswith("source digest:"):
+            digest = ln.split(":", 1)[1].strip()
+        if ln.startswith(f"traffic {kernel}:"):
+            val = float(ln.split(":", 1)[1].split()[0])
+    if digest != source_digest():
+        return None
+    return val
 
 
 def run_gpu(w, precision, steps, warmup):
@@ -85,6 +160,64 @@ def run_gpu(w, precision, steps, warmup):
     return dict(wall=wall, timing=timing, dict_ms=dict_ms, res=res)
 
 
+def run_uneven(precision, steps, warmup, B_each=10000):
+    """Uneven batch: two dictionaries (128x512, 512x2048), 10,000 signals each, per-signal
+    S_i in 4..64 and eps_i = 1e-2 ||y_i||, solved in one slot-scheduled call after the
+    autotuner picked each problem's schedule; timed beside the keep-in-batch form
+    (omp_solve per problem with the same per-signal arrays). Results must be identical."""
+    import torch
+    from paper_2407_06434_amd import omp, workloads
+    dev = torch.device("cuda:0")
+    ws = workloads.uneven_pair(B_each)
+    probs, plain_args = [], []
+    for w in ws:
+        A = torch.from_numpy(w.A).to(dev)
+        d = omp.Dictionary(A, precision)
+        Y = torch.from_numpy(w.Y).to(dev)
+        Sp = torch.from_numpy(w.S_per_signal).to(dev)
+        Ep = torch.from_numpy(w.eps_per_signal).to(dev)
+        probs.append(omp.Problem(d, Y, w.S, 0.0, S_per_signal=Sp, eps_per_signal=Ep))
+        plain_args.append((A, Y, w.S, d, Sp, Ep))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    choice = omp.tune(probs, precision=precision, sample=4096)
+    tune_s = time.perf_counter() - t0
+    for _ in range(warmup):
+        omp.solve_multi(probs, precision=precision)
+    walls, gpu_ms, iters = [], [], 0
+    for _ in range(steps):
+        info = {}
+        t0 = time.perf_counter()
+        outs = omp.solve_multi(probs, precision=precision, info=info)
+        walls.append(time.perf_counter() - t0)
+        gpu_ms.append(info["elapsed_ms"])
+        iters = info["iterations"]
+    nsig = sum(w.B for w in ws)
+    plain = [None] * len(ws)
+    for _ in range(warmup):
+        for i, (A, Y, S, d, Sp, Ep) in enumerate(plain_args):
+            plain[i] = omp.solve(A, Y, S, 0.0, precision=precision, dictionary=d, S_per_signal=Sp,
+                                 eps_per_signal=Ep, dense=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for i, (A, Y, S, d, Sp, Ep) in enumerate(plain_args):
+            plain[i] = omp.solve(A, Y, S, 0.0, precision=precision, dictionary=d, S_per_signal=Sp,
+                                 eps_per_signal=Ep, dense=False, out=plain[i])
+    torch.cuda.synchronize()
+    plain_wall = (time.perf_counter() - t0) / steps
+    same = all(torch.equal(a.support, b.support) and torch.equal(a.coef, b.coef) and
+               torch.equal(a.status, b.status) for a, b in zip(outs, plain))
+    wall = float(np.median(walls))
+    ks = [int(((o.status >> 8).sum()).item()) for o in outs]
+    return {"workload": "uneven_128x512_512x2048_B20000", "value": round(nsig / wall, 1), "unit": "signals/s",
+            "ms_per_call": round(1e3 * wall, 3), "gpu_ms_per_call": round(float(np.median(gpu_ms)), 3),
+            "iterations": iters, "schedule": [dict(tile_config=c, slots=s, residual_lanes=l) for c, s, l in choice],
+            "tune_s": round(tune_s, 2), "sum_k": ks,
+            "keep_in_batch": {"value": round(nsig / plain_wall, 1), "ms_per_call": round(1e3 * plain_wall, 3)},
+            "speedup_vs_keep_in_batch": round(plain_wall / wall, 3), "identical_to_keep_in_batch": bool(same)}
+
+
 def cpu_baseline(w, target_s):
     """The oracle, as it stands, on the first n signals of the same workload."""
     import oracle
@@ -117,6 +250,9 @@ def main():
                     help="skip timing the plain FP32 form beside the BF16 form")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch (slot scheduler) measurement")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (scale reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
@@ -129,6 +265,16 @@ def main():
     w = workloads.bf16_1024x4096()
     log(f"workload {w.name} M={w.M} N={w.N} B={w.B} S={w.S} generated in {time.perf_counter() - t:.1f}s")
 
+    if args.copy_mib > 0:
+        import torch
+        src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {src.numel() * 4} bytes read, {dst.numel() * 4} bytes written")
+        del src, dst
+
     g = run_gpu(w, args.precision, args.steps, args.warmup)
     sps = w.B * args.steps / g["wall"]
     ms_step = 1e3 * g["wall"] / args.steps
@@ -136,23 +282,12 @@ def main():
 
     tim = g["timing"]
     phase_ms = {k: v[0] / args.steps for k, v in tim.items()}
-    corr_ms, corr_n = tim["corr"]
-    upd_ms, upd_n = tim["update"]
-    corr_avg = corr_ms / max(corr_n, 1)
-    upd_avg = upd_ms / max(upd_n, 1)
-    if corr_ms >= upd_ms:
-        flops = corr_flops_per_launch(w.M, w.N, w.B)
-        peak = PEAK["bf16_mfma"] if args.precision == "bf16" else PEAK["fp32_mfma"]
-        ach = flops / (corr_avg * 1e-3) / 1e12
-        roof = dict(kernel="k_corr_select", bound="mfma", achieved=round(ach, 2), peak=peak, unit="TFLOP/s",
-                    frac=round(ach / peak, 4), traffic=None, avg_launch_ms=round(corr_avg, 5),
-                    per_launch=f"{flops:.4e} flop")
-    else:
-        nbytes = update_bytes_per_launch(w.M, w.S, w.B)
-        ach = nbytes / (upd_avg * 1e-3) / 1e9
-        roof = dict(kernel="k_update", bound="hbm", achieved=round(ach, 1), peak=PEAK["hbm"], unit="GB/s",
-                    frac=round(ach / PEAK["hbm"], 4), traffic=None, avg_launch_ms=round(upd_avg, 5),
-                    per_launch=f"{nbytes:.4e} B")
+    kern = kernel_rooflines(w, args.precision, tim)
+    dom = max(kern, key=lambda k: kern[k]["total_ms"])
+    roof = dict(kernel=dom, **{k: v for k, v in kern[dom].items() if k != "total_ms"})
+    roof["traffic"] = measured_traffic(dom, args.precision)
+    if roof["traffic"] is not None:
+        roof["traffic_over_algorithmic"] = round(roof["traffic"] / roof["algorithmic_per_launch"], 3)
 
     line = {
         "metric": METRIC, "value": round(sps, 1), "unit": "signals/s", "n_gpus": 1, "steps": args.steps,
@@ -162,8 +297,8 @@ def main():
         "config": {"workload": "omp_1024x4096_S64_B4096", "M": w.M, "N": w.N, "S": w.S, "B": w.B,
                    "precision": args.precision, "early_stop": False},
         "roofline": roof,
+        "kernels": {k: {kk: vv for kk, vv in v.items() if kk not in ("per_launch",)} for k, v in kern.items()},
         "phase_ms_per_step": {k: round(v, 4) for k, v in phase_ms.items()},
-        "corr_avg_ms": round(corr_avg, 5), "update_avg_ms": round(upd_avg, 5),
         "dict_prep_ms": round(g["dict_ms"], 3),
     }
 
@@ -172,13 +307,19 @@ def main():
         f = run_gpu(w, "fp32", fs, 1)
         fsps = w.B * fs / f["wall"]
         same = [set(a.tolist()) == set(b.tolist()) for a, b in zip(g["res"]["support"], f["res"]["support"])]
+        fk = kernel_rooflines(w, "fp32", f["timing"])
         line["plain_fp32"] = {"value": round(fsps, 1), "unit": "signals/s", "steps": fs,
-                              "corr_avg_ms": round(f["timing"]["corr"][0] / max(f["timing"]["corr"][1], 1), 5),
-                              "update_avg_ms": round(f["timing"]["update"][0] / max(f["timing"]["update"][1], 1), 5)}
+                              "avg_launch_ms": {k: v["avg_launch_ms"] for k, v in fk.items()},
+                              "corr_frac_of_fp32_mfma": fk["k_corr_select"]["frac"]}
         line["speedup_vs_plain_fp32"] = round(sps / fsps, 3)
         line["same_supports_vs_fp32"] = f"{sum(same)}/{w.B}"
         log(f"fp32: {fsps:.0f} signals/s; same supports {sum(same)}/{w.B}")
     line["widened_signals"] = int(np.sum((g["res"]["status"] & 64) != 0))
+
+    if not args.no_uneven:
+        u = run_uneven(args.precision, max(3, args.steps // 2), 1)
+        line["uneven"] = u
+        log(f"uneven: {u}")
 
     if not args.no_cpu_baseline:
         cb, first = cpu_baseline(w, args.cpu_seconds)

@@ -71,6 +71,7 @@ extern "C" {
 #define OMP_SIG_NONFINITE 8  /* y_b held a NaN or Inf; nothing was selected, x_b = 0 */
 #define OMP_SIG_EXHAUSTED 32 /* no selectable atom was left (all selected or zero norm) */
 #define OMP_SIG_WIDENED 64   /* BF16 form: the FP32 re-score needed the widened candidate set */
+#define OMP_SIG_LEARNED 128  /* omp_learned_solve: the network's proposal was accepted (no OMP run) */
 
 /* ---- prepared dictionary ------------------------------------------------
  * Everything about A that does not depend on the signals (Section 2.2: the
@@ -161,6 +162,163 @@ size_t omp_workspace_size(int64_t M, int64_t N, int64_t B, int32_t S, const omp_
 int omp_solve(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y, int64_t B,
               int64_t ldy, int32_t S, float eps, float *X_out, int32_t *support_out,
               const omp_opts_t *opts, void *stream);
+
+/* ---- uneven batches: several problems, slot scheduling ------------------
+ * Batches whose signals stop at very different iterations (per-signal S_b and
+ * eps_b, Section 3.3 of the paper: finished signals either stay in the batch or
+ * are compacted out) and batches over several dictionaries. Each problem owns
+ * `slots` columns of the correlation product. A signal occupies a slot from
+ * its admission until it stops; the solve kernel then writes its outputs and
+ * admits the next waiting signal into that slot, so the product only spends
+ * work on signals still running (plus one iteration per signal for the hand
+ * over). The iteration loop of all problems is captured once into a hipGraph
+ * (problems on parallel branches) and replayed in chunks until every signal
+ * is out; the host reads one counter per problem between chunks.
+ * Results per signal are bit-identical to omp_solve with the same precision
+ * (a signal's arithmetic does not depend on its slot or neighbours). */
+typedef struct omp_problem {
+  const omp_dict_t *dict;       /* host, required: prepared dictionary (precision = opts->precision) */
+  const float *Y;               /* device [B][ldy]: signals, as in omp_solve */
+  int64_t B, ldy;
+  int32_t S;                    /* sparsity cap, 1 <= S <= min(M, N, OMP_MAX_S) */
+  float eps;                    /* tolerance when eps_per_signal is NULL (not NaN) */
+  const int32_t *S_per_signal;  /* device [B], optional */
+  const float *eps_per_signal;  /* device [B], optional */
+  int32_t *support_out;         /* device [B][S], required */
+  float *coef_out;              /* device [B][S], optional */
+  float *X_out;                 /* device [B][N], optional: dense x */
+  int32_t *status_out;          /* device [B], optional: as in omp_solve */
+  float *rnorm_out;             /* device [B], optional */
+  /* schedule (0 = chosen by shape; omp_tune writes its choices here) */
+  int32_t tile_config;          /* as omp_opts_t.tile_config */
+  int32_t slots;                /* signals in flight: a multiple of 256 (rounded up), capped at B */
+  int32_t residual_lanes;       /* lanes per signal in the residual kernel: 1, 2, 4, ..., 64 */
+} omp_problem_t;
+
+#define OMP_MAX_PROBLEMS 8
+
+typedef struct omp_multi_opts {
+  int32_t precision;            /* OMP_PREC_FP32 or OMP_PREC_BF16, for every problem */
+  int32_t iters_per_graph;      /* iterations per captured graph chunk; 0 = 8 */
+  void *workspace;              /* device, required: >= omp_multi_workspace_size(), 256-byte aligned */
+  size_t workspace_bytes;
+  float *elapsed_ms;            /* HOST, optional: GPU time of the whole call (events on `stream`) */
+  int32_t *iterations;          /* HOST, optional: iterations enqueued (whole chunks) */
+} omp_multi_opts_t;
+
+/* Workspace bytes for omp_solve_multi with these problems and schedules
+ * (0 for invalid arguments). */
+size_t omp_multi_workspace_size(const omp_problem_t *probs, int32_t nprob, const omp_multi_opts_t *opts);
+
+/* Solve nprob (1..OMP_MAX_PROBLEMS) batched OMP problems together (host
+ * arrays `probs`). Unlike omp_solve this call WAITS: it returns once every
+ * signal is out (the outputs are then complete). Concurrent calls from several
+ * host threads are serialized. The library keeps one small pinned host buffer,
+ * internal streams at default priority and a cache of captured graphs (keyed
+ * by every pointer and size of the call) for the life of the process.
+ * Returns OMP_EDEVICE (and leaves the outputs incomplete) if the signals have
+ * not all stopped after the bound sum over problems of
+ * ceil(B / slots) * (S + 2) + S + 2 iterations, which cannot happen for
+ * valid input. */
+int omp_solve_multi(const omp_problem_t *probs, int32_t nprob, const omp_multi_opts_t *opts, void *stream);
+
+/* Schedule autotuner: for each problem, times omp_solve_multi on its first
+ * `sample` signals (0 = min(B, 8192)) over the candidate tile configurations
+ * (1, 3, 4), slot counts (1024 .. 8192) and residual lane counts (by shape and
+ * half of it), and writes the fastest choice into probs[p].tile_config, .slots
+ * and .residual_lanes. The workspace must hold the largest candidate: size it
+ * with omp_multi_workspace_size on problems whose slots field is 8192 (or B).
+ * Overwrites the problems' output arrays (sample rows). Waits like
+ * omp_solve_multi. */
+int omp_tune(omp_problem_t *probs, int32_t nprob, const omp_multi_opts_t *opts, int64_t sample, void *stream);
+
+/* ---- learned support proposal -------------------------------------------
+ * An extension of the paper's method: a small network proposes the support
+ * and one least-squares solve checks it; plain OMP (omp_solve) takes over for
+ * every signal the proposal does not explain.
+ *   features  f_n = a_n^T y / (||a_n|| ||y||): Algorithm 1's first correlation,
+ *             normalised (BF16 product, so the dictionary is prepared for
+ *             OMP_PREC_BF16)
+ *   network   h1 = relu(W1 f + b1), h2 = relu(W2 h1 + b2), z = W3 h2 + b3,
+ *             BF16 operands, FP32 accumulation, W_l stored [out][in]
+ *   proposal  the S atoms with the largest z (ties to the lowest index)
+ *   check     least squares on the proposal (Eq. 2) by Cholesky of the Gram
+ *             block G[P, P] (Section 2.2), FP64 pivots; accepted when
+ *             ||y - A_P x|| <= eps_b and no pivot falls under the dependency
+ *             threshold
+ *   training  binary cross-entropy with logits against the multi-hot support
+ *             of a plain OMP solve, averaged over the batch; Adam (Kingma and
+ *             Ba, 2015) on FP32 master weights with BF16 copies.
+ * Sizes: n_in = n_out = the dictionary's N, n_hidden; each a multiple of 256. */
+typedef struct omp_mlp {
+  uint32_t magic;     /* set by omp_mlp_init */
+  int32_t n_in, n_hidden, n_out;
+  int64_t step;       /* Adam steps taken */
+  void *mem;          /* device memory holding weights, BF16 copies and Adam moments */
+  size_t bytes;
+} omp_mlp_t;
+
+/* Bytes of device memory for a network of these sizes (0 if invalid). */
+size_t omp_mlp_size(int32_t n_in, int32_t n_hidden, int32_t n_out);
+
+/* Initialise a network from caller-drawn FP32 parameters (device):
+ * params[0..5] = W1 [n_hidden][n_in], b1 [n_hidden], W2 [n_hidden][n_hidden],
+ * b2 [n_hidden], W3 [n_out][n_hidden], b3 [n_out]. Adam moments are zeroed and
+ * step = 0. `mem` (device, >= omp_mlp_size, 256-byte aligned) is caller-owned. */
+int omp_mlp_init(omp_mlp_t *mlp, int32_t n_in, int32_t n_hidden, int32_t n_out, const float *const params[6],
+                 void *mem, size_t bytes, void *stream);
+
+/* Copy the FP32 master parameters out (device arrays laid out as in omp_mlp_init). */
+int omp_mlp_export(const omp_mlp_t *mlp, float *const params[6], void *stream);
+
+/* Workspace bytes for omp_mlp_features / _forward / _grad / _train_step on B
+ * signals of length M (M only matters for omp_mlp_features). */
+size_t omp_mlp_workspace_size(const omp_mlp_t *mlp, int64_t M, int64_t B);
+
+/* Features of B signals: F[b][n] (BF16 bits, row stride N) = f_n of y_b; a zero
+ * or non-finite y_b gives a zero row. `dict` prepared for OMP_PREC_BF16. */
+int omp_mlp_features(const omp_dict_t *dict, const float *Y, int64_t B, int64_t ldy, uint16_t *F,
+                     const omp_mlp_t *mlp, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Scores Z[b][n] (FP32, row stride n_out) of B feature rows F (BF16, row stride n_in). */
+int omp_mlp_forward(const omp_mlp_t *mlp, const uint16_t *F, int64_t B, float *Z, void *workspace,
+                    size_t workspace_bytes, void *stream);
+
+/* Loss and gradients on B feature rows against the supports support[.][S]
+ * (-1 entries ignored). rows (device int32 [B], optional): the batch is rows
+ * rows[0..B-1] of F and support (a minibatch of a larger set); NULL takes
+ * rows 0..B-1. loss_out (device [1], optional): the batch loss.
+ * grads_out (host array of 6 device pointers, optional; entries may be NULL):
+ * FP32 gradients in the parameter layout of omp_mlp_init. The network is not
+ * changed. */
+int omp_mlp_grad(const omp_mlp_t *mlp, const uint16_t *F, const int32_t *support, const int32_t *rows, int64_t B,
+                 int32_t S, float *loss_out, float *const grads_out[6], void *workspace, size_t workspace_bytes,
+                 void *stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, epsilon 1e-8) with learning rate lr
+ * on the batch's gradients (batch selection as in omp_mlp_grad); mlp->step is
+ * incremented. */
+int omp_mlp_train_step(omp_mlp_t *mlp, const uint16_t *F, const int32_t *support, const int32_t *rows, int64_t B,
+                       int32_t S, float lr, float *loss_out, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Workspace bytes for omp_learned_solve (including the fallback omp_solve on
+ * up to B signals at opts->precision). */
+size_t omp_learned_workspace_size(const omp_dict_t *dict, const omp_mlp_t *mlp, int64_t B, int32_t S,
+                                  const omp_opts_t *fallback);
+
+/* Learned solve of B signals: features, network, top-S proposal, least-squares
+ * check; the rejected signals are gathered and solved by omp_solve (with
+ * `fallback`'s precision and tile configuration; its workspace, dict and
+ * optional-array fields are ignored: the dictionary `dict` and this call's
+ * workspace are used) and scattered back. Outputs as omp_solve's compact ones:
+ * support_out/coef_out [B][S], status_out [B] (accepted: (S << 8) | OMP_SIG_EPS
+ * | OMP_SIG_LEARNED), rnorm_out [B]. accepted_out (HOST, optional) receives the
+ * number of accepted proposals. S <= 64. This call waits for the stream once
+ * (to size the fallback). */
+int omp_learned_solve(const omp_dict_t *dict, const omp_mlp_t *mlp, const float *Y, int64_t B, int64_t ldy,
+                      int32_t S, float eps, const float *eps_per_signal, int32_t *support_out, float *coef_out,
+                      int32_t *status_out, float *rnorm_out, int64_t *accepted_out, const omp_opts_t *fallback,
+                      void *workspace, size_t workspace_bytes, void *stream);
 
 /* Human-readable text for a return code (static storage). */
 const char *omp_status_string(int status);

@@ -101,6 +101,8 @@ T *at(void *base, size_t off) {
   return reinterpret_cast<T *>(static_cast<char *>(base) + off);
 }
 
+}  // namespace
+
 bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
 // Sizes whose padded buffers would overflow or exceed any real device are rejected.
@@ -134,6 +136,8 @@ int check_device() {
   }
   return OMP_OK;
 }
+
+namespace {
 
 // Optional profiling (omp_opts_t.phase_ms): brackets every launch with a pair
 // of hipEvents on the solve's stream and sums the elapsed times per phase.

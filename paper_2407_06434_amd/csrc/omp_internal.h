@@ -25,6 +25,7 @@ constexpr double DEP_TOL2 = 1e-6;
 // Internal per-signal flag bits (the low byte holds the public OMP_SIG_* bits).
 constexpr int FLAG_DONE = 1 << 16;  // the signal takes no further picks
 constexpr int FLAG_NEWX = 1 << 17;  // coefficients changed: the residual kernel must run
+constexpr int FLAG_EMPTY = 1 << 18; // slot scheduler: the slot holds no signal (its last one is out)
 
 // The residual is computed in up to this many slices of M (one per XCD).
 constexpr int NSLICE_MAX = 8;
@@ -82,6 +83,30 @@ struct WorkView {
 size_t work_bytes(int64_t M, int64_t N, int64_t B, int S, int precision, int cfg);
 WorkView work_view(void *mem, int64_t M, int64_t N, int64_t B, int S, int precision, int cfg);
 
+// Slot scheduler (uneven batches): the workspace's B columns are slots that
+// signals pass through. When a slot's signal stops, the solve kernel writes that
+// signal's outputs and admits the next waiting signal into the slot.
+struct SlotView {
+  int32_t *sig;          // [slots] signal held by each slot, -1 when empty
+  int32_t *ctrl;         // [0] next signal to admit, [1] signals finished
+  const float *Y;        // the problem's signals, y_i = Y[i*ldy ..]
+  int64_t ldy, M, nsig;
+  const int32_t *S_per;  // optional per-signal sparsity caps
+  const float *eps_per;  // optional per-signal tolerances
+  float eps;
+  int32_t *support_out;  // [nsig][S]
+  float *coef_out;       // [nsig][S]
+  int32_t *status_out;   // optional [nsig]
+  float *rnorm_out;      // optional [nsig]
+};
+
+// ---- host helpers shared by the entry points --------------------------------
+bool aligned(const void *p, size_t a);
+bool dims_ok(int64_t M, int64_t N);          // sizes the padded buffers can hold
+int device_error(hipError_t e);              // records e for omp_last_hip_error, returns OMP_EDEVICE
+int check_device();                          // OMP_OK on a gfx950 device
+constexpr size_t WS_ALIGN = 256;
+
 // ---- launchers (all enqueue on `st`, return the launch status) -------------
 
 // Atom norms, padded FP32 copy and (optionally) BF16 copy of A.
@@ -99,6 +124,21 @@ hipError_t launch_corr_select(const DictView &d, const WorkView &w, int precisio
 hipError_t launch_solve(const DictView &d, const WorkView &w, int precision, hipStream_t st);
 // Residual r = y - A_S x (and its BF16 copy and per-slice norms) for the signals just updated.
 hipError_t launch_residual(const DictView &d, const WorkView &w, int precision, hipStream_t st);
+// Slot scheduler: fill the slots with the first signals and reset the queue.
+hipError_t launch_init_slots(const WorkView &w, const SlotView &sv, hipStream_t st);
+// One OMP step per occupied slot; stopped signals are written out and replaced.
+hipError_t launch_solve_slots(const DictView &d, const WorkView &w, const SlotView &sv, int precision,
+                              hipStream_t st);
+// Residual with an explicit number of lanes per signal (power of two, 1..64; 0 = by shape).
+hipError_t launch_residual_lp(const DictView &d, const WorkView &w, int precision, int lanes,
+                              hipStream_t st);
+// Dense X [nsig][N] from compact supports and coefficients.
+hipError_t launch_densify(const int32_t *support, const float *coef, int64_t nsig, int S, int64_t N,
+                          float *X_out, hipStream_t st);
+// Raise the LDS limits of every kernel a solve with these views launches (no launch).
+hipError_t prepare_kernels(const DictView &d, const WorkView &w, int precision, int lanes);
+hipError_t prepare_corr(const DictView &d, const WorkView &w, int precision);
+
 // Outputs: dense X, support, coefficients, status, residual norm.
 hipError_t launch_finalize(const DictView &d, const WorkView &w, float *X_out,
                            int32_t *support_out, float *coef_out, int32_t *status_out,

@@ -29,6 +29,7 @@
 // Section 3.3, and is staged through LDS for the two triangular solves.
 
 #include <cmath>
+#include <cstring>
 
 #include "../../include/batched_omp.h"
 #include "omp_internal.h"
@@ -151,38 +152,55 @@ __device__ __attribute__((always_inline)) inline void atom_dots(const DictView &
 }
 
 // Queue of atoms to re-score against r, flushed two at a time (all values
-// wave-uniform; a pick has about two candidates on the benchmark workload);
-// keeps the best exact score, its atom, and that atom's a^T y.
+// wave-uniform; a pick has about two candidates on the benchmark workload).
+// A flush fetches, in one round with the dot products, each candidate's
+// ||a_n||^2 and Gram row G[n, support] (lane holds rows i = lane + 64 p), so
+// that whichever candidate wins, the solve needs no further memory round.
+// Keeps the best exact score, its atom, its a^T y, ||a||^2 and Gram row.
+template <int RPL>
 struct RescoreQueue {
   int n0 = -1, n1 = -1;
   double bs = -1.0;
-  double by = 0.0;
+  double by = 0.0, bnu2 = 0.0;
   int bn = 0x7fffffff;
+  float bg[RPL];
   __device__ __attribute__((always_inline)) void flush(const DictView &d, const float4 *r4, const float4 *y4,
-                                                       int lane) {
+                                                       const int (&si)[RPL], int k, int lane) {
     if (n0 < 0) return;
     const int n[2] = {n0, n1};
+    double nu2[2];
+    float gc[2][RPL];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      nu2[i] = n[i] >= 0 ? d.nu2[n[i]] : 1.0;
+#pragma unroll
+      for (int p = 0; p < RPL; ++p)
+        gc[i][p] = (n[i] >= 0 && lane + 64 * p < k) ? d.G[(int64_t)n[i] * d.Np + si[p]] : 0.f;
+    }
     double ar[2], ay[2];
     atom_dots<2, true, 2>(d, n, r4, y4, lane, ar, ay);
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       if (n[i] < 0) continue;
-      const double sc = fabs(ar[i]) / sqrt(d.nu2[n[i]]);
+      const double sc = fabs(ar[i]) / sqrt(nu2[i]);
       if (better(sc, n[i], bs, bn)) {
         bs = sc;
         bn = n[i];
         by = ay[i];
+        bnu2 = nu2[i];
+#pragma unroll
+        for (int p = 0; p < RPL; ++p) bg[p] = gc[i][p];
       }
     }
     n0 = n1 = -1;
   }
   __device__ __attribute__((always_inline)) void push(int atom, const DictView &d, const float4 *r4,
-                                                      const float4 *y4, int lane) {
+                                                      const float4 *y4, const int (&si)[RPL], int k, int lane) {
     if (n0 < 0) {
       n0 = atom;
     } else {
       n1 = atom;
-      flush(d, r4, y4, lane);
+      flush(d, r4, y4, si, k, lane);
     }
   }
 };
@@ -200,17 +218,19 @@ struct RescoreQueue {
 //      theta the subgroup's last kept score; when that reaches s_w the whole
 //      subgroup is re-scored (and the signal is flagged OMP_SIG_WIDENED).
 // The result is the exact argmax of s over the selectable atoms, ties to the
-// lowest index; *beta receives a_n*^T y of the pick (computed in the same pass
-// as its score).
-__device__ int select_bf16(const DictView &d, const WorkView &w, int64_t b, float smax, double tau, int lane,
-                           int *widened, double *beta) {
+// lowest index; *beta, *nu2 and g receive a_n*^T y, ||a_n*||^2 and the Gram
+// row G[n*, support] of the pick (fetched in the same round as its score).
+template <int RPL>
+__device__ int select_bf16(const DictView &d, const WorkView &w, int64_t b, float smax, double tau,
+                           const int (&si)[RPL], int k, int lane, int *widened, double *beta, double *nu2,
+                           float (&g)[RPL]) {
   const int nkeys = w.ntile * w.ncand;
   const uint64_t *keys = w.part + b * nkeys;
   const float4 *r4 = reinterpret_cast<const float4 *>(w.R32) + b * (d.Mp / 4);
   const float4 *y4 = reinterpret_cast<const float4 *>(w.Yp) + b * (d.Mp / 4);
   const double et = 1.0 / 262144.0;  // 2^-18: the epilogue's rounding of listed scores
   const double thr = (double)smax - 2.0 * tau - et * (double)smax;
-  RescoreQueue q;
+  RescoreQueue<RPL> q;
   for (int t0 = 0; t0 < nkeys; t0 += 64) {
     const int t = t0 + lane;
     const uint64_t k = t < nkeys ? keys[t] : 0ull;
@@ -220,10 +240,10 @@ __device__ int select_bf16(const DictView &d, const WorkView &w, int64_t b, floa
     while (m) {
       const int l = __ffsll((unsigned long long)m) - 1;
       m &= m - 1;
-      q.push(__builtin_amdgcn_readlane(n_l, l), d, r4, y4, lane);
+      q.push(__builtin_amdgcn_readlane(n_l, l), d, r4, y4, si, k, lane);
     }
   }
-  q.flush(d, r4, y4, lane);
+  q.flush(d, r4, y4, si, k, lane);
   const int64_t mwords = d.Np / 32;
   const uint32_t *mk = w.mask + b * mwords;
   for (int t0 = 0; t0 < nkeys; t0 += 64) {
@@ -247,12 +267,15 @@ __device__ int select_bf16(const DictView &d, const WorkView &w, int64_t b, floa
           for (int e = 0; e < 4; ++e) {
             const int n = tile * w.tile_atoms + wn * w.wave_atoms + 32 * (ig * w.sub_frags + i) + 8 * g + 4 * hh + e;
             if (d.inv_nu[n] <= 0.f || ((mk[n >> 5] >> (n & 31)) & 1u)) continue;
-            q.push(n, d, r4, y4, lane);
+            q.push(n, d, r4, y4, si, k, lane);
           }
-      q.flush(d, r4, y4, lane);
+      q.flush(d, r4, y4, si, k, lane);
     }
   }
   *beta = q.by;
+  *nu2 = q.bnu2;
+#pragma unroll
+  for (int p = 0; p < RPL; ++p) g[p] = q.bg[p];
   return q.bn == 0x7fffffff ? -1 : q.bn;
 }
 
@@ -263,10 +286,6 @@ typedef __attribute__((address_space(3))) void lds_void_t;
 // with s_waitcnt before the LDS data is read.
 __device__ inline void lds_load16(const float4 *src, float4 *dst_wave) {
   __builtin_amdgcn_global_load_lds(reinterpret_cast<const void *>(src), (lds_void_t *)(dst_wave), 16, 0,
-                                   0);
-}
-__device__ inline void lds_load4(const int32_t *src, int *dst_wave) {
-  __builtin_amdgcn_global_load_lds(reinterpret_cast<const void *>(src), (lds_void_t *)(dst_wave), 4, 0,
                                    0);
 }
 
@@ -325,19 +344,25 @@ __global__ __launch_bounds__(1024) void k_dict_aerr_max(const float *__restrict_
 }
 
 // ---------------------------------------------------------------------------
-// Solve set-up: one wavefront per (padded) signal.
+// Solve set-up.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_init(const float *__restrict__ Y, int64_t ldy,
-                                             const int32_t *__restrict__ S_per,
-                                             const float *__restrict__ eps_per, float eps, int64_t M,
-                                             WorkView w) {
-  const int64_t b = blockIdx.x;
-  const int lane = threadIdx.x;
-  const bool real = b < w.B;
+__device__ inline int signal_S(const int32_t *S_per, int64_t i, int S) {
+  return S_per ? min(max(S_per[i], 0), S) : S;
+}
+__device__ inline float signal_eps(const float *eps_per, int64_t i, float eps) {
+  return eps_per ? eps_per[i] : eps;
+}
+
+// Puts signal y (length M; null = no signal) into column b of the workspace: the
+// padded copy, r = y in FP32 (and BF16), ||y||^2 and ||y - bf16(y)||^2, a clear
+// atom mask, k = 0, and the stops that need no pick (non-finite y, ||y|| <= eps,
+// S_b = 0). A column without a signal gets `idle` as its flags. One wavefront.
+__device__ void init_column(const WorkView &w, int64_t b, const float *__restrict__ y, int64_t M, int Sb,
+                            float eb, int idle, int lane) {
   double s = 0.0, dl = 0.0;
   int finite = 1;
   for (int64_t m = lane; m < w.Mp; m += 64) {
-    const float v = (real && m < M) ? Y[b * ldy + m] : 0.f;
+    const float v = (y && m < M) ? y[m] : 0.f;
     finite &= isfinite(v) ? 1 : 0;
     const float vz = isfinite(v) ? v : 0.f;
     w.Yp[b * w.Mp + m] = vz;
@@ -360,13 +385,10 @@ __global__ __launch_bounds__(64) void k_init(const float *__restrict__ Y, int64_
     w.pdelta[b * NSLICE_MAX + lane] = (lane == 0 && all_finite) ? dl : 0.0;
   }
   if (lane == 0) {
-    int Sb = w.S;
-    if (S_per && real) Sb = min(max(S_per[b], 0), w.S);
-    float eb = (eps_per && real) ? eps_per[b] : eps;
     eb = fmaxf(eb, 0.f);  // also maps NaN to 0
     const double rn = sqrt(s);
     int fl = 0;
-    if (!real) fl = FLAG_DONE;
+    if (!y) fl = idle;
     else if (!all_finite) fl = FLAG_DONE | OMP_SIG_NONFINITE;
     else if (rn <= (double)eb || Sb == 0) fl = FLAG_DONE;
     w.flags[b] = fl;
@@ -376,16 +398,79 @@ __global__ __launch_bounds__(64) void k_init(const float *__restrict__ Y, int64_
   }
 }
 
+// One wavefront per (padded) signal.
+__global__ __launch_bounds__(64) void k_init(const float *__restrict__ Y, int64_t ldy,
+                                             const int32_t *__restrict__ S_per,
+                                             const float *__restrict__ eps_per, float eps, int64_t M,
+                                             WorkView w) {
+  const int64_t b = blockIdx.x;
+  const bool real = b < w.B;
+  init_column(w, b, real ? Y + b * ldy : nullptr, M, real ? signal_S(S_per, b, w.S) : w.S,
+              real ? signal_eps(eps_per, b, eps) : eps, FLAG_DONE, threadIdx.x);
+}
+
+// Slot scheduler set-up: slot i takes signal i while signals last; block 0
+// also resets the queue (next signal to admit, signals finished).
+__global__ __launch_bounds__(64) void k_init_slots(WorkView w, SlotView sv) {
+  const int64_t b = blockIdx.x;
+  const int lane = threadIdx.x;
+  const bool real = b < sv.nsig;
+  if (lane == 0) sv.sig[b] = real ? (int32_t)b : -1;
+  if (b == 0 && lane == 0) {
+    sv.ctrl[0] = (int32_t)min<int64_t>(sv.nsig, w.B);
+    sv.ctrl[1] = 0;
+  }
+  init_column(w, b, real ? sv.Y + b * sv.ldy : nullptr, sv.M, real ? signal_S(sv.S_per, b, w.S) : w.S,
+              real ? signal_eps(sv.eps_per, b, sv.eps) : sv.eps, FLAG_DONE | FLAG_EMPTY, lane);
+}
+
+// Slot scheduler: the signal in slot b has stopped (flags fl, k atoms, residual
+// norm rn). Writes its support, coefficients, status and ||r|| (same stop
+// reasons and order as the output kernel), then admits the next waiting
+// signal into the slot, or marks the slot empty. One wavefront.
+__device__ void retire_and_admit(const WorkView &w, const SlotView &sv, int64_t b, int fl, int k, double rn,
+                                 int lane) {
+  const int S = w.S;
+  const int64_t sg = sv.sig[b];
+  for (int j = lane; j < S; j += 64) {
+    const bool in = j < k;
+    sv.support_out[sg * S + j] = in ? w.sup[b * S + j] : -1;
+    sv.coef_out[sg * S + j] = in ? w.xh[b * S + j] : 0.f;
+  }
+  int nxt = 0;
+  if (lane == 0) {
+    int st = fl & (OMP_SIG_NONFINITE | OMP_SIG_DEPENDENT | OMP_SIG_EXHAUSTED);
+    if (st == 0) {
+      if (rn <= (double)w.epsb[b]) st |= OMP_SIG_EPS;
+      if (k >= w.Sb[b]) st |= OMP_SIG_SMAX;
+    }
+    st |= fl & OMP_SIG_WIDENED;
+    if (sv.status_out) sv.status_out[sg] = (k << 8) | st;
+    if (sv.rnorm_out) sv.rnorm_out[sg] = (float)rn;
+    nxt = atomicAdd(sv.ctrl, 1);
+    atomicAdd(sv.ctrl + 1, 1);
+  }
+  nxt = __shfl(nxt, 0);
+  if (nxt < sv.nsig) {
+    if (lane == 0) sv.sig[b] = nxt;
+    init_column(w, b, sv.Y + (int64_t)nxt * sv.ldy, sv.M, signal_S(sv.S_per, nxt, S),
+                signal_eps(sv.eps_per, nxt, sv.eps), FLAG_DONE | FLAG_EMPTY, lane);
+  } else if (lane == 0) {
+    sv.sig[b] = -1;
+    w.flags[b] = FLAG_DONE | FLAG_EMPTY;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Solve step. One 64-lane wavefront per signal, SOLVE_WAVES signals per block
 // (the wavefronts share nothing; each has its own LDS region). RPL = rows of V
 // per lane (S <= 64 RPL; RPL in {1, 2, 4}).
 // LDS per wavefront: V (vstride floats).
-// Memory is read in as few dependent rounds as possible: first everything
-// whose address depends on the signal only (state, norms, the epilogue's
-// keys, support, u), then the packed factor together with what depends on
-// the pick (FP32 form: Gram row, ||a_n*||^2, a_n*^T y; BF16 form: the exact
-// re-score of the candidates, followed by the Gram row of the winner).
+// Memory is read in two dependent rounds: first everything whose address
+// depends on the signal only (state, norms, the epilogue's keys, support, u),
+// then the packed factor together with what depends on the pick (Gram row,
+// ||a_n*||^2, a_n*^T y; in the BF16 form fetched for every re-scored
+// candidate alongside its exact score).
 // The triangular solves run column by column; the reciprocal diagonal is
 // computed up front in parallel and the next column is read from LDS while
 // the current one is applied, so the sequential chain holds no division and
@@ -393,8 +478,17 @@ __global__ __launch_bounds__(64) void k_init(const float *__restrict__ Y, int64_
 // ---------------------------------------------------------------------------
 constexpr int SOLVE_WAVES = 4;
 
-template <int RPL, bool BF16>
-__global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView w) {
+// A stop found by the solve step: record the flags, or (slot scheduler) write
+// the signal out and admit the next one.
+template <bool SLOTS>
+__device__ inline void stop_signal(const WorkView &w, const SlotView &sv, int64_t b, int fl, int k, double rn,
+                                   int lane) {
+  if (SLOTS) retire_and_admit(w, sv, b, fl, k, rn, lane);
+  else if (lane == 0) w.flags[b] = fl;
+}
+
+template <int RPL, bool BF16, bool SLOTS>
+__global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView w, SlotView sv) {
   extern __shared__ float smem[];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t b = (int64_t)blockIdx.x * SOLVE_WAVES + wv;
@@ -409,6 +503,11 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
   const int k = w.k[b];
   const double pn = lane < NSLICE_MAX ? w.pnorm[b * NSLICE_MAX + lane] : 0.0;
   const double pd = (BF16 && lane < NSLICE_MAX) ? w.pdelta[b * NSLICE_MAX + lane] : 0.0;
+  // Every stop found below leaves through the `stop` label with these set, so
+  // that the stop's code (slot scheduler: the retire and admit) exists once.
+  int stopfl = 0;
+  double rn = 0.0;
+  {
   int si[RPL];
   float uo[RPL];
 #pragma unroll
@@ -429,18 +528,27 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
     fl &= ~FLAG_NEWX;
     if (lane == 0) w.flags[b] = fl;
   }
-  if (fl & FLAG_DONE) return;  // the wavefront exits as a whole
+  if (fl & FLAG_DONE) {  // the wavefront exits as a whole
+    // slot scheduler: a signal that stopped at its last pick leaves now that
+    // its final residual is known
+    if (SLOTS && !(fl & FLAG_EMPTY)) {
+      rn = sqrt(wave_sum(pn));
+      stopfl = fl;
+      goto stop;
+    }
+    return;
+  }
 
   // 0. Stop test on the current residual (Algorithm 1 stops once ||r|| <= eps).
-  const double rn = sqrt(wave_sum(pn));
+  rn = sqrt(wave_sum(pn));
   if (rn <= (double)w.epsb[b]) {
-    if (lane == 0) w.flags[b] = fl | FLAG_DONE;
-    return;
+    stopfl = fl | FLAG_DONE;
+    goto stop;
   }
   kmax = wave_max(kmax);
   if (kmax == 0ull) {  // nothing selectable is left
-    if (lane == 0) w.flags[b] = fl | FLAG_DONE | OMP_SIG_EXHAUSTED;
-    return;
+    stopfl = fl | FLAG_DONE | OMP_SIG_EXHAUSTED;
+    goto stop;
   }
 #pragma unroll
   for (int p = 0; p < RPL; ++p)
@@ -467,17 +575,11 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
   float g[RPL];
   if (BF16) {
     const double tau = bf16_tau(rn, sqrt(wave_sum(pd)), (double)d.aerr_max[0], d.Mp);
-    nstar = select_bf16(d, w, b, __uint_as_float((uint32_t)(kmax >> 32)), tau, lane, &widened, &beta);
+    nstar = select_bf16<RPL>(d, w, b, __uint_as_float((uint32_t)(kmax >> 32)), tau, si, k, lane, &widened, &beta,
+                             &nu2, g);
     if (nstar < 0) {
-      if (lane == 0) w.flags[b] = fl | FLAG_DONE | OMP_SIG_EXHAUSTED;
-      return;
-    }
-    // ---- round 3: Gram row and ||a_n*||^2 of the pick
-    nu2 = d.nu2[nstar];
-#pragma unroll
-    for (int p = 0; p < RPL; ++p) {
-      const int i = lane + 64 * p;
-      g[p] = i < k ? d.G[(int64_t)nstar * d.Np + si[p]] : 0.f;
+      stopfl = fl | FLAG_DONE | OMP_SIG_EXHAUSTED;
+      goto stop;
     }
   } else {
     nstar = (int)(0xFFFFFFFFu - (uint32_t)(kmax & 0xFFFFFFFFull));
@@ -555,8 +657,8 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
   zz = wave_sum(zz);
   const double d2 = nu2 - zz;
   if (!(d2 > DEP_TOL2 * nu2)) {  // dependent atom: stop without appending
-    if (lane == 0) w.flags[b] = fl | FLAG_DONE | OMP_SIG_DEPENDENT;
-    return;
+    stopfl = fl | FLAG_DONE | OMP_SIG_DEPENDENT;
+    goto stop;
   }
   const float dk = (float)sqrt(d2);
 
@@ -650,6 +752,10 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
     w.k[b] = K;
     w.flags[b] = fl;
   }
+  }
+  return;
+stop:
+  stop_signal<SLOTS>(w, sv, b, stopfl, k, rn, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -791,14 +897,57 @@ hipError_t allow_lds(K kernel, size_t bytes) {
                              (int)bytes);
 }
 
-template <int RPL, bool BF16>
-hipError_t launch_solve_t(const DictView &d, const WorkView &w, hipStream_t st) {
+// Dense X [nsig][N] from the compact outputs: one 256-lane block per signal
+// zero-fills its row, then scatters the coefficients (the barrier orders the
+// two passes' stores within the block).
+__global__ __launch_bounds__(256) void k_densify(const int32_t *__restrict__ support, const float *__restrict__ coef,
+                                                 int S, int64_t N, float *__restrict__ X_out) {
+  const int64_t b = blockIdx.x;
+  for (int64_t n = threadIdx.x; n < N; n += blockDim.x) X_out[b * N + n] = 0.f;
+  __syncthreads();
+  for (int j = threadIdx.x; j < S; j += blockDim.x) {
+    const int n = support[b * S + j];
+    if (n >= 0 && n < N) X_out[b * N + n] = coef[b * S + j];
+  }
+}
+
+template <int RPL, bool BF16, bool SLOTS>
+hipError_t launch_solve_t(const DictView &d, const WorkView &w, const SlotView &sv, hipStream_t st) {
   const size_t lds = (size_t)w.vstride * 4 * SOLVE_WAVES;
-  hipError_t e = allow_lds(k_solve<RPL, BF16>, lds);
+  hipError_t e = allow_lds(k_solve<RPL, BF16, SLOTS>, lds);
   if (e != hipSuccess) return e;
   const unsigned blocks = (unsigned)((w.B + SOLVE_WAVES - 1) / SOLVE_WAVES);
-  hipLaunchKernelGGL((k_solve<RPL, BF16>), dim3(blocks), dim3(64 * SOLVE_WAVES), lds, st, d, w);
+  hipLaunchKernelGGL((k_solve<RPL, BF16, SLOTS>), dim3(blocks), dim3(64 * SOLVE_WAVES), lds, st, d, w, sv);
   return hipGetLastError();
+}
+
+template <bool SLOTS>
+hipError_t launch_solve_any(const DictView &d, const WorkView &w, const SlotView &sv, int precision,
+                            hipStream_t st) {
+  if (w.B == 0) return hipSuccess;
+  const bool bf = precision == OMP_PREC_BF16;
+  if (w.S <= 64)
+    return bf ? launch_solve_t<1, true, SLOTS>(d, w, sv, st) : launch_solve_t<1, false, SLOTS>(d, w, sv, st);
+  if (w.S <= 128)
+    return bf ? launch_solve_t<2, true, SLOTS>(d, w, sv, st) : launch_solve_t<2, false, SLOTS>(d, w, sv, st);
+  return bf ? launch_solve_t<4, true, SLOTS>(d, w, sv, st) : launch_solve_t<4, false, SLOTS>(d, w, sv, st);
+}
+
+size_t residual_lds(const WorkView &w, int LP) { return (size_t)4 * (64 / LP) * w.S * 8; }
+
+// Lanes per signal of the residual kernel: as requested, else by shape (one
+// lane per float4 of a slice, up to a whole wavefront); raised until the
+// block's coefficient and support tables fit in LDS.
+int residual_lanes(const WorkView &w, int lanes) {
+  int LP = 1;
+  if (lanes > 0) {
+    LP = lanes;
+  } else {
+    const int sl4 = w.slice_len / 4;
+    while (LP < sl4 && LP < 64) LP *= 2;
+  }
+  while (LP < 64 && residual_lds(w, LP) > (size_t)160 * 1024) LP *= 2;
+  return LP;
 }
 
 }  // namespace
@@ -818,21 +967,29 @@ hipError_t launch_init(const float *Y, int64_t ldy, const int32_t *S_per, const 
 }
 
 hipError_t launch_solve(const DictView &d, const WorkView &w, int precision, hipStream_t st) {
-  if (w.B == 0) return hipSuccess;
-  const bool bf = precision == OMP_PREC_BF16;
-  if (w.S <= 64) return bf ? launch_solve_t<1, true>(d, w, st) : launch_solve_t<1, false>(d, w, st);
-  if (w.S <= 128) return bf ? launch_solve_t<2, true>(d, w, st) : launch_solve_t<2, false>(d, w, st);
-  return bf ? launch_solve_t<4, true>(d, w, st) : launch_solve_t<4, false>(d, w, st);
+  SlotView none;
+  memset(&none, 0, sizeof(none));
+  return launch_solve_any<false>(d, w, none, precision, st);
 }
 
-hipError_t launch_residual(const DictView &d, const WorkView &w, int precision, hipStream_t st) {
+hipError_t launch_solve_slots(const DictView &d, const WorkView &w, const SlotView &sv, int precision,
+                              hipStream_t st) {
+  return launch_solve_any<true>(d, w, sv, precision, st);
+}
+
+hipError_t launch_init_slots(const WorkView &w, const SlotView &sv, hipStream_t st) {
   if (w.B == 0) return hipSuccess;
-  const int sl4 = w.slice_len / 4;
-  int LP = 1;
-  while (LP < sl4 && LP < 64) LP *= 2;
+  hipLaunchKernelGGL(k_init_slots, dim3((unsigned)w.Bp), dim3(64), 0, st, w, sv);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual_lp(const DictView &d, const WorkView &w, int precision, int lanes, hipStream_t st) {
+  if (w.B == 0) return hipSuccess;
+  const int LP = residual_lanes(w, lanes);
+  if (LP < 1 || LP > 64 || (LP & (LP - 1))) return hipErrorInvalidValue;
   const int items = 4 * (64 / LP);
   const int64_t groups = (w.B + items - 1) / items;
-  const size_t lds = (size_t)items * w.S * 8;
+  const size_t lds = residual_lds(w, LP);
   const dim3 grid((unsigned)(groups * w.nslice)), block(256);
   if (precision == OMP_PREC_BF16) {
     hipError_t e = allow_lds(k_residual<true>, lds);
@@ -844,6 +1001,31 @@ hipError_t launch_residual(const DictView &d, const WorkView &w, int precision, 
     hipLaunchKernelGGL(k_residual<false>, grid, block, lds, st, d, w, LP);
   }
   return hipGetLastError();
+}
+
+hipError_t launch_residual(const DictView &d, const WorkView &w, int precision, hipStream_t st) {
+  return launch_residual_lp(d, w, precision, 0, st);
+}
+
+hipError_t launch_densify(const int32_t *support, const float *coef, int64_t nsig, int S, int64_t N,
+                          float *X_out, hipStream_t st) {
+  if (nsig == 0 || !X_out) return hipSuccess;
+  hipLaunchKernelGGL(k_densify, dim3((unsigned)nsig), dim3(256), 0, st, support, coef, S, N, X_out);
+  return hipGetLastError();
+}
+
+hipError_t prepare_kernels(const DictView &d, const WorkView &w, int precision, int lanes) {
+  const size_t slds = (size_t)w.vstride * 4 * SOLVE_WAVES;
+  const bool bf = precision == OMP_PREC_BF16;
+  hipError_t e = hipSuccess;
+  if (w.S <= 64) e = bf ? allow_lds(k_solve<1, true, true>, slds) : allow_lds(k_solve<1, false, true>, slds);
+  else if (w.S <= 128) e = bf ? allow_lds(k_solve<2, true, true>, slds) : allow_lds(k_solve<2, false, true>, slds);
+  else e = bf ? allow_lds(k_solve<4, true, true>, slds) : allow_lds(k_solve<4, false, true>, slds);
+  if (e != hipSuccess) return e;
+  const size_t rlds = residual_lds(w, residual_lanes(w, lanes));
+  e = bf ? allow_lds(k_residual<true>, rlds) : allow_lds(k_residual<false>, rlds);
+  if (e != hipSuccess) return e;
+  return prepare_corr(d, w, precision);
 }
 
 hipError_t launch_finalize(const DictView &d, const WorkView &w, float *X_out, int32_t *support_out,

@@ -26,7 +26,12 @@ PHASES = ("dict", "init", "corr", "update", "output", "residual")
 SIG_EPS, SIG_SMAX, SIG_DEPENDENT, SIG_NONFINITE, SIG_EXHAUSTED, SIG_WIDENED = 1, 2, 4, 8, 32, 64
 
 EXPORTED = ("omp_dict_size", "omp_dict_init", "omp_opts_default", "omp_workspace_size", "omp_solve",
-            "omp_status_string", "omp_last_hip_error", "omp_version")
+            "omp_status_string", "omp_last_hip_error", "omp_version", "omp_multi_workspace_size",
+            "omp_solve_multi", "omp_tune", "omp_mlp_size", "omp_mlp_init", "omp_mlp_export",
+            "omp_mlp_workspace_size", "omp_mlp_features", "omp_mlp_forward", "omp_mlp_grad", "omp_mlp_train_step",
+            "omp_learned_workspace_size", "omp_learned_solve")
+SIG_LEARNED = 128
+OMP_MAX_PROBLEMS = 8
 
 
 class OmpError(RuntimeError):
@@ -55,6 +60,27 @@ class OmpOptsStruct(ctypes.Structure):
                 ("phase_launches", ctypes.POINTER(ctypes.c_int32))]
 
 
+class OmpProblemStruct(ctypes.Structure):
+    _fields_ = [("dict", ctypes.POINTER(OmpDictStruct)), ("Y", ctypes.c_void_p), ("B", ctypes.c_int64),
+                ("ldy", ctypes.c_int64), ("S", ctypes.c_int32), ("eps", ctypes.c_float),
+                ("S_per_signal", ctypes.c_void_p), ("eps_per_signal", ctypes.c_void_p),
+                ("support_out", ctypes.c_void_p), ("coef_out", ctypes.c_void_p), ("X_out", ctypes.c_void_p),
+                ("status_out", ctypes.c_void_p), ("rnorm_out", ctypes.c_void_p),
+                ("tile_config", ctypes.c_int32), ("slots", ctypes.c_int32), ("residual_lanes", ctypes.c_int32)]
+
+
+class OmpMultiOptsStruct(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("iters_per_graph", ctypes.c_int32),
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
+                ("elapsed_ms", ctypes.POINTER(ctypes.c_float)), ("iterations", ctypes.POINTER(ctypes.c_int32))]
+
+
+class OmpMlpStruct(ctypes.Structure):
+    _fields_ = [("magic", ctypes.c_uint32), ("n_in", ctypes.c_int32), ("n_hidden", ctypes.c_int32),
+                ("n_out", ctypes.c_int32), ("step", ctypes.c_int64), ("mem", ctypes.c_void_p),
+                ("bytes", ctypes.c_size_t)]
+
+
 _lib = None
 
 
@@ -78,6 +104,38 @@ def load():
     lib.omp_solve.restype = ctypes.c_int
     lib.omp_solve.argtypes = [P, I64, I64, I64, P, I64, I64, I32, ctypes.c_float, P, P,
                               ctypes.POINTER(OmpOptsStruct), P]
+    PP = ctypes.POINTER(OmpProblemStruct)
+    PO = ctypes.POINTER(OmpMultiOptsStruct)
+    lib.omp_multi_workspace_size.restype = SZ
+    lib.omp_multi_workspace_size.argtypes = [PP, I32, PO]
+    lib.omp_solve_multi.restype = ctypes.c_int
+    lib.omp_solve_multi.argtypes = [PP, I32, PO, P]
+    lib.omp_tune.restype = ctypes.c_int
+    lib.omp_tune.argtypes = [PP, I32, PO, I64, P]
+    PM = ctypes.POINTER(OmpMlpStruct)
+    PD = ctypes.POINTER(OmpDictStruct)
+    P6 = ctypes.POINTER(ctypes.c_void_p)
+    lib.omp_mlp_size.restype = SZ
+    lib.omp_mlp_size.argtypes = [I32, I32, I32]
+    lib.omp_mlp_init.restype = ctypes.c_int
+    lib.omp_mlp_init.argtypes = [PM, I32, I32, I32, P6, P, SZ, P]
+    lib.omp_mlp_export.restype = ctypes.c_int
+    lib.omp_mlp_export.argtypes = [PM, P6, P]
+    lib.omp_mlp_workspace_size.restype = SZ
+    lib.omp_mlp_workspace_size.argtypes = [PM, I64, I64]
+    lib.omp_mlp_features.restype = ctypes.c_int
+    lib.omp_mlp_features.argtypes = [PD, P, I64, I64, P, PM, P, SZ, P]
+    lib.omp_mlp_forward.restype = ctypes.c_int
+    lib.omp_mlp_forward.argtypes = [PM, P, I64, P, P, SZ, P]
+    lib.omp_mlp_grad.restype = ctypes.c_int
+    lib.omp_mlp_grad.argtypes = [PM, P, P, P, I64, I32, P, P6, P, SZ, P]
+    lib.omp_mlp_train_step.restype = ctypes.c_int
+    lib.omp_mlp_train_step.argtypes = [PM, P, P, P, I64, I32, ctypes.c_float, P, P, SZ, P]
+    lib.omp_learned_workspace_size.restype = SZ
+    lib.omp_learned_workspace_size.argtypes = [PD, PM, I64, I32, ctypes.POINTER(OmpOptsStruct)]
+    lib.omp_learned_solve.restype = ctypes.c_int
+    lib.omp_learned_solve.argtypes = [PD, PM, P, I64, I64, I32, ctypes.c_float, P, P, P, P, P,
+                                      ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(OmpOptsStruct), P, SZ, P]
     lib.omp_status_string.restype = ctypes.c_char_p
     lib.omp_status_string.argtypes = [ctypes.c_int]
     lib.omp_last_hip_error.restype = ctypes.c_int
@@ -214,3 +272,249 @@ def solve(A: torch.Tensor, Y: torch.Tensor, S: int, eps: float = 0.0, *, precisi
             t0, n0 = timing.get(name, (0.0, 0))
             timing[name] = (t0 + float(ms[p]), n0 + int(nl[p]))
     return out
+
+
+class Problem:
+    """One batch of an uneven multi-problem solve: signals Y (B, M) over a prepared
+    dictionary, with optional per-signal S and eps. `tile_config`, `slots` and
+    `residual_lanes` are the schedule (0 = by shape; tune() fills them)."""
+
+    def __init__(self, dictionary: Dictionary, Y: torch.Tensor, S: int, eps: float = 0.0,
+                 S_per_signal: Optional[torch.Tensor] = None, eps_per_signal: Optional[torch.Tensor] = None,
+                 dense: bool = False, tile_config: int = 0, slots: int = 0, residual_lanes: int = 0):
+        _check_matrix(Y, "Y", dictionary.M)
+        B = Y.shape[0]
+        dev = Y.device
+        for name, t, dt in (("S_per_signal", S_per_signal, torch.int32), ("eps_per_signal", eps_per_signal,
+                                                                           torch.float32)):
+            if t is not None and (t.dtype != dt or t.shape != (B,) or not t.is_contiguous() or not t.is_cuda):
+                raise TypeError(f"{name} must be a contiguous {dt} CUDA tensor of shape (B,)")
+        self.dictionary, self.Y, self.S, self.eps = dictionary, Y, int(S), float(eps)
+        self.S_per_signal, self.eps_per_signal = S_per_signal, eps_per_signal
+        self.tile_config, self.slots, self.residual_lanes = int(tile_config), int(slots), int(residual_lanes)
+        self.out = Result(torch.empty((B, dictionary.N), dtype=torch.float32, device=dev) if dense else None,
+                          torch.empty((B, self.S), dtype=torch.int32, device=dev),
+                          torch.empty((B, self.S), dtype=torch.float32, device=dev),
+                          torch.empty(B, dtype=torch.int32, device=dev),
+                          torch.empty(B, dtype=torch.float32, device=dev))
+
+    def struct(self) -> OmpProblemStruct:
+        p = OmpProblemStruct()
+        p.dict = ctypes.pointer(self.dictionary.struct)
+        p.Y = self.Y.data_ptr()
+        p.B = self.Y.shape[0]
+        p.ldy = self.Y.stride(0)
+        p.S = self.S
+        p.eps = self.eps
+        p.S_per_signal = None if self.S_per_signal is None else self.S_per_signal.data_ptr()
+        p.eps_per_signal = None if self.eps_per_signal is None else self.eps_per_signal.data_ptr()
+        p.support_out = self.out.support.data_ptr()
+        p.coef_out = self.out.coef.data_ptr()
+        p.X_out = None if self.out.X is None else self.out.X.data_ptr()
+        p.status_out = self.out.status.data_ptr()
+        p.rnorm_out = self.out.rnorm.data_ptr()
+        p.tile_config, p.slots, p.residual_lanes = self.tile_config, self.slots, self.residual_lanes
+        return p
+
+
+def _multi_call(problems, precision, iters_per_graph, workspace):
+    if not 1 <= len(problems) <= OMP_MAX_PROBLEMS:
+        raise ValueError(f"1..{OMP_MAX_PROBLEMS} problems")
+    precs = {p.dictionary.precision for p in problems}
+    if precs != {precision}:
+        raise ValueError("every dictionary must be prepared for the solve's precision")
+    lib = load()
+    arr = (OmpProblemStruct * len(problems))(*[p.struct() for p in problems])
+    o = OmpMultiOptsStruct()
+    o.precision = PREC[precision]
+    o.iters_per_graph = int(iters_per_graph)
+    need = lib.omp_multi_workspace_size(arr, len(problems), ctypes.byref(o))
+    if need == 0:
+        raise OmpError(OMP_EINVAL, "omp_multi_workspace_size")
+    dev = problems[0].Y.device
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+    o.workspace = workspace.data_ptr()
+    o.workspace_bytes = workspace.numel()
+    return lib, arr, o, dev, workspace
+
+
+def solve_multi(problems, precision: str = "fp32", iters_per_graph: int = 0, workspace=None, stream=None,
+                info: Optional[dict] = None):
+    """Solve several OMP problems together with the slot scheduler (waits for the
+    result). Returns each problem's Result; `info` receives elapsed_ms and iterations."""
+    lib, arr, o, dev, workspace = _multi_call(problems, precision, iters_per_graph, workspace)
+    ms = ctypes.c_float(0.0)
+    it = ctypes.c_int32(0)
+    o.elapsed_ms = ctypes.pointer(ms)
+    o.iterations = ctypes.pointer(it)
+    with torch.cuda.device(dev):
+        rc = lib.omp_solve_multi(arr, len(problems), ctypes.byref(o), _stream_handle(stream, dev))
+    if rc != OMP_OK:
+        raise OmpError(rc, "omp_solve_multi")
+    if info is not None:
+        info["elapsed_ms"] = float(ms.value)
+        info["iterations"] = int(it.value)
+    return [p.out for p in problems]
+
+
+def tune(problems, precision: str = "fp32", sample: int = 0, iters_per_graph: int = 0, workspace=None,
+         stream=None):
+    """Autotune each problem's schedule (tile configuration, slots, residual lanes) on
+    its first `sample` signals; writes the choices into the Problem objects."""
+    for p in problems:
+        if p.slots == 0:
+            p.slots = min(8192, ((p.Y.shape[0] + 255) // 256) * 256)
+    lib, arr, o, dev, workspace = _multi_call(problems, precision, iters_per_graph, workspace)
+    with torch.cuda.device(dev):
+        rc = lib.omp_tune(arr, len(problems), ctypes.byref(o), int(sample), _stream_handle(stream, dev))
+    if rc != OMP_OK:
+        raise OmpError(rc, "omp_tune")
+    for p, st in zip(problems, arr):
+        p.tile_config, p.slots, p.residual_lanes = int(st.tile_config), int(st.slots), int(st.residual_lanes)
+    return [(p.tile_config, p.slots, p.residual_lanes) for p in problems]
+
+
+PARAM_NAMES = ("W1", "b1", "W2", "b2", "W3", "b3")
+
+
+class MLP:
+    """The support-proposal network on the GPU (weights, BF16 copies and Adam state in
+    one device allocation). `params` maps W1 (n_hidden, n_in), b1, W2 (n_hidden,
+    n_hidden), b2, W3 (n_out, n_hidden), b3 to float32 arrays or tensors (the initial
+    values, drawn by the caller)."""
+
+    def __init__(self, params: dict, device="cuda:0", stream=None):
+        lib = load()
+        self.device = torch.device(device)
+        t = {k: torch.as_tensor(params[k], dtype=torch.float32).to(self.device).contiguous() for k in PARAM_NAMES}
+        n_hidden, n_in = t["W1"].shape
+        n_out = t["W3"].shape[0]
+        self.n_in, self.n_hidden, self.n_out = n_in, n_hidden, n_out
+        nbytes = lib.omp_mlp_size(n_in, n_hidden, n_out)
+        if nbytes == 0:
+            raise ValueError("network sizes must be multiples of 256")
+        self.mem = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.struct = OmpMlpStruct()
+        ptrs = (ctypes.c_void_p * 6)(*[t[k].data_ptr() for k in PARAM_NAMES])
+        with torch.cuda.device(self.device):
+            rc = lib.omp_mlp_init(ctypes.byref(self.struct), n_in, n_hidden, n_out, ptrs, _ptr(self.mem), nbytes,
+                                  _stream_handle(stream, self.device))
+            torch.cuda.current_stream(self.device).synchronize() if stream is None else stream.synchronize()
+        if rc != OMP_OK:
+            raise OmpError(rc, "omp_mlp_init")
+        self._ws = None
+
+    def _workspace(self, M, B):
+        need = load().omp_mlp_workspace_size(ctypes.byref(self.struct), M, B)
+        if need == 0:
+            raise OmpError(OMP_EINVAL, "omp_mlp_workspace_size")
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def export(self, stream=None) -> dict:
+        out = {"W1": torch.empty((self.n_hidden, self.n_in)), "b1": torch.empty(self.n_hidden),
+               "W2": torch.empty((self.n_hidden, self.n_hidden)), "b2": torch.empty(self.n_hidden),
+               "W3": torch.empty((self.n_out, self.n_hidden)), "b3": torch.empty(self.n_out)}
+        out = {k: v.to(self.device) for k, v in out.items()}
+        ptrs = (ctypes.c_void_p * 6)(*[out[k].data_ptr() for k in PARAM_NAMES])
+        with torch.cuda.device(self.device):
+            rc = load().omp_mlp_export(ctypes.byref(self.struct), ptrs, _stream_handle(stream, self.device))
+        if rc != OMP_OK:
+            raise OmpError(rc, "omp_mlp_export")
+        return out
+
+    def features(self, dictionary: Dictionary, Y: torch.Tensor, stream=None) -> torch.Tensor:
+        """f[b, n] = a_n^T y_b / (||a_n|| ||y_b||) as BF16 bits (int16 tensor, shape (B, N))."""
+        _check_matrix(Y, "Y", dictionary.M)
+        B = Y.shape[0]
+        F = torch.empty((B, dictionary.N), dtype=torch.int16, device=self.device)
+        ws = self._workspace(dictionary.M, B)
+        with torch.cuda.device(self.device):
+            rc = load().omp_mlp_features(ctypes.byref(dictionary.struct), _ptr(Y), B, Y.stride(0), _ptr(F),
+                                         ctypes.byref(self.struct), _ptr(ws), ws.numel(),
+                                         _stream_handle(stream, self.device))
+        if rc != OMP_OK:
+            raise OmpError(rc, "omp_mlp_features")
+        return F
+
+    def forward(self, F: torch.Tensor, stream=None) -> torch.Tensor:
+        B = F.shape[0]
+        Z = torch.empty((B, self.n_out), dtype=torch.float32, device=self.device)
+        ws = self._workspace(0, B)
+        with torch.cuda.device(self.device):
+            rc = load().omp_mlp_forward(ctypes.byref(self.struct), _ptr(F.contiguous()), B, _ptr(Z), _ptr(ws),
+                                        ws.numel(), _stream_handle(stream, self.device))
+        if rc != OMP_OK:
+            raise OmpError(rc, "omp_mlp_forward")
+        return Z
+
+    def grad(self, F: torch.Tensor, support: torch.Tensor, rows: Optional[torch.Tensor] = None, stream=None):
+        """(loss tensor [1], dict of FP32 gradients) on one batch (rows `rows` of F and
+        support, default all); the network is unchanged."""
+        S = support.shape[1]
+        B = support.shape[0] if rows is None else rows.shape[0]
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        g = {k: torch.empty(v, dtype=torch.float32, device=self.device) for k, v in
+             (("W1", (self.n_hidden, self.n_in)), ("b1", (self.n_hidden,)), ("W2", (self.n_hidden, self.n_hidden)),
+              ("b2", (self.n_hidden,)), ("W3", (self.n_out, self.n_hidden)), ("b3", (self.n_out,)))}
+        ptrs = (ctypes.c_void_p * 6)(*[g[k].data_ptr() for k in PARAM_NAMES])
+        ws = self._workspace(0, B)
+        with torch.cuda.device(self.device):
+            rc = load().omp_mlp_grad(ctypes.byref(self.struct), _ptr(F.contiguous()), _ptr(support.contiguous()),
+                                     _ptr(rows), B, S, _ptr(loss), ptrs, _ptr(ws), ws.numel(),
+                                     _stream_handle(stream, self.device))
+        if rc != OMP_OK:
+            raise OmpError(rc, "omp_mlp_grad")
+        return loss, g
+
+    def train_step(self, F: torch.Tensor, support: torch.Tensor, lr: float, loss: Optional[torch.Tensor] = None,
+                   rows: Optional[torch.Tensor] = None, stream=None):
+        """One Adam step on rows `rows` (int32 device tensor, default all) of F and support.
+        `loss` (a one-element float32 device tensor or view) receives the batch loss."""
+        S = support.shape[1]
+        B = support.shape[0] if rows is None else rows.shape[0]
+        ws = self._workspace(0, B)
+        with torch.cuda.device(self.device):
+            rc = load().omp_mlp_train_step(ctypes.byref(self.struct), _ptr(F), _ptr(support), _ptr(rows), B, S,
+                                           float(lr), _ptr(loss), _ptr(ws), ws.numel(),
+                                           _stream_handle(stream, self.device))
+        if rc != OMP_OK:
+            raise OmpError(rc, "omp_mlp_train_step")
+        return loss
+
+
+def learned_solve(dictionary: Dictionary, mlp: MLP, Y: torch.Tensor, S: int, eps: float = 0.0,
+                  eps_per_signal: Optional[torch.Tensor] = None, tile_config: int = 0, workspace=None, stream=None):
+    """Proposal + least-squares check, plain OMP for the rejects. Returns (Result with
+    X None, number accepted). Waits for the stream once."""
+    _check_matrix(Y, "Y", dictionary.M)
+    B = Y.shape[0]
+    dev = Y.device
+    lib = load()
+    o = OmpOptsStruct()
+    lib.omp_opts_default(ctypes.byref(o))
+    o.precision = PREC[dictionary.precision]
+    o.tile_config = int(tile_config)
+    need = lib.omp_learned_workspace_size(ctypes.byref(dictionary.struct), ctypes.byref(mlp.struct), B, int(S),
+                                          ctypes.byref(o))
+    if need == 0:
+        raise OmpError(OMP_EINVAL, "omp_learned_workspace_size")
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+    out = Result(None, torch.empty((B, S), dtype=torch.int32, device=dev),
+                 torch.empty((B, S), dtype=torch.float32, device=dev), torch.empty(B, dtype=torch.int32, device=dev),
+                 torch.empty(B, dtype=torch.float32, device=dev))
+    acc = ctypes.c_int64(0)
+    if eps_per_signal is not None and (eps_per_signal.dtype != torch.float32 or eps_per_signal.shape != (B,)):
+        raise TypeError("eps_per_signal must be float32 of shape (B,)")
+    with torch.cuda.device(dev):
+        rc = lib.omp_learned_solve(ctypes.byref(dictionary.struct), ctypes.byref(mlp.struct), _ptr(Y), B,
+                                   Y.stride(0), int(S), float(eps), _ptr(eps_per_signal), _ptr(out.support),
+                                   _ptr(out.coef), _ptr(out.status), _ptr(out.rnorm), ctypes.byref(acc),
+                                   ctypes.byref(o), _ptr(workspace), workspace.numel(),
+                                   _stream_handle(stream, dev))
+    if rc != OMP_OK:
+        raise OmpError(rc, "omp_learned_solve")
+    return out, int(acc.value)

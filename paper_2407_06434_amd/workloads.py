@@ -186,6 +186,20 @@ def custom(M: int, N: int, B: int, S: int, seed: int = 7, values: str = "pm",
                     true_support=sup, true_values=vals, sigma=sig)
 
 
+def mlp_init_params(n_in: int = 1024, n_hidden: int = 1024, n_out: int = 1024, seed: int = 3005) -> dict:
+    """Initial weights of the support-proposal network, drawn here and passed to the
+    library: He-uniform U(-sqrt(6/fan_in), sqrt(6/fan_in)) for the ReLU layers, the
+    output layer scaled by 1/4, zero biases. float32, W stored (out, in)."""
+    g = _rng(seed)
+    p = {}
+    for name, (o, i), scale in (("1", (n_hidden, n_in), 1.0), ("2", (n_hidden, n_hidden), 1.0),
+                                ("3", (n_out, n_hidden), 0.25)):
+        lim = np.sqrt(6.0 / i) * scale
+        p["W" + name] = g.uniform(-lim, lim, size=(o, i)).astype(np.float32)
+        p["b" + name] = np.zeros(o, np.float32)
+    return p
+
+
 WORKLOADS = {
     "plain_64x256": plain_64x256,
     "batched_256x1024": batched_256x1024,

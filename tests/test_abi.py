@@ -154,3 +154,174 @@ def test_empty_batch_is_a_no_op(lib):
     o = _opts()
     rc = lib.omp_solve(FAKE, 64, 256, 64, None, 0, 64, 8, 0.0, None, None, ctypes.byref(o), None)
     assert rc == omp.OMP_OK
+
+
+def _fake_dict(M=128, N=512, prec=0):
+    from paper_2407_06434_amd import omp
+    d = omp.OmpDictStruct()
+    d.magic = 0x4F4D5044
+    d.precision = prec
+    d.M, d.N = M, N
+    d.A = FAKE
+    d.mem = FAKE
+    return d
+
+
+def _problem(d, B=1000, S=32, slots=0):
+    from paper_2407_06434_amd import omp
+    p = omp.OmpProblemStruct()
+    p.dict = ctypes.pointer(d)
+    p.Y = FAKE.value
+    p.B, p.ldy, p.S = B, d.M, S
+    p.support_out = FAKE.value
+    p.slots = slots
+    return p
+
+
+def _mopts(ws=1 << 40, prec=0):
+    from paper_2407_06434_amd import omp
+    o = omp.OmpMultiOptsStruct()
+    o.precision = prec
+    o.workspace = FAKE.value
+    o.workspace_bytes = ws
+    return o
+
+
+def test_multi_struct_layout():
+    from paper_2407_06434_amd import omp
+    assert ctypes.sizeof(omp.OmpProblemStruct) == 8 * 4 + 8 + 8 * 7 + 16
+    assert ctypes.sizeof(omp.OmpMultiOptsStruct) == 8 + 8 * 4
+
+
+def test_multi_workspace_size(lib):
+    d0, d1 = _fake_dict(128, 512), _fake_dict(512, 2048)
+    o = _mopts()
+    one = (type(_problem(d0)) * 1)(_problem(d0, slots=256))
+    two = (type(_problem(d0)) * 2)(_problem(d0, slots=256), _problem(d1, slots=1024))
+    big = (type(_problem(d0)) * 2)(_problem(d0, slots=512), _problem(d1, slots=1024))
+    s1 = lib.omp_multi_workspace_size(one, 1, ctypes.byref(o))
+    s2 = lib.omp_multi_workspace_size(two, 2, ctypes.byref(o))
+    s3 = lib.omp_multi_workspace_size(big, 2, ctypes.byref(o))
+    assert 0 < s1 < s2 < s3
+    assert lib.omp_multi_workspace_size(two, 0, ctypes.byref(o)) == 0
+    assert lib.omp_multi_workspace_size(two, 9, ctypes.byref(o)) == 0
+
+
+@pytest.mark.parametrize("case", ["nprob0", "nprob9", "badprec", "dict_prec", "dict_magic", "S0", "S_gt_M",
+                                  "nan_eps", "ldy", "nullY", "nullsup", "cfg", "lanes", "slots_neg", "chunk"])
+def test_multi_rejects_invalid(lib, case):
+    from paper_2407_06434_amd import omp
+    d = _fake_dict()
+    p = _problem(d)
+    o = _mopts()
+    n = 1
+    if case == "nprob0": n = 0
+    if case == "nprob9": n = 9
+    if case == "badprec": o.precision = 5
+    if case == "dict_prec": d.precision = 1
+    if case == "dict_magic": d.magic = 1
+    if case == "S0": p.S = 0
+    if case == "S_gt_M": p.S = 129
+    if case == "nan_eps": p.eps = math.nan
+    if case == "ldy": p.ldy = 127
+    if case == "nullY": p.Y = None
+    if case == "nullsup": p.support_out = None
+    if case == "cfg": p.tile_config = 5
+    if case == "lanes": p.residual_lanes = 3
+    if case == "slots_neg": p.slots = -256
+    if case == "chunk": o.iters_per_graph = 65
+    arr = (type(p) * 9)(*([p] * 9))
+    assert lib.omp_solve_multi(arr, n, ctypes.byref(o), None) == omp.OMP_EINVAL, case
+    assert lib.omp_tune(arr, n, ctypes.byref(o), 0, None) == omp.OMP_EINVAL, case
+
+
+def test_multi_rejects_small_workspace(lib):
+    from paper_2407_06434_amd import omp
+    d = _fake_dict()
+    arr = (type(_problem(d)) * 1)(_problem(d))
+    o = _mopts(ws=4096)
+    assert lib.omp_solve_multi(arr, 1, ctypes.byref(o), None) == omp.OMP_EWORKSPACE
+    o = _mopts()
+    o.workspace = (1 << 20) + 64
+    assert lib.omp_solve_multi(arr, 1, ctypes.byref(o), None) == omp.OMP_EWORKSPACE
+    p = _problem(d, S=300)
+    arr = (type(p) * 1)(p)
+    d.M, d.N = 512, 1024
+    p.ldy = 512
+    assert lib.omp_solve_multi(arr, 1, ctypes.byref(_mopts()), None) == omp.OMP_ENOTSUPP
+
+
+def test_multi_all_empty_is_a_no_op(lib):
+    from paper_2407_06434_amd import omp
+    d = _fake_dict()
+    p = _problem(d, B=0)
+    p.Y = None
+    p.support_out = None
+    arr = (type(p) * 1)(p)
+    assert lib.omp_solve_multi(arr, 1, ctypes.byref(_mopts()), None) == omp.OMP_OK
+
+
+def test_mlp_struct_and_sizes(lib):
+    from paper_2407_06434_amd import omp
+    assert ctypes.sizeof(omp.OmpMlpStruct) == 4 * 4 + 8 * 3
+    s = lib.omp_mlp_size(1024, 1024, 1024)
+    assert s >= 3 * 1024 * 1024 * (4 * 3 + 2 * 2)
+    assert lib.omp_mlp_size(1000, 1024, 1024) == 0
+    assert lib.omp_mlp_size(1024, 0, 1024) == 0
+    assert lib.omp_mlp_size(512, 256, 512) < s
+
+
+def _fake_mlp(n=1024, h=512):
+    from paper_2407_06434_amd import omp
+    m = omp.OmpMlpStruct()
+    m.magic = 0x4F4D4C50
+    m.n_in, m.n_hidden, m.n_out = n, h, n
+    m.mem = FAKE.value
+    return m
+
+
+def test_mlp_rejects_invalid(lib):
+    from paper_2407_06434_amd import omp
+    m = omp.OmpMlpStruct()
+    ptrs = (ctypes.c_void_p * 6)(*([FAKE.value] * 6))
+    assert lib.omp_mlp_init(ctypes.byref(m), 1024, 512, 1024, None, FAKE, 1 << 40, None) == omp.OMP_EINVAL
+    assert lib.omp_mlp_init(ctypes.byref(m), 1000, 512, 1024, ptrs, FAKE, 1 << 40, None) == omp.OMP_EINVAL
+    assert lib.omp_mlp_init(ctypes.byref(m), 1024, 512, 1024, ptrs, FAKE, 1024, None) == omp.OMP_EWORKSPACE
+    bad = (ctypes.c_void_p * 6)(*([FAKE.value] * 5 + [None]))
+    assert lib.omp_mlp_init(ctypes.byref(m), 1024, 512, 1024, bad, FAKE, 1 << 40, None) == omp.OMP_EINVAL
+    fm = _fake_mlp()
+    assert lib.omp_mlp_workspace_size(ctypes.byref(fm), 256, 100) > 0
+    assert lib.omp_mlp_workspace_size(ctypes.byref(m), 256, 100) == 0  # not initialised
+    # gradients need at least one signal and S within the output size
+    assert lib.omp_mlp_grad(ctypes.byref(fm), FAKE, FAKE, None, 0, 32, None, None, FAKE, 1 << 40,
+                            None) == omp.OMP_EINVAL
+    assert lib.omp_mlp_train_step(ctypes.byref(fm), FAKE, FAKE, None, 10, 32, -1.0, None, FAKE, 1 << 40,
+                                  None) == omp.OMP_EINVAL
+    assert lib.omp_mlp_train_step(ctypes.byref(fm), FAKE, FAKE, None, 10, 1025, 1e-3, None, FAKE, 1 << 40,
+                                  None) == omp.OMP_EINVAL
+    assert lib.omp_mlp_forward(ctypes.byref(fm), FAKE, 10, FAKE, FAKE, 16, None) == omp.OMP_EWORKSPACE
+
+
+def test_learned_solve_rejects_invalid(lib):
+    from paper_2407_06434_amd import omp
+    fm = _fake_mlp()
+    d = _fake_dict(256, 1024, prec=1)
+    o = _opts(prec=1)
+    assert lib.omp_learned_workspace_size(ctypes.byref(d), ctypes.byref(fm), 100, 32, ctypes.byref(o)) > 0
+    d0 = _fake_dict(256, 1024, prec=0)
+    assert lib.omp_learned_workspace_size(ctypes.byref(d0), ctypes.byref(fm), 100, 32, ctypes.byref(o)) == 0
+    d2 = _fake_dict(256, 2048, prec=1)
+    assert lib.omp_learned_workspace_size(ctypes.byref(d2), ctypes.byref(fm), 100, 32, ctypes.byref(o)) == 0
+    acc = ctypes.c_int64(0)
+    args = [FAKE, 100, 256, 32, 0.0, None, FAKE, FAKE, FAKE, FAKE, ctypes.byref(acc), ctypes.byref(o), FAKE,
+            1 << 40, None]
+    a = list(args)
+    a[3] = 65
+    assert lib.omp_learned_solve(ctypes.byref(d), ctypes.byref(fm), *a) == omp.OMP_ENOTSUPP
+    a = list(args)
+    a[4] = math.nan
+    assert lib.omp_learned_solve(ctypes.byref(d), ctypes.byref(fm), *a) == omp.OMP_EINVAL
+    a = list(args)
+    a[13] = 1024
+    assert lib.omp_learned_solve(ctypes.byref(d), ctypes.byref(fm), *a) == omp.OMP_EWORKSPACE
+    assert lib.omp_learned_solve(ctypes.byref(d0), ctypes.byref(fm), *args) == omp.OMP_EINVAL
