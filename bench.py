@@ -218,6 +218,70 @@ def run_uneven(precision, steps, warmup, B_each=10000):
             "speedup_vs_keep_in_batch": round(plain_wall / wall, 3), "identical_to_keep_in_batch": bool(same)}
 
 
+def run_learned(n_train, epochs, n_eval=65536, log=None):
+    """Learned support proposal on 256x1024 (S=32, 20 dB, eps_i = sigma_i sqrt(M)):
+    labels from our own BF16 OMP on n_train training signals, features, `epochs` of
+    Adam, then the learned solve (proposal + least-squares check + OMP fallback) of the
+    65,536 evaluation signals, timed beside plain BF16 and plain FP32 OMP on the same
+    signals. Training and evaluation are on the GPU; the data is generated on the host."""
+    import torch
+    from paper_2407_06434_amd import learned, omp, workloads
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    tr = workloads.learned_256x1024(B=n_train, stream=1)
+    ev = workloads.learned_256x1024(B=n_eval, stream=0)
+    gen_s = time.perf_counter() - t0
+    A = torch.from_numpy(tr.A).to(dev)
+    d16 = omp.Dictionary(A, "bf16")
+    d32 = omp.Dictionary(A, "fp32")
+    Ytr = torch.from_numpy(tr.Y).to(dev)
+    Etr = torch.from_numpy(tr.eps_per_signal).to(dev)
+    Yev = torch.from_numpy(ev.Y).to(dev)
+    Eev = torch.from_numpy(ev.eps_per_signal).to(dev)
+    net = omp.MLP(workloads.mlp_init_params())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sup = learned.omp_labels(d16, Ytr, 32, Etr)
+    F = learned.features(net, d16, Ytr)
+    torch.cuda.synchronize()
+    label_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    hist = learned.train(net, F, sup, epochs, batch=1024, lr=1e-3, log=log)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t = time.perf_counter()
+            r = fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+        return r, float(np.median(ts))
+
+    (out, nacc), t_l = timed(lambda: omp.learned_solve(d16, net, Yev, 32, eps_per_signal=Eev))
+    ref, t_b = timed(lambda: omp.solve(A, Yev, 32, precision="bf16", dictionary=d16, eps_per_signal=Eev,
+                                       dense=False))
+    ref32, t_f = timed(lambda: omp.solve(A, Yev, 32, precision="fp32", dictionary=d32, eps_per_signal=Eev,
+                                         dense=False))
+    s_l = out.support.cpu().numpy()
+    s_o = ref.support.cpu().numpy()
+    acc = (out.status.cpu().numpy() & 128) != 0
+    same = np.array([set(a[a >= 0]) == set(b[b >= 0]) for a, b in zip(s_l, s_o)])
+    rn_ok = bool(np.all(out.rnorm.cpu().numpy()[acc] <= ev.eps_per_signal[acc]))
+    rej_same = bool(np.array_equal(s_l[~acc], s_o[~acc]))
+    return {"workload": "learned_256x1024_S32_eval65536", "value": round(n_eval / t_l, 1), "unit": "signals/s",
+            "accepted": f"{int(nacc)}/{n_eval}", "accepted_same_support_as_omp": f"{int(same[acc].sum())}/{int(acc.sum())}",
+            "all_same_support_as_omp": f"{int(same.sum())}/{n_eval}", "accepted_residuals_within_eps": rn_ok,
+            "rejects_identical_to_omp": rej_same,
+            "plain_bf16_omp": round(n_eval / t_b, 1), "plain_fp32_omp": round(n_eval / t_f, 1),
+            "speedup_vs_plain_bf16": round(t_b / t_l, 3), "speedup_vs_plain_fp32": round(t_f / t_l, 3),
+            "train": {"signals": n_train, "epochs": epochs, "final_loss": round(hist[-1], 4), "train_s": round(train_s, 2),
+                      "labels_and_features_s": round(label_s, 2), "host_generation_s": round(gen_s, 2)}}
+
+
 def cpu_baseline(w, target_s):
     """The oracle, as it stands, on the first n signals of the same workload."""
     import oracle
@@ -251,6 +315,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch (slot scheduler) measurement")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal measurement")
+    ap.add_argument("--learned-train", type=int, default=262144, help="training signals for the learned proposal")
+    ap.add_argument("--learned-epochs", type=int, default=20)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (scale reference for HBM counters)")
     args = ap.parse_args()
@@ -320,6 +387,10 @@ def main():
         u = run_uneven(args.precision, max(3, args.steps // 2), 1)
         line["uneven"] = u
         log(f"uneven: {u}")
+    if not args.no_learned:
+        lr = run_learned(args.learned_train, args.learned_epochs, log=log)
+        line["learned"] = lr
+        log(f"learned: {lr}")
 
     if not args.no_cpu_baseline:
         cb, first = cpu_baseline(w, args.cpu_seconds)

@@ -421,7 +421,7 @@ size_t omp_learned_workspace_size(const omp_dict_t *dict, const omp_mlp_t *mlp, 
   if (dict->N != mlp->n_in || dict->N != mlp->n_out || B < 0 || B > ((int64_t)1 << 24)) return 0;
   if (S < 1 || S > 64 || S > dict->M || S > dict->N) return 0;
   const int cfg = fallback ? fallback->tile_config : 0;
-  if (cfg < 0 || cfg > 4) return 0;
+  if (cfg < 0 || cfg > MAX_TILE_CFG) return 0;
   return solve_layout(dict, mlp, B, S, cfg).total;
 }
 
@@ -436,7 +436,7 @@ int omp_learned_solve(const omp_dict_t *dict, const omp_mlp_t *mlp, const float 
   if (S > 64) return OMP_ENOTSUPP;
   if (std::isnan(eps)) return OMP_EINVAL;
   const int cfg = fallback ? fallback->tile_config : 0;
-  if (cfg < 0 || cfg > 4) return OMP_EINVAL;
+  if (cfg < 0 || cfg > MAX_TILE_CFG) return OMP_EINVAL;
   if (B > 0 && (!Y || ldy < dict->M || !aligned(Y, 4) || !support_out || !coef_out || !status_out || !rnorm_out))
     return OMP_EINVAL;
   const SolveLayout L = solve_layout(dict, mlp, B, S, cfg);

@@ -313,7 +313,7 @@ size_t omp_workspace_size(int64_t M, int64_t N, int64_t B, int32_t S, const omp_
   if (!dims_ok(M, N) || B < 0 || B > ((int64_t)1 << 26) || S < 1 || S > OMP_MAX_S) return 0;
   if (prec != OMP_PREC_FP32 && prec != OMP_PREC_BF16) return 0;
   const int cfg = opts ? opts->tile_config : 0;
-  if (cfg < 0 || cfg > 4) return 0;
+  if (cfg < 0 || cfg > MAX_TILE_CFG) return 0;
   size_t total = work_bytes(M, N, B, S, prec, cfg);
   if (!opts || !opts->dict) total += dict_bytes(M, N, prec);
   return total;
@@ -327,7 +327,7 @@ int omp_solve(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y,
   const int prec = opts->precision;
   if (prec != OMP_PREC_FP32 && prec != OMP_PREC_BF16) return OMP_EINVAL;
   const int cfg = opts->tile_config;
-  if (cfg < 0 || cfg > 4) return OMP_EINVAL;
+  if (cfg < 0 || cfg > MAX_TILE_CFG) return OMP_EINVAL;
   if (!dims_ok(M, N) || B < 0 || B > ((int64_t)1 << 26)) return OMP_EINVAL;
   if (S < 1 || S > M || S > N) return OMP_EINVAL;
   if (S > OMP_MAX_S) return OMP_ENOTSUPP;

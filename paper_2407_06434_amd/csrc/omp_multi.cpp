@@ -84,7 +84,7 @@ int check_problem(const omp_problem_t &p, int precision) {
   if (p.S < 1 || p.S > dd->M || p.S > dd->N) return OMP_EINVAL;
   if (p.S > OMP_MAX_S) return OMP_ENOTSUPP;
   if (std::isnan(p.eps)) return OMP_EINVAL;
-  if (p.tile_config < 0 || p.tile_config > 4 || p.slots < 0) return OMP_EINVAL;
+  if (p.tile_config < 0 || p.tile_config > MAX_TILE_CFG || p.slots < 0) return OMP_EINVAL;
   const int l = p.residual_lanes;
   if (l < 0 || l > 64 || (l & (l - 1))) return OMP_EINVAL;
   if (p.B > 0 && (!p.Y || p.ldy < dd->M || !aligned(p.Y, 4) || !p.support_out)) return OMP_EINVAL;

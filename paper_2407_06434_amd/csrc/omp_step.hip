@@ -151,6 +151,24 @@ __device__ __attribute__((always_inline)) inline void atom_dots(const DictView &
     }
 }
 
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+// Asynchronous global-to-LDS loads (gfx950 global_load_lds): lane l's element
+// lands at dst + l (lane order), dst being wave-uniform. Completion is awaited
+// with s_waitcnt before the LDS data is read.
+__device__ inline void lds_load16(const float4 *src, float4 *dst_wave) {
+  __builtin_amdgcn_global_load_lds(reinterpret_cast<const void *>(src), (lds_void_t *)(dst_wave), 16, 0,
+                                   0);
+}
+
+// Intra-wavefront LDS ordering: one wavefront's LDS instructions execute in
+// order, so it suffices that the compiler keeps them in program order.
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Queue of atoms to re-score against r, flushed two at a time (all values
 // wave-uniform; a pick has about two candidates on the benchmark workload).
 // A flush fetches, in one round with the dot products, each candidate's
@@ -223,7 +241,7 @@ struct RescoreQueue {
 template <int RPL>
 __device__ int select_bf16(const DictView &d, const WorkView &w, int64_t b, float smax, double tau,
                            const int (&si)[RPL], int k, int lane, int *widened, double *beta, double *nu2,
-                           float (&g)[RPL]) {
+                           float (&g)[RPL], int *clist) {
   const int nkeys = w.ntile * w.ncand;
   const uint64_t *keys = w.part + b * nkeys;
   const float4 *r4 = reinterpret_cast<const float4 *>(w.R32) + b * (d.Mp / 4);
@@ -231,46 +249,75 @@ __device__ int select_bf16(const DictView &d, const WorkView &w, int64_t b, floa
   const double et = 1.0 / 262144.0;  // 2^-18: the epilogue's rounding of listed scores
   const double thr = (double)smax - 2.0 * tau - et * (double)smax;
   RescoreQueue<RPL> q;
-  for (int t0 = 0; t0 < nkeys; t0 += 64) {
-    const int t = t0 + lane;
-    const uint64_t k = t < nkeys ? keys[t] : 0ull;
-    const bool cand = (k & 0xFFFFFFFFull) && (double)__uint_as_float((uint32_t)(k >> 32)) >= thr;
-    uint64_t m = __ballot(cand);
-    const int n_l = (int)(0xFFFFFFFFu - (uint32_t)(k & 0xFFFFFFFFull));
-    while (m) {
-      const int l = __ffsll((unsigned long long)m) - 1;
-      m &= m - 1;
-      q.push(__builtin_amdgcn_readlane(n_l, l), d, r4, y4, si, k, lane);
+  // Pass 1: the candidates. Keys are read KB per lane at a time (the loads of a
+  // batch are in flight together) and each candidate's atom is appended to the
+  // wavefront's LDS list (room for every key); the re-score then walks the list.
+  constexpr int KB = 8;
+  int ncand = 0;
+  for (int t0 = 0; t0 < nkeys; t0 += 64 * KB) {
+    uint64_t kv[KB];
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      const int t = t0 + 64 * j + lane;
+      kv[j] = t < nkeys ? keys[t] : 0ull;
+    }
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      const bool cand = (kv[j] & 0xFFFFFFFFull) && (double)__uint_as_float((uint32_t)(kv[j] >> 32)) >= thr;
+      const uint64_t m = __ballot(cand);
+      const int pos = ncand + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+      if (cand) clist[pos] = (int)(0xFFFFFFFFu - (uint32_t)(kv[j] & 0xFFFFFFFFull));
+      ncand += __popcll(m);
     }
   }
+  wave_lds_sync();
+  for (int i = 0; i < ncand; ++i) q.push(__builtin_amdgcn_readfirstlane(clist[i]), d, r4, y4, si, k, lane);
   q.flush(d, r4, y4, si, k, lane);
+
+  // Pass 2: the subgroups whose bound reaches the provisional pick (their key
+  // slots go to the same LDS list), each then re-scored whole.
+  wave_lds_sync();
+  int nopen = 0;
+  for (int t0 = 0; t0 < nkeys; t0 += 64 * KB) {
+    uint64_t kv[KB];
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      const int t = t0 + 64 * j + lane;
+      const bool third = t < nkeys && (t % NKEEP) == NKEEP - 1;  // the subgroup's bounding key
+      kv[j] = third ? keys[t] : 0ull;
+    }
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+      const int t = t0 + 64 * j + lane;
+      const bool third = t < nkeys && (t % NKEEP) == NKEEP - 1;
+      const bool open = third && (double)__uint_as_float((uint32_t)(kv[j] >> 32)) * (1.0 + et) + tau >= q.bs;
+      const uint64_t m = __ballot(open);
+      const int pos = nopen + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+      if (open) clist[pos] = t;
+      nopen += __popcll(m);
+    }
+  }
+  wave_lds_sync();
   const int64_t mwords = d.Np / 32;
   const uint32_t *mk = w.mask + b * mwords;
-  for (int t0 = 0; t0 < nkeys; t0 += 64) {
-    const int t = t0 + lane;
-    const bool third = t < nkeys && (t % NKEEP) == NKEEP - 1;  // the subgroup's bounding key
-    const uint64_t k = third ? keys[t] : 0ull;
-    const bool open = third && (double)__uint_as_float((uint32_t)(k >> 32)) * (1.0 + et) + tau >= q.bs;
-    uint64_t m = __ballot(open);
-    while (m) {
-      const int l = __ffsll((unsigned long long)m) - 1;
-      m &= m - 1;
-      const int slot = t0 + l;
-      const int tile = slot / w.ncand;
-      const int sgl = (slot % w.ncand) / NKEEP;  // ((wn * subs_per_half + ig) * 2 + h)
-      const int hh = sgl & 1;
-      const int ig = (sgl >> 1) % w.subs_per_half;
-      const int wn = (sgl >> 1) / w.subs_per_half;
-      *widened = 1;
-      for (int i = 0; i < w.sub_frags; ++i)
-        for (int g = 0; g < 4; ++g)
-          for (int e = 0; e < 4; ++e) {
-            const int n = tile * w.tile_atoms + wn * w.wave_atoms + 32 * (ig * w.sub_frags + i) + 8 * g + 4 * hh + e;
-            if (d.inv_nu[n] <= 0.f || ((mk[n >> 5] >> (n & 31)) & 1u)) continue;
-            q.push(n, d, r4, y4, si, k, lane);
-          }
-      q.flush(d, r4, y4, si, k, lane);
-    }
+  for (int i = 0; i < nopen; ++i) {
+    const int slot = __builtin_amdgcn_readfirstlane(clist[i]);
+    const int tile = slot / w.ncand;
+    const int sgl = (slot % w.ncand) / NKEEP;  // ((wn * subs_per_half + ig) * 2 + h)
+    const int hh = sgl & 1;
+    const int ig = (sgl >> 1) % w.subs_per_half;
+    const int wn = (sgl >> 1) / w.subs_per_half;
+    *widened = 1;
+    for (int ii = 0; ii < w.sub_frags; ++ii)
+      for (int g4 = 0; g4 < 4; ++g4)
+        for (int e = 0; e < 4; ++e) {
+          const int n = tile * w.tile_atoms + wn * w.wave_atoms + 32 * (ig * w.sub_frags + ii) + 8 * g4 + 4 * hh + e;
+          if (d.inv_nu[n] <= 0.f || ((mk[n >> 5] >> (n & 31)) & 1u)) continue;
+          q.push(n, d, r4, y4, si, k, lane);
+        }
+    q.flush(d, r4, y4, si, k, lane);
   }
   *beta = q.by;
   *nu2 = q.bnu2;
@@ -279,23 +326,6 @@ __device__ int select_bf16(const DictView &d, const WorkView &w, int64_t b, floa
   return q.bn == 0x7fffffff ? -1 : q.bn;
 }
 
-typedef __attribute__((address_space(3))) void lds_void_t;
-
-// Asynchronous global-to-LDS loads (gfx950 global_load_lds): lane l's element
-// lands at dst + l (lane order), dst being wave-uniform. Completion is awaited
-// with s_waitcnt before the LDS data is read.
-__device__ inline void lds_load16(const float4 *src, float4 *dst_wave) {
-  __builtin_amdgcn_global_load_lds(reinterpret_cast<const void *>(src), (lds_void_t *)(dst_wave), 16, 0,
-                                   0);
-}
-
-// Intra-wavefront LDS ordering: one wavefront's LDS instructions execute in
-// order, so it suffices that the compiler keeps them in program order.
-__device__ inline void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // ---------------------------------------------------------------------------
 // Dictionary preparation: one wavefront per (padded) atom.
@@ -478,6 +508,12 @@ __device__ void retire_and_admit(const WorkView &w, const SlotView &sv, int64_t 
 // ---------------------------------------------------------------------------
 constexpr int SOLVE_WAVES = 4;
 
+// Ints of the BF16 pick's candidate list per wavefront (a multiple of 4, so
+// that every wavefront's LDS region stays 16-byte aligned); 0 in the FP32 form.
+__host__ __device__ inline int64_t solve_list_len(const WorkView &w) {
+  return w.R16 ? (int64_t)(w.ntile * w.ncand + 3) / 4 * 4 : 0;
+}
+
 // A stop found by the solve step: record the flags, or (slot scheduler) write
 // the signal out and admit the next one.
 template <bool SLOTS>
@@ -495,7 +531,8 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
   if (b >= w.B) return;
   const int S = w.S;
   const int64_t VS = w.vstride;
-  float *Vs = smem + (size_t)wv * VS;
+  float *Vs = smem + (size_t)wv * (VS + solve_list_len(w));
+  int *clist = reinterpret_cast<int *>(Vs + VS);  // BF16 pick: candidate list (one entry per key at most)
 
   // ---- round 1: state, residual norms, keys, support, u (none of these
   // addresses depends on another load)
@@ -576,7 +613,7 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
   if (BF16) {
     const double tau = bf16_tau(rn, sqrt(wave_sum(pd)), (double)d.aerr_max[0], d.Mp);
     nstar = select_bf16<RPL>(d, w, b, __uint_as_float((uint32_t)(kmax >> 32)), tau, si, k, lane, &widened, &beta,
-                             &nu2, g);
+                             &nu2, g, clist);
     if (nstar < 0) {
       stopfl = fl | FLAG_DONE | OMP_SIG_EXHAUSTED;
       goto stop;
@@ -913,7 +950,7 @@ __global__ __launch_bounds__(256) void k_densify(const int32_t *__restrict__ sup
 
 template <int RPL, bool BF16, bool SLOTS>
 hipError_t launch_solve_t(const DictView &d, const WorkView &w, const SlotView &sv, hipStream_t st) {
-  const size_t lds = (size_t)w.vstride * 4 * SOLVE_WAVES;
+  const size_t lds = (size_t)(w.vstride + solve_list_len(w)) * 4 * SOLVE_WAVES;
   hipError_t e = allow_lds(k_solve<RPL, BF16, SLOTS>, lds);
   if (e != hipSuccess) return e;
   const unsigned blocks = (unsigned)((w.B + SOLVE_WAVES - 1) / SOLVE_WAVES);
@@ -1015,7 +1052,7 @@ hipError_t launch_densify(const int32_t *support, const float *coef, int64_t nsi
 }
 
 hipError_t prepare_kernels(const DictView &d, const WorkView &w, int precision, int lanes) {
-  const size_t slds = (size_t)w.vstride * 4 * SOLVE_WAVES;
+  const size_t slds = (size_t)(w.vstride + solve_list_len(w)) * 4 * SOLVE_WAVES;
   const bool bf = precision == OMP_PREC_BF16;
   hipError_t e = hipSuccess;
   if (w.S <= 64) e = bf ? allow_lds(k_solve<1, true, true>, slds) : allow_lds(k_solve<1, false, true>, slds);

@@ -106,13 +106,14 @@ def test_forward_and_gradients_match_oracle():
         assert mx <= 1e-2 and fr <= 2e-3, k
 
 
-def test_adam_step_matches_oracle():
-    """Two Adam steps. Where the oracle's gradients are well above the GPU-oracle
-    gradient difference (>= 1e-2 of the largest entry in both steps) the weight
-    displacement agrees within 1e-2 lr; everywhere it respects Adam's step bound
-    (|step| <= lr for the first two steps with beta1 = 0.9, beta2 = 0.999: the
-    bias-corrected ratio m/sqrt(v) is at most 1 in magnitude when the gradient
-    keeps its sign, and at most ~1.3 otherwise)."""
+def test_adam_steps_closed_form():
+    """Adam's moments and bias correction: a step with learning rate 0 (moments only)
+    followed by a step with lr on the same batch at the same weights sees the same
+    gradient g twice, so the bias-corrected ratio m/sqrt(v) is exactly g/|g|: every
+    weight moves by lr g/(|g| + 1e-8). Checked against the oracle's gradient where it is
+    firm (|g| >= 1e-2 max |g|, far above the GPU-oracle gradient difference); elsewhere
+    the displacement is bounded by lr. A wrong bias correction at t = 2 would move the
+    firm weights by 1.9 lr or 0.1 lr."""
     torch = _torch()
     from oracle import learned_oracle as lo
     from paper_2407_06434_amd import omp
@@ -122,28 +123,23 @@ def test_adam_step_matches_oracle():
     dev = torch.device("cuda:0")
     Fb = _bf16_bits(F).to(dev)
     sup = torch.from_numpy(w.true_support.astype(np.int32)).to(dev)
-    print("case adam two steps", flush=True)
+    print("case adam lr 0 then lr", flush=True)
     lr = 1e-3
+    net.train_step(Fb, sup, 0.0)
+    net.train_step(Fb, sup, lr)
+    assert net.struct.step == 2
     pz = {k: v.astype(np.float64) for k, v in p.items()}
-    state = {}
-    T = lo.multi_hot(w.true_support, 1024)
-    grads = []
-    for _ in range(2):
-        net.train_step(Fb, sup, lr)
-        _, gr = lo.backward(pz, F, T, lo.bf16_round)
-        grads.append(gr)
-        pz = lo.adam_step(pz, gr, state, lr)
+    _, g = lo.backward(pz, F, lo.multi_hot(w.true_support, 1024), lo.bf16_round)
     got = {k: v.cpu().numpy().astype(np.float64) for k, v in net.export().items()}
     for k in pz:
-        dg = got[k] - p[k]
-        dr = pz[k] - p[k]
-        firm = np.ones(dg.shape, bool)
-        for gr in grads:
-            firm &= np.abs(gr[k]) >= 1e-2 * np.abs(gr[k]).max()
-        err = np.abs(dg - dr)[firm].max() if firm.any() else 0.0
-        print(k, "firm entries", int(firm.sum()), "max displacement error", err / lr)
-        assert err <= 1e-2 * lr, k
-        assert np.abs(dg).max() <= 2 * 1.3 * lr, k
+        disp = got[k] - p[k].astype(np.float64)
+        firm = np.abs(g[k]) >= 1e-2 * np.abs(g[k]).max()
+        want = -lr * np.sign(g[k])
+        err = np.abs(disp - want)[firm].max()
+        print(k, "firm", int(firm.sum()), "of", firm.size, "max error / lr", err / lr)
+        # FP32 weights of magnitude <= 0.08 carry 2^-24 * 0.08 of rounding per update
+        assert err <= 1e-3 * lr, k
+        assert np.abs(disp).max() <= lr * (1 + 1e-3), k
 
 
 def test_ls_check_and_fallback_against_oracle_and_plain_omp(orc):
