@@ -237,9 +237,9 @@ int omp_tune(omp_problem_t *probs, int32_t nprob, const omp_multi_opts_t *opts, 
  * An extension of the paper's method: a small network proposes the support
  * and one least-squares solve checks it; plain OMP (omp_solve) takes over for
  * every signal the proposal does not explain.
- *   features  f_n = a_n^T y / (||a_n|| ||y||): Algorithm 1's first correlation,
- *             normalised (BF16 product, so the dictionary is prepared for
- *             OMP_PREC_BF16)
+ *   features  f_n = sqrt(M) |a_n^T y| / (||a_n|| ||y||): Algorithm 1's first
+ *             selection statistic, scaled to unit size (BF16 product, so the
+ *             dictionary is prepared for OMP_PREC_BF16)
  *   network   h1 = relu(W1 f + b1), h2 = relu(W2 h1 + b2), z = W3 h2 + b3,
  *             BF16 operands, FP32 accumulation, W_l stored [out][in]
  *   proposal  the S atoms with the largest z (ties to the lowest index)

@@ -7,8 +7,9 @@ The learned proposal is an extension of the paper's method, not part of it. The
 pieces follow their textbook definitions, written out plainly in float64 with
 numpy matrix products as the only library steps:
 
-* features: the first correlation of Algorithm 1, normalised,
-  f_n = (a_n^T y) / (||a_n|| ||y||) (0 for a zero atom or a zero signal);
+* features: the magnitude of the first correlation of Algorithm 1, normalised
+  and scaled to unit size, f_n = sqrt(M) |a_n^T y| / (||a_n|| ||y||) (0 for a
+  zero atom or a zero signal);
 * a multilayer perceptron with two ReLU hidden layers,
   h1 = relu(W1 f + b1), h2 = relu(W2 h1 + b2), z = W3 h2 + b3;
 * the loss: binary cross-entropy with logits against the multi-hot support of
@@ -49,7 +50,7 @@ def identity(x):
 
 
 def features(A: np.ndarray, Y: np.ndarray) -> np.ndarray:
-    """f[b, n] = a_n^T y_b / (||a_n|| ||y_b||); A is (N, M) atom-major, Y (B, M)."""
+    """f[b, n] = sqrt(M) |a_n^T y_b| / (||a_n|| ||y_b||); A is (N, M) atom-major, Y (B, M)."""
     A = np.asarray(A, np.float64)
     Y = np.asarray(Y, np.float64)
     an = np.linalg.norm(A, axis=1)
@@ -57,7 +58,7 @@ def features(A: np.ndarray, Y: np.ndarray) -> np.ndarray:
     C = Y @ A.T
     inv_a = np.where(an > 0, 1.0 / np.where(an > 0, an, 1.0), 0.0)
     inv_y = np.where(yn > 0, 1.0 / np.where(yn > 0, yn, 1.0), 0.0)
-    return C * inv_a[None, :] * inv_y[:, None]
+    return np.sqrt(A.shape[1]) * np.abs(C) * inv_a[None, :] * inv_y[:, None]
 
 
 def multi_hot(support: np.ndarray, n_out: int) -> np.ndarray:

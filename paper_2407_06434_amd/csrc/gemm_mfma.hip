@@ -67,7 +67,7 @@ __global__ __launch_bounds__(GramTile::NTHR) void k_gram(const float *__restrict
 //   it holds for its signal (16 atoms per fragment, SUBF fragments), the three
 //   best scores and writes them as three keys. Inside the loop a candidate is
 //   a 32-bit key (bits(s) with its low 5 bits replaced by 31 - local index),
-//   so keeping the best three is a min/max sorting network; the dropped bits
+//   so keeping the best three is a max and two medians of three; the dropped bits
 //   change s by less than 2^-18 relative, which the certificate accounts for.
 //   All atoms of the subgroup compete; only when the keys are written are
 //   selected, zero-norm and padding atoms marked invalid (low word 0), so the
@@ -132,11 +132,14 @@ __global__ __launch_bounds__(T::NTHR) void k_corr_select(
           for (int r = 0; r < 16; ++r) {
             const float sc = fabsf(acc[i][j][r]) * iv[i][r];
             const uint32_t key = (__float_as_uint(sc) & ~31u) | (uint32_t)(31 - (ii * 16 + r));
-            const uint32_t lo1 = min(k1, key);
-            k1 = max(k1, key);
-            const uint32_t lo2 = min(k2, lo1);
-            k2 = max(k2, lo1);
-            k3 = max(k3, lo2);
+            // insert into k1 >= k2 >= k3: the new second and third are medians of
+            // three (v_med3_u32), independent of each other
+            const uint32_t n1 = max(k1, key);
+            const uint32_t n2 = max(min(k1, k2), min(max(k1, k2), key));
+            const uint32_t n3 = max(min(k2, k3), min(max(k2, k3), key));
+            k1 = n1;
+            k2 = n2;
+            k3 = n3;
           }
         }
         const uint32_t ks[3] = {k1, k2, k3};

@@ -1,6 +1,7 @@
 // Kernels of the learned support proposal (an extension of the paper's
-// method): a multilayer perceptron maps the normalised first correlation of a
-// signal, f_n = a_n^T y / (||a_n|| ||y||) (Algorithm 1's first argmax input),
+// method): a multilayer perceptron maps the magnitude of the normalised first
+// correlation of a signal, f_n = sqrt(M) |a_n^T y| / (||a_n|| ||y||) (Algorithm
+// 1's first selection statistic, scaled to unit size),
 // to one score per atom; the S best-scored atoms are checked by one
 // least-squares solve (Eq. 2, by the Cholesky factorisation of the Gram
 // block, Section 2.2), and plain OMP handles the signals whose residual misses
@@ -79,7 +80,7 @@ __global__ __launch_bounds__(GT::NTHR) void k_gemm_nt(const uint16_t *__restrict
         const float c = acc[i][j][r];
         const int64_t o = m * e.ldo + n;
         if (EPI == EPI_FEATURES) {
-          reinterpret_cast<uint16_t *>(e.out)[o] = bf16_rne(c * e.colscale[n] * e.rowscale[m]);
+          reinterpret_cast<uint16_t *>(e.out)[o] = bf16_rne(fabsf(c) * e.colscale[n] * e.rowscale[m] * e.scale);
         } else if (EPI == EPI_BIAS_RELU) {
           reinterpret_cast<uint16_t *>(e.out)[o] = bf16_rne(fmaxf(c + e.bias[n], 0.f));
         } else if (EPI == EPI_BIAS) {

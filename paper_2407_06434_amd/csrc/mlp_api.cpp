@@ -286,6 +286,7 @@ int omp_mlp_features(const omp_dict_t *dict, const float *Y, int64_t B, int64_t 
   g.ldo = d.Np;
   g.colscale = d.inv_nu;
   g.rowscale = w.yinv;
+  g.scale = (float)std::sqrt((double)d.M);
   if (e == hipSuccess) e = launch_gemm_bf16(EPI_FEATURES, w.Y16, d.Mp, d.A16, d.Mp, w.Bp, d.Np, d.Mp, 1, g, st);
   if (e == hipSuccess) e = launch_pad_rows16(w.F, d.Np, nullptr, B, d.N, B, F, st);
   if (e != hipSuccess) return device_error(e);
@@ -468,6 +469,7 @@ int omp_learned_solve(const omp_dict_t *dict, const omp_mlp_t *mlp, const float 
   g.ldo = d.Np;
   g.colscale = d.inv_nu;
   g.rowscale = w.yinv;
+  g.scale = (float)std::sqrt((double)d.M);
   if (e == hipSuccess) e = launch_gemm_bf16(EPI_FEATURES, w.Y16, d.Mp, d.A16, d.Mp, w.Bp, d.Np, d.Mp, 1, g, st);
   if (e == hipSuccess) e = forward(n, w, B, false, st);
   if (e == hipSuccess) e = launch_topk(w.Z, n.no, n.no, B, S, P, st);

@@ -12,7 +12,7 @@ namespace bomp {
 
 // Epilogues of the BF16 "NT" product C[m][n] = sum_k P[m][k] Q[n][k].
 enum {
-  EPI_FEATURES = 0,  // out bf16 = c * colscale[n] * rowscale[m]
+  EPI_FEATURES = 0,  // out bf16 = |c| * colscale[n] * rowscale[m] * scale
   EPI_BIAS_RELU = 1, // out bf16 = relu(c + bias[n])
   EPI_BIAS = 2,      // out f32  = c + bias[n]
   EPI_BCE = 3,       // out bf16 = (sigmoid(c + bias[n]) - t[m][n]) * scale; loss terms per block
@@ -30,7 +30,7 @@ struct GemmEpi {
   const uint32_t *labels;    // [m][ldl] multi-hot bits (EPI_BCE)
   int64_t ldl;
   int64_t mvalid;            // rows below this are real signals (EPI_BCE)
-  float scale;               // EPI_BCE: 1 / batch
+  float scale;               // EPI_BCE: 1 / batch; EPI_FEATURES: sqrt(M)
   float *loss_part;          // EPI_BCE: one partial per block
 };
 

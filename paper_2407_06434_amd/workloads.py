@@ -186,17 +186,23 @@ def custom(M: int, N: int, B: int, S: int, seed: int = 7, values: str = "pm",
                     true_support=sup, true_values=vals, sigma=sig)
 
 
-def mlp_init_params(n_in: int = 1024, n_hidden: int = 1024, n_out: int = 1024, seed: int = 3005) -> dict:
+def mlp_init_params(n_in: int = 1024, n_hidden: int = 1024, n_out: int = 1024, seed: int = 3005,
+                    prior: float = 32.0 / 1024.0, noise: float = 0.1) -> dict:
     """Initial weights of the support-proposal network, drawn here and passed to the
-    library: He-uniform U(-sqrt(6/fan_in), sqrt(6/fan_in)) for the ReLU layers, the
-    output layer scaled by 1/4, zero biases. float32, W stored (out, in)."""
+    library. Each layer starts as the identity (on the leading diagonal) plus
+    He-uniform noise U(-s, s), s = noise * sqrt(6/fan_in); hidden biases are zero and
+    the output bias is the log-odds of the prior support density. The untrained
+    network therefore scores each atom by its matched-filter magnitude (the features),
+    which training then refines. float32, W stored (out, in)."""
     g = _rng(seed)
     p = {}
-    for name, (o, i), scale in (("1", (n_hidden, n_in), 1.0), ("2", (n_hidden, n_hidden), 1.0),
-                                ("3", (n_out, n_hidden), 0.25)):
-        lim = np.sqrt(6.0 / i) * scale
-        p["W" + name] = g.uniform(-lim, lim, size=(o, i)).astype(np.float32)
+    for name, (o, i) in (("1", (n_hidden, n_in)), ("2", (n_hidden, n_hidden)), ("3", (n_out, n_hidden))):
+        lim = np.sqrt(6.0 / i) * noise
+        W = g.uniform(-lim, lim, size=(o, i))
+        W[np.arange(min(o, i)), np.arange(min(o, i))] += 1.0
+        p["W" + name] = W.astype(np.float32)
         p["b" + name] = np.zeros(o, np.float32)
+    p["b3"][:] = np.log(prior / (1.0 - prior))
     return p
 
 

@@ -83,17 +83,17 @@ def pin_bf16_rounding(lo):
 
 
 def pin_features(lo):
-    """f_n = +-1 when y is a multiple of atom n (Cauchy-Schwarz equality), |f| <= 1,
+    """f_n = sqrt(M) when y is a multiple of atom n (Cauchy-Schwarz equality), 0 <= f <= sqrt(M),
     zero atoms and zero signals give 0."""
     g = np.random.default_rng(5)
     A = g.normal(size=(40, 16))
     A[7] = 0.0
     Y = np.vstack([3.0 * A[3], -0.5 * A[11], np.zeros(16), g.normal(size=16)])
     F = lo.features(A, Y)
-    assert abs(F[0, 3] - 1.0) < 1e-14 and abs(F[1, 11] + 1.0) < 1e-14
-    assert np.all(np.abs(F) <= 1 + 1e-14)
+    assert abs(F[0, 3] - 4.0) < 1e-13 and abs(F[1, 11] - 4.0) < 1e-13
+    assert np.all(F >= 0) and np.all(F <= 4 + 1e-13)
     assert np.all(F[:, 7] == 0.0) and np.all(F[2] == 0.0)
-    assert abs(F[3, 0] - A[0] @ Y[3] / np.linalg.norm(A[0]) / np.linalg.norm(Y[3])) < 1e-14
+    assert abs(F[3, 0] - 4 * abs(A[0] @ Y[3]) / np.linalg.norm(A[0]) / np.linalg.norm(Y[3])) < 1e-13
 
 
 def pin_top_s(lo):

@@ -34,7 +34,10 @@ MUTATIONS = {
     "no_bias_correction": ("mh = m / (1 - beta1 ** t)", "mh = m"),
     "adam_second_moment_unsquared": ("(1 - beta2) * gk * gk", "(1 - beta2) * np.abs(gk)"),
     "bf16_truncates": ("u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000", "u = u & 0xFFFF0000"),
-    "features_no_atom_norm": ("return C * inv_a[None, :] * inv_y[:, None]", "return C * inv_y[:, None]"),
+    "features_no_atom_norm": ("return np.sqrt(A.shape[1]) * np.abs(C) * inv_a[None, :] * inv_y[:, None]",
+                              "return np.sqrt(A.shape[1]) * np.abs(C) * inv_y[:, None]"),
+    "features_signed": ("return np.sqrt(A.shape[1]) * np.abs(C) * inv_a[None, :] * inv_y[:, None]",
+                        "return np.sqrt(A.shape[1]) * C * inv_a[None, :] * inv_y[:, None]"),
     "top_s_ties_high": ("key=lambda n: (-scores[b, n], n)", "key=lambda n: (-scores[b, n], -n)"),
     "ls_residual_wrong": ("rn[b] = np.linalg.norm(Y[b] - AP @ X[b])", "rn[b] = np.linalg.norm(Y[b])"),
     "first_layer_skips_bias": ("a1 = x0 @ rnd(params[\"W1\"]).T + params[\"b1\"]", "a1 = x0 @ rnd(params[\"W1\"]).T"),

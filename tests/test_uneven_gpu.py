@@ -134,7 +134,7 @@ def test_tune_and_determinism():
     choice = omp.tune(probs, precision="bf16", sample=2048)
     print("tuned", choice, flush=True)
     for cfg, slots, lanes in choice:
-        assert cfg in (1, 3, 4) and slots % 256 == 0 and 256 <= slots <= 2048 and lanes in (1, 2, 4, 8, 16, 32, 64)
+        assert cfg in (1, 3, 4) and slots % 256 == 0 and 256 <= slots <= 2048 and lanes in (0, 1, 2, 4, 8, 16, 32, 64)
     a = [_to_np(o) for o in omp.solve_multi(probs, precision="bf16")]
     b = [_to_np(o) for o in omp.solve_multi(probs, precision="bf16")]
     for x, y, w in zip(a, b, ws):
