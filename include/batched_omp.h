@@ -108,8 +108,7 @@ typedef struct omp_opts {
   int32_t precision;            /* OMP_PREC_FP32 (default) or OMP_PREC_BF16 */
   int32_t tile_config;          /* correlation tiles (atoms x signals): 0 = chosen by shape
                                    (default), 1 = 128x128, 2 = 256x256 (4 wavefronts),
-                                   3 = 256x256 (8 wavefronts), 4 = 256x128, 5 = 256x128 with
-                                   global loads issued two K slices ahead */
+                                   3 = 256x256 (8 wavefronts), 4 = 256x128 */
   const int32_t *S_per_signal;  /* device [B], optional: per-signal S_b in 0..S */
   const float *eps_per_signal;  /* device [B], optional: per-signal eps_b (replaces eps) */
   int32_t *status_out;          /* device [B], optional: (k_b << 8) | OMP_SIG_* bits */

@@ -93,8 +93,7 @@ __global__ __launch_bounds__(T::NTHR) void k_corr_select(
   const u32x4 *P = reinterpret_cast<const u32x4 *>(Aop) + (int64_t)tn * T::TN * rs;
   const u32x4 *Q = reinterpret_cast<const u32x4 *>(Rop) + b0 * rs;
   f32x16 acc[T::FN][T::FB];
-  if (T::PF == 2) mainloop_pf2<Op, T>(P, rs, Q, rs, (int)(rs / T::CH), lds, acc);
-  else mainloop<Op, T>(P, rs, Q, rs, (int)(rs / T::CH), lds, acc);
+  mainloop<Op, T>(P, rs, Q, rs, (int)(rs / T::CH), lds, acc);
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wn = wave % T::WN, wb = wave / T::WN;
@@ -207,7 +206,6 @@ using Cfg1 = Tile<128, 128, 2, 2>;
 using Cfg2 = Tile<256, 256, 2, 2>;
 using Cfg3 = Tile<256, 256, 2, 4>;
 using Cfg4 = Tile<256, 128, 2, 2>;
-using Cfg5 = Tile<256, 128, 2, 2, 2>;
 
 template <class K>
 hipError_t set_lds(K kernel, size_t bytes) {
@@ -253,7 +251,6 @@ CorrGeom corr_geometry(int precision, int64_t Np, int64_t Bp, int cfg) {
     case 2: return geom<Cfg2>(precision, 2);
     case 3: return geom<Cfg3>(precision, 3);
     case 4: return geom<Cfg4>(precision, 4);
-    case 5: return geom<Cfg5>(precision, 5);
     default: return geom<Cfg1>(precision, 1);
   }
 }
@@ -285,7 +282,6 @@ hipError_t prepare_corr(const DictView &d, const WorkView &w, int precision) {
     case 2: return prepare_corr_cfg<Cfg2>(precision);
     case 3: return prepare_corr_cfg<Cfg3>(precision);
     case 4: return prepare_corr_cfg<Cfg4>(precision);
-    case 5: return prepare_corr_cfg<Cfg5>(precision);
     default: return prepare_corr_cfg<Cfg1>(precision);
   }
 }
@@ -295,7 +291,6 @@ hipError_t launch_corr_select(const DictView &d, const WorkView &w, int precisio
     case 2: return launch_corr_cfg<Cfg2>(d, w, precision, st);
     case 3: return launch_corr_cfg<Cfg3>(d, w, precision, st);
     case 4: return launch_corr_cfg<Cfg4>(d, w, precision, st);
-    case 5: return launch_corr_cfg<Cfg5>(d, w, precision, st);
     default: return launch_corr_cfg<Cfg1>(d, w, precision, st);
   }
 }

@@ -46,10 +46,9 @@ struct OpBF16 {
   }
 };
 
-template <int TN_, int TB_, int WN_, int WB_, int PF_ = 1>
+template <int TN_, int TB_, int WN_, int WB_>
 struct Tile {
   static constexpr int TN = TN_, TB = TB_, WN = WN_, WB = WB_;
-  static constexpr int PF = PF_;     // prefetch distance of the global loads, in K slices (1 or 2)
   static constexpr int NTHR = WN * WB * 64;
   static constexpr int FN = TN / (32 * WN);
   static constexpr int FB = TB / (32 * WB);
@@ -143,97 +142,6 @@ __device__ inline void mainloop(const u32x4 *__restrict__ P, int64_t prs, const 
         nb[T::TN * T::RS + (idx / T::CH) * T::RS + (idx % T::CH)] = rb[i];
       }
     }
-    __syncthreads();
-  }
-}
-
-// Pieces of the prefetch-distance-2 main loop (force-inlined helpers: arrays
-// passed by reference stay in registers once inlined).
-template <class T>
-__device__ __attribute__((always_inline)) inline void tile_gload(const u32x4 *__restrict__ P, int64_t prs,
-                                                                 const u32x4 *__restrict__ Q, int64_t qrs, int s,
-                                                                 u32x4 (&ra)[T::A_LD], u32x4 (&rb)[T::B_LD]) {
-  const int tid = threadIdx.x;
-#pragma unroll
-  for (int i = 0; i < T::A_LD; ++i) {
-    const int idx = tid + i * T::NTHR;
-    ra[i] = P[(int64_t)(idx / T::CH) * prs + (int64_t)s * T::CH + (idx % T::CH)];
-  }
-#pragma unroll
-  for (int i = 0; i < T::B_LD; ++i) {
-    const int idx = tid + i * T::NTHR;
-    rb[i] = Q[(int64_t)(idx / T::CH) * qrs + (int64_t)s * T::CH + (idx % T::CH)];
-  }
-}
-
-template <class T>
-__device__ __attribute__((always_inline)) inline void tile_lstore(u32x4 *lds, int buf, const u32x4 (&ra)[T::A_LD],
-                                                                  const u32x4 (&rb)[T::B_LD]) {
-  const int tid = threadIdx.x;
-  u32x4 *nb = lds + buf * T::STAGE;
-#pragma unroll
-  for (int i = 0; i < T::A_LD; ++i) {
-    const int idx = tid + i * T::NTHR;
-    nb[(idx / T::CH) * T::RS + (idx % T::CH)] = ra[i];
-  }
-#pragma unroll
-  for (int i = 0; i < T::B_LD; ++i) {
-    const int idx = tid + i * T::NTHR;
-    nb[T::TN * T::RS + (idx / T::CH) * T::RS + (idx % T::CH)] = rb[i];
-  }
-}
-
-template <class Op, class T>
-__device__ __attribute__((always_inline)) inline void tile_compute(const u32x4 *lds, int buf,
-                                                                   f32x16 (&acc)[T::FN][T::FB]) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wn = wave % T::WN, wb = wave / T::WN;
-  const int h = lane >> 5, r32 = lane & 31;
-  const u32x4 *la = lds + buf * T::STAGE + (wn * T::FN * 32 + r32) * T::RS + h;
-  const u32x4 *lb = lds + buf * T::STAGE + T::TN * T::RS + (wb * T::FB * 32 + r32) * T::RS + h;
-#pragma unroll
-  for (int q = 0; q < T::CH / 2; ++q) {
-    u32x4 af[T::FN], bf[T::FB];
-#pragma unroll
-    for (int i = 0; i < T::FN; ++i) af[i] = la[i * 32 * T::RS + 2 * q];
-#pragma unroll
-    for (int j = 0; j < T::FB; ++j) bf[j] = lb[j * 32 * T::RS + 2 * q];
-#pragma unroll
-    for (int i = 0; i < T::FN; ++i)
-#pragma unroll
-      for (int j = 0; j < T::FB; ++j) Op::mma(af[i], bf[j], acc[i][j]);
-  }
-}
-
-// Main loop with prefetch distance 2: the global loads of slice s+2 are issued
-// (into one of two register sets) before slice s is multiplied, and slice s+1
-// (loaded one iteration earlier) is stored to LDS after it, so every load has
-// two slices of MFMA work to land. The slice loop is unrolled by two so that
-// both register sets are addressed statically. Needs nslices >= 1.
-template <class Op, class T>
-__device__ inline void mainloop_pf2(const u32x4 *__restrict__ P, int64_t prs, const u32x4 *__restrict__ Q,
-                                    int64_t qrs, int nslices, u32x4 *lds, f32x16 (&acc)[T::FN][T::FB]) {
-#pragma unroll
-  for (int i = 0; i < T::FN; ++i)
-#pragma unroll
-    for (int j = 0; j < T::FB; ++j) acc[i][j] = f32x16{};
-
-  u32x4 ra0[T::A_LD], rb0[T::B_LD], ra1[T::A_LD], rb1[T::B_LD];
-  tile_gload<T>(P, prs, Q, qrs, 0, ra0, rb0);
-  if (nslices > 1) tile_gload<T>(P, prs, Q, qrs, 1, ra1, rb1);
-  tile_lstore<T>(lds, 0, ra0, rb0);
-  __syncthreads();
-  for (int s = 0; s < nslices; s += 2) {
-    // even slice s: LDS buffer 0; set 1 holds slice s+1 in flight
-    if (s + 2 < nslices) tile_gload<T>(P, prs, Q, qrs, s + 2, ra0, rb0);
-    tile_compute<Op, T>(lds, 0, acc);
-    if (s + 1 < nslices) tile_lstore<T>(lds, 1, ra1, rb1);
-    __syncthreads();
-    if (s + 1 >= nslices) break;
-    // odd slice s+1: LDS buffer 1; set 0 holds slice s+2 in flight
-    if (s + 3 < nslices) tile_gload<T>(P, prs, Q, qrs, s + 3, ra1, rb1);
-    tile_compute<Op, T>(lds, 1, acc);
-    if (s + 2 < nslices) tile_lstore<T>(lds, 0, ra0, rb0);
     __syncthreads();
   }
 }

@@ -33,7 +33,7 @@ constexpr int NSLICE_MAX = 8;
 constexpr uint32_t DICT_MAGIC = 0x4f4d5044u;  // "OMPD"
 
 // Correlation tile configurations 1..MAX_TILE_CFG (0 = chosen by shape).
-constexpr int MAX_TILE_CFG = 5;
+constexpr int MAX_TILE_CFG = 4;
 
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 

@@ -120,26 +120,41 @@ __device__ __attribute__((always_inline)) inline void atom_dots(const DictView &
                                  const float4 *__restrict__ y4, int lane, double (&av)[NA], double (&ay)[NA]) {
   const int64_t nc4 = d.Mp / 4;
   const float4 *A4 = reinterpret_cast<const float4 *>(d.A32);
-  const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
+  // Every load reads a valid address (unused atoms read row 0, chunks past the
+  // end read chunk 0) and the value is then masked: a conditional choice between
+  // a load and a constant would be compiled as a choice of pointers.
+  int64_t row[NA];
+  bool use[NA];
+#pragma unroll
+  for (int i = 0; i < NA; ++i) {
+    use[i] = n[i] >= 0;
+    row[i] = (int64_t)(use[i] ? n[i] : 0) * nc4;
+  }
 #pragma unroll
   for (int i = 0; i < NA; ++i) av[i] = ay[i] = 0.0;
   for (int64_t c0 = 0; c0 < nc4; c0 += 64 * CP) {
     float4 vv[CP], yy[CP], aa[NA][CP];
+    bool ok[CP];
 #pragma unroll
     for (int q = 0; q < CP; ++q) {
       const int64_t c = c0 + lane + 64 * q;
-      const bool ok = c < nc4;
-      vv[q] = ok ? v4[c] : zero;
-      yy[q] = (TWO && ok) ? y4[c] : zero;
+      ok[q] = c < nc4;
+      const int64_t cs = ok[q] ? c : 0;
+      vv[q] = v4[cs];
+      if (TWO) yy[q] = y4[cs];
 #pragma unroll
-      for (int i = 0; i < NA; ++i) aa[i][q] = (ok && n[i] >= 0) ? A4[(int64_t)n[i] * nc4 + c] : zero;
+      for (int i = 0; i < NA; ++i) aa[i][q] = A4[row[i] + cs];
     }
 #pragma unroll
     for (int i = 0; i < NA; ++i)
 #pragma unroll
       for (int q = 0; q < CP; ++q) {
-        av[i] += dot4d(aa[i][q], vv[q]);
-        if (TWO) ay[i] += dot4d(aa[i][q], yy[q]);
+        const double pa = dot4d(aa[i][q], vv[q]);
+        av[i] += (use[i] && ok[q]) ? pa : 0.0;
+        if (TWO) {
+          const double py = dot4d(aa[i][q], yy[q]);
+          ay[i] += (use[i] && ok[q]) ? py : 0.0;
+        }
       }
   }
 #pragma unroll

@@ -226,7 +226,7 @@ def test_multi_rejects_invalid(lib, case):
     if case == "ldy": p.ldy = 127
     if case == "nullY": p.Y = None
     if case == "nullsup": p.support_out = None
-    if case == "cfg": p.tile_config = 6
+    if case == "cfg": p.tile_config = 5
     if case == "lanes": p.residual_lanes = 3
     if case == "slots_neg": p.slots = -256
     if case == "chunk": o.iters_per_graph = 65
