@@ -54,6 +54,33 @@ __global__ __launch_bounds__(GramTile::NTHR) void k_gram(const float *__restrict
 }
 
 // ---------------------------------------------------------------------------
+// XCD-aware tile order. Workgroups are handed to the 8 XCDs round robin
+// (workgroup b runs on XCD b mod 8), each XCD with its own L2. When the tile
+// grid (nta atom tiles x ntb signal tiles) splits into 8 equal rectangles,
+// XCD x takes rectangle x, the split chosen to minimise the operand panels one
+// XCD reads (nta/px + ntb/py); otherwise the order is plain row-major.
+// ---------------------------------------------------------------------------
+__device__ inline void xcd_tile(int b, int nta, int ntb, int *tn, int *tb) {
+  int px = 0, best = 1 << 30;
+  for (int q = 1; q <= 8; q *= 2) {
+    const int r = 8 / q;  // q columns of atom tiles, r rows of signal tiles
+    if (nta % q == 0 && ntb % r == 0 && nta / q + ntb / r < best) {
+      best = nta / q + ntb / r;
+      px = q;
+    }
+  }
+  if (px == 0) {
+    *tn = b % nta;
+    *tb = b / nta;
+    return;
+  }
+  const int x = b % 8, l = b / 8;
+  const int lw = nta / px, lh = ntb / (8 / px);
+  *tn = (x % px) * lw + l % lw;
+  *tb = (x / px) * lh + l / lw;
+}
+
+// ---------------------------------------------------------------------------
 // Correlation + select. For every signal j of the tile and every atom n of the
 // tile, score s = |c_nj| * inv_nu[n]; an atom is a candidate when inv_nu[n] > 0
 // (not a zero or padding atom) and its bit in the signal's selected-atom mask
@@ -79,7 +106,8 @@ __global__ __launch_bounds__(T::NTHR) void k_corr_select(
     int64_t Np, const float *__restrict__ inv_nu, const uint32_t *__restrict__ mask,
     const int32_t *__restrict__ flags, uint64_t *__restrict__ part, int ntile) {
   extern __shared__ u32x4 lds[];
-  const int tn = blockIdx.x % ntile, tb = blockIdx.x / ntile;
+  int tn, tb;
+  xcd_tile(blockIdx.x, ntile, gridDim.x / ntile, &tn, &tb);
   const int64_t b0 = (int64_t)tb * T::TB;
 
   // Skip the tile when every signal in it has stopped (keep-in-batch stopping,

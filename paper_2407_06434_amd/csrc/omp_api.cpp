@@ -140,26 +140,26 @@ int check_device() {
 namespace {
 
 // Optional profiling (omp_opts_t.phase_ms): brackets every launch with a pair
-// of hipEvents on the solve's stream and sums the elapsed times per phase.
+// of hipEvents on the solve's stream and sums the elapsed times per phase. The
+// events come from a per-thread pool that is created once and reused, so that
+// timing adds no event creation to the enqueue path (which would otherwise let
+// the GPU run ahead of the host and idle between launches).
 class PhaseTimer {
  public:
   PhaseTimer(float *ms, int32_t *launches, hipStream_t st) : ms_(ms), n_(launches), st_(st) {}
-  ~PhaseTimer() {
-    for (auto &r : recs_) {
-      (void)hipEventDestroy(r.a);
-      (void)hipEventDestroy(r.b);
-    }
-  }
   template <class F>
   hipError_t run(int phase, F &&launch) {
     if (!ms_) return launch();
-    Rec r{nullptr, nullptr, phase};
-    hipError_t e = hipEventCreate(&r.a);
-    if (e == hipSuccess) e = hipEventCreate(&r.b);
-    if (e == hipSuccess) e = hipEventRecord(r.a, st_);
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = pool_get(2 * used_, &a);
+    if (e == hipSuccess) e = pool_get(2 * used_ + 1, &b);
+    if (e == hipSuccess) e = hipEventRecord(a, st_);
     if (e == hipSuccess) e = launch();
-    if (e == hipSuccess) e = hipEventRecord(r.b, st_);
-    recs_.push_back(r);
+    if (e == hipSuccess) e = hipEventRecord(b, st_);
+    if (e == hipSuccess) {
+      phases_.push_back(phase);
+      ++used_;
+    }
     return e;
   }
   hipError_t finish() {
@@ -169,24 +169,38 @@ class PhaseTimer {
       ms_[p] = 0.f;
       if (n_) n_[p] = 0;
     }
-    for (auto &r : recs_) {
+    for (size_t i = 0; i < used_ && e == hipSuccess; ++i) {
       float t = 0.f;
-      if (e == hipSuccess) e = hipEventElapsedTime(&t, r.a, r.b);
-      ms_[r.phase] += t;
-      if (n_) n_[r.phase] += 1;
+      e = hipEventElapsedTime(&t, pool()[2 * i], pool()[2 * i + 1]);
+      ms_[phases_[i]] += t;
+      if (n_) n_[phases_[i]] += 1;
     }
     return e;
   }
 
  private:
-  struct Rec {
-    hipEvent_t a, b;
-    int phase;
-  };
+  // Held until the process ends (never destroyed: the runtime may already be
+  // shutting down when thread-local destructors run).
+  static std::vector<hipEvent_t> &pool() {
+    thread_local std::vector<hipEvent_t> *ev = new std::vector<hipEvent_t>();
+    return *ev;
+  }
+  static hipError_t pool_get(size_t i, hipEvent_t *out) {
+    std::vector<hipEvent_t> &ev = pool();
+    while (ev.size() <= i) {
+      hipEvent_t x = nullptr;
+      hipError_t e = hipEventCreate(&x);
+      if (e != hipSuccess) return e;
+      ev.push_back(x);
+    }
+    *out = ev[i];
+    return hipSuccess;
+  }
   float *ms_;
   int32_t *n_;
   hipStream_t st_;
-  std::vector<Rec> recs_;
+  size_t used_ = 0;
+  std::vector<int> phases_;
 };
 
 }  // namespace
