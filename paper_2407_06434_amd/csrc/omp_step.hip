@@ -238,6 +238,40 @@ struct RescoreQueue {
   }
 };
 
+// Keys kept in registers per lane by the solve's first memory round (BF16 form):
+// up to 64 * KREG keys per signal, otherwise they are read again in batches.
+constexpr int KREG = 8;
+// Subgroups listed as possibly open (beyond this the bounding keys are scanned).
+constexpr int MAYBE_CAP = 32;
+// Ints of the candidate list (room for every key, a multiple of 4).
+__host__ __device__ inline int64_t solve_cand_len(int64_t nkeys) { return (nkeys + 3) / 4 * 4; }
+
+// One batch of keys (KB per lane, key t0 + 64 j + lane in kb[j]): candidates
+// (valid, score >= thr) are appended to clist, subgroups whose bounding key
+// could reach the exact winner (theta (1 + et) >= mthr) to mlist.
+template <int KB>
+__device__ __attribute__((always_inline)) inline void scan_keys(const uint64_t (&kb)[KB], int t0, int nkeys,
+                                                                double thr, double mthr, double et, int *clist,
+                                                                int *mlist, int &ncand, int &nmaybe) {
+#pragma unroll
+  for (int j = 0; j < KB; ++j) {
+    const int t = t0 + 64 * j + (int)(threadIdx.x & 63);
+    const double sc = (double)__uint_as_float((uint32_t)(kb[j] >> 32));
+    const bool cand = (kb[j] & 0xFFFFFFFFull) && sc >= thr;
+    const uint64_t m = __ballot(cand);
+    const int pos = ncand + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                           __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    if (cand) clist[pos] = (int)(0xFFFFFFFFu - (uint32_t)(kb[j] & 0xFFFFFFFFull));
+    ncand += __popcll(m);
+    const bool maybe = t < nkeys && (t % NKEEP) == NKEEP - 1 && sc * (1.0 + et) >= mthr;
+    const uint64_t mm = __ballot(maybe);
+    const int mpos = nmaybe + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mm >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)mm, 0u));
+    if (maybe && mpos < MAYBE_CAP) mlist[mpos] = t;
+    nmaybe += __popcll(mm);
+  }
+}
+
 // BF16 form of the pick. The epilogue left, per subgroup of atoms, keys for
 // its NKEEP best BF16 scores, each score rounded down by less than 2^-18
 // relative (et below); keys of selected, zero or padding atoms carry their
@@ -249,76 +283,58 @@ struct RescoreQueue {
 //      the window has exact score <= s (1 + et) + tau < s_max - tau.)
 //   2. an unlisted atom of a subgroup has exact score <= theta (1 + et) + tau,
 //      theta the subgroup's last kept score; when that reaches s_w the whole
-//      subgroup is re-scored (and the signal is flagged OMP_SIG_WIDENED).
+//      subgroup is re-scored (and the signal is flagged OMP_SIG_WIDENED). Since
+//      s_w >= s_max - tau, only subgroups with theta (1 + et) >= s_max - 2 tau
+//      can open: they are listed while the keys are scanned for step 1 and
+//      tested against s_w afterwards.
 // The result is the exact argmax of s over the selectable atoms, ties to the
 // lowest index; *beta, *nu2 and g receive a_n*^T y, ||a_n*||^2 and the Gram
 // row G[n*, support] of the pick (fetched in the same round as its score).
+// kv holds the signal's keys when kreg (read in the first memory round).
 template <int RPL>
 __device__ int select_bf16(const DictView &d, const WorkView &w, int64_t b, float smax, double tau,
                            const int (&si)[RPL], int k, int lane, int *widened, double *beta, double *nu2,
-                           float (&g)[RPL], int *clist) {
+                           float (&g)[RPL], int *clist, const uint64_t (&kv)[KREG], bool kreg) {
   const int nkeys = w.ntile * w.ncand;
   const uint64_t *keys = w.part + b * nkeys;
   const float4 *r4 = reinterpret_cast<const float4 *>(w.R32) + b * (d.Mp / 4);
   const float4 *y4 = reinterpret_cast<const float4 *>(w.Yp) + b * (d.Mp / 4);
   const double et = 1.0 / 262144.0;  // 2^-18: the epilogue's rounding of listed scores
   const double thr = (double)smax - 2.0 * tau - et * (double)smax;
+  const double mthr = (double)smax - 2.0 * tau;
+  int *mlist = clist + solve_cand_len(nkeys);
   RescoreQueue<RPL> q;
-  // Pass 1: the candidates. Keys are read KB per lane at a time (the loads of a
-  // batch are in flight together) and each candidate's atom is appended to the
-  // wavefront's LDS list (room for every key); the re-score then walks the list.
-  constexpr int KB = 8;
-  int ncand = 0;
-  for (int t0 = 0; t0 < nkeys; t0 += 64 * KB) {
-    uint64_t kv[KB];
+  // Candidates and possibly open subgroups, from the keys in registers or, for
+  // more keys than that, read again KREG per lane at a time.
+  int ncand = 0, nmaybe = 0;
+  if (kreg) {
+    scan_keys<KREG>(kv, 0, nkeys, thr, mthr, et, clist, mlist, ncand, nmaybe);
+  } else {
+    for (int t0 = 0; t0 < nkeys; t0 += 64 * KREG) {
+      uint64_t kb[KREG];
 #pragma unroll
-    for (int j = 0; j < KB; ++j) {
-      const int t = t0 + 64 * j + lane;
-      kv[j] = t < nkeys ? keys[t] : 0ull;
-    }
-#pragma unroll
-    for (int j = 0; j < KB; ++j) {
-      const bool cand = (kv[j] & 0xFFFFFFFFull) && (double)__uint_as_float((uint32_t)(kv[j] >> 32)) >= thr;
-      const uint64_t m = __ballot(cand);
-      const int pos = ncand + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-      if (cand) clist[pos] = (int)(0xFFFFFFFFu - (uint32_t)(kv[j] & 0xFFFFFFFFull));
-      ncand += __popcll(m);
+      for (int j = 0; j < KREG; ++j) {
+        const int t = t0 + 64 * j + lane;
+        const uint64_t v = keys[t < nkeys ? t : 0];
+        kb[j] = t < nkeys ? v : 0ull;
+      }
+      scan_keys<KREG>(kb, t0, nkeys, thr, mthr, et, clist, mlist, ncand, nmaybe);
     }
   }
   wave_lds_sync();
   for (int i = 0; i < ncand; ++i) q.push(__builtin_amdgcn_readfirstlane(clist[i]), d, r4, y4, si, k, lane);
   q.flush(d, r4, y4, si, k, lane);
 
-  // Pass 2: the subgroups whose bound reaches the provisional pick (their key
-  // slots go to the same LDS list), each then re-scored whole.
-  wave_lds_sync();
-  int nopen = 0;
-  for (int t0 = 0; t0 < nkeys; t0 += 64 * KB) {
-    uint64_t kv[KB];
-#pragma unroll
-    for (int j = 0; j < KB; ++j) {
-      const int t = t0 + 64 * j + lane;
-      const bool third = t < nkeys && (t % NKEEP) == NKEEP - 1;  // the subgroup's bounding key
-      kv[j] = third ? keys[t] : 0ull;
-    }
-#pragma unroll
-    for (int j = 0; j < KB; ++j) {
-      const int t = t0 + 64 * j + lane;
-      const bool third = t < nkeys && (t % NKEEP) == NKEEP - 1;
-      const bool open = third && (double)__uint_as_float((uint32_t)(kv[j] >> 32)) * (1.0 + et) + tau >= q.bs;
-      const uint64_t m = __ballot(open);
-      const int pos = nopen + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-      if (open) clist[pos] = t;
-      nopen += __popcll(m);
-    }
-  }
-  wave_lds_sync();
+  // The listed subgroups (all bounding keys if the list overflowed) against
+  // the exact winner; an open subgroup is re-scored whole.
   const int64_t mwords = d.Np / 32;
   const uint32_t *mk = w.mask + b * mwords;
-  for (int i = 0; i < nopen; ++i) {
-    const int slot = __builtin_amdgcn_readfirstlane(clist[i]);
+  const bool movf = nmaybe > MAYBE_CAP;
+  const int npass = movf ? nkeys / NKEEP : nmaybe;
+  for (int i = 0; i < npass; ++i) {
+    const int slot = movf ? i * NKEEP + NKEEP - 1 : __builtin_amdgcn_readfirstlane(mlist[i]);
+    const double theta = (double)__uint_as_float((uint32_t)(keys[slot] >> 32));
+    if (!(theta * (1.0 + et) + tau >= q.bs)) continue;
     const int tile = slot / w.ncand;
     const int sgl = (slot % w.ncand) / NKEEP;  // ((wn * subs_per_half + ig) * 2 + h)
     const int hh = sgl & 1;
@@ -523,10 +539,11 @@ __device__ void retire_and_admit(const WorkView &w, const SlotView &sv, int64_t 
 // ---------------------------------------------------------------------------
 constexpr int SOLVE_WAVES = 4;
 
-// Ints of the BF16 pick's candidate list per wavefront (a multiple of 4, so
-// that every wavefront's LDS region stays 16-byte aligned); 0 in the FP32 form.
+// Ints of the BF16 pick's candidate and possibly-open lists per wavefront (a
+// multiple of 4, so that every wavefront's LDS region stays 16-byte aligned);
+// 0 in the FP32 form.
 __host__ __device__ inline int64_t solve_list_len(const WorkView &w) {
-  return w.R16 ? (int64_t)(w.ntile * w.ncand + 3) / 4 * 4 : 0;
+  return w.R16 ? solve_cand_len((int64_t)w.ntile * w.ncand) + MAYBE_CAP : 0;
 }
 
 // A stop found by the solve step: record the flags, or (slot scheduler) write
@@ -571,10 +588,25 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
   const int nkeys = w.ntile * w.ncand;
   const uint64_t *keys = w.part + b * nkeys;
   uint64_t kmax = 0;  // largest valid key (a valid key has a non-zero index word)
+  // BF16 form: up to 64 KREG keys stay in registers for the pick
+  uint64_t kv[KREG];
+  const bool kreg = BF16 && nkeys <= 64 * KREG;
+  if (kreg) {
+#pragma unroll
+    for (int j = 0; j < KREG; ++j) {
+      const int t = 64 * j + lane;
+      const uint64_t v = keys[t < nkeys ? t : 0];
+      kv[j] = t < nkeys ? v : 0ull;
+      kmax = ((kv[j] & 0xFFFFFFFFull) && kv[j] > kmax) ? kv[j] : kmax;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < KREG; ++j) kv[j] = 0ull;
 #pragma unroll 4
-  for (int t = lane; t < nkeys; t += 64) {
-    const uint64_t v = keys[t];
-    kmax = ((v & 0xFFFFFFFFull) && v > kmax) ? v : kmax;
+    for (int t = lane; t < nkeys; t += 64) {
+      const uint64_t v = keys[t];
+      kmax = ((v & 0xFFFFFFFFull) && v > kmax) ? v : kmax;
+    }
   }
   if (fl & FLAG_NEWX) {
     fl &= ~FLAG_NEWX;
@@ -628,7 +660,7 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
   if (BF16) {
     const double tau = bf16_tau(rn, sqrt(wave_sum(pd)), (double)d.aerr_max[0], d.Mp);
     nstar = select_bf16<RPL>(d, w, b, __uint_as_float((uint32_t)(kmax >> 32)), tau, si, k, lane, &widened, &beta,
-                             &nu2, g, clist);
+                             &nu2, g, clist, kv, kreg);
     if (nstar < 0) {
       stopfl = fl | FLAG_DONE | OMP_SIG_EXHAUSTED;
       goto stop;
