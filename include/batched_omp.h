@@ -125,6 +125,10 @@ typedef struct omp_opts {
                                    the stream, and phase_ms[p] receives the summed kernel time (ms)
                                    of phase p; NULL (default) keeps the call asynchronous */
   int32_t *phase_launches;      /* HOST [OMP_NPHASE], optional: launches per phase (with phase_ms) */
+  int32_t use_graph;            /* 1 (the default of omp_opts_default): the solve's launches are
+                                   captured once into a hipGraph, cached per device and per
+                                   argument set (every pointer and size of the call), and replayed
+                                   with one graph launch; 0: the kernels are launched one by one */
 } omp_opts_t;
 
 /* Phases reported through omp_opts_t.phase_ms. */

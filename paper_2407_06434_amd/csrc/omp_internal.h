@@ -6,6 +6,8 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <functional>
+#include <string>
 
 namespace bomp {
 
@@ -109,6 +111,12 @@ bool dims_ok(int64_t M, int64_t N);          // sizes the padded buffers can hol
 int device_error(hipError_t e);              // records e for omp_last_hip_error, returns OMP_EDEVICE
 int check_device();                          // OMP_OK on a gfx950 device
 constexpr size_t WS_ALIGN = 256;
+
+// Enqueues on `st` the hipGraph cached under `key` for the current device; on
+// the first use of a key, `body` enqueues the work on the capture stream it is
+// given and is captured. Serialized with the uneven-batch entry points.
+hipError_t graph_launch_cached(const std::string &key, const std::function<hipError_t(hipStream_t)> &body,
+                               hipStream_t st);
 
 // ---- launchers (all enqueue on `st`, return the launch status) -------------
 

@@ -15,9 +15,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <chrono>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <list>
 #include <mutex>
 #include <string>
@@ -165,10 +165,46 @@ hipError_t capture_chunk(DevState *ds, const std::vector<Plan> &plans, int preci
 }
 
 hipError_t cached_graph(DevState *ds, const std::vector<Plan> &plans, int precision, int chunk,
+                        hipGraphExec_t *exec);
+
+// Looks `key` up in the device's graph cache; on a miss, runs `body` under
+// stream capture on internal stream 0 and caches the instantiated graph.
+hipError_t cached_graph_body(DevState *ds, const std::string &key,
+                             const std::function<hipError_t(hipStream_t)> &body, hipGraphExec_t *exec) {
+  for (auto it = ds->cache.begin(); it != ds->cache.end(); ++it) {
+    if (it->first == key) {
+      ds->cache.splice(ds->cache.begin(), ds->cache, it);
+      *exec = it->second;
+      return hipSuccess;
+    }
+  }
+  hipStream_t s0 = ds->streams[0];
+  hipError_t e = hipStreamBeginCapture(s0, hipStreamCaptureModeRelaxed);
+  if (e != hipSuccess) return e;
+  e = body(s0);
+  hipGraph_t graph = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(s0, &graph);  // always ends the capture
+  if (e == hipSuccess) e = e2;
+  hipGraphExec_t g = nullptr;
+  if (e == hipSuccess) e = hipGraphInstantiate(&g, graph, nullptr, nullptr, 0);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return e;
+  ds->cache.emplace_front(key, g);
+  while (ds->cache.size() > GRAPH_CACHE) {
+    (void)hipGraphExecDestroy(ds->cache.back().second);
+    ds->cache.pop_back();
+  }
+  *exec = g;
+  return hipSuccess;
+}
+
+hipError_t cached_graph(DevState *ds, const std::vector<Plan> &plans, int precision, int chunk,
                         hipGraphExec_t *exec) {
-  std::string key(reinterpret_cast<const char *>(plans.data()), plans.size() * sizeof(Plan));
+  std::string key("M");
+  key.append(reinterpret_cast<const char *>(plans.data()), plans.size() * sizeof(Plan));
   key.append(reinterpret_cast<const char *>(&precision), sizeof(precision));
   key.append(reinterpret_cast<const char *>(&chunk), sizeof(chunk));
+  // the chunk is captured by capture_chunk (its own fork/join over the problem streams)
   for (auto it = ds->cache.begin(); it != ds->cache.end(); ++it) {
     if (it->first == key) {
       ds->cache.splice(ds->cache.begin(), ds->cache, it);
@@ -307,6 +343,18 @@ int validate(const omp_problem_t *probs, int nprob, const omp_multi_opts_t *opts
 }
 
 }  // namespace
+
+hipError_t graph_launch_cached(const std::string &key, const std::function<hipError_t(hipStream_t)> &body,
+                               hipStream_t st) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  DevState *ds = nullptr;
+  hipError_t e = dev_state(&ds);
+  if (e != hipSuccess) return e;
+  hipGraphExec_t exec = nullptr;
+  e = cached_graph_body(ds, "S" + key, body, &exec);
+  if (e != hipSuccess) return e;
+  return hipGraphLaunch(exec, st);
+}
 
 }  // namespace bomp
 

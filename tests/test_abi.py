@@ -32,6 +32,13 @@ def test_exports_every_declared_symbol(lib):
     assert set(omp.EXPORTED) == set(names)
 
 
+def test_opts_default_enables_graphs(lib):
+    from paper_2407_06434_amd import omp
+    o = omp.OmpOptsStruct()
+    lib.omp_opts_default(ctypes.byref(o))
+    assert o.use_graph == 1 and o.precision == 0 and o.workspace is None
+
+
 def test_version_and_strings(lib):
     assert lib.omp_version().decode().count(".") == 2
     for code in (0, -1, -2, -3, -4):
@@ -41,7 +48,7 @@ def test_version_and_strings(lib):
 def test_struct_layout_matches_header():
     from paper_2407_06434_amd import omp
     assert ctypes.sizeof(omp.OmpDictStruct) == 64
-    assert ctypes.sizeof(omp.OmpOptsStruct) == 8 + 8 * 7 + 8 + 16
+    assert ctypes.sizeof(omp.OmpOptsStruct) == 8 + 8 * 7 + 8 + 16 + 8
 
 
 def _opts(ws=1 << 30, prec=0):

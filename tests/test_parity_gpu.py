@@ -189,3 +189,42 @@ def test_batch_composition_independence(prec):
     part = run_gpu(sub, prec)
     for key in ("support", "coef", "status", "rnorm"):
         assert np.array_equal(full[key][130:137], part[key]), key
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_graph_replays_match_direct_launches(prec):
+    """The graph-replayed solve (cached per argument set) equals the directly launched one
+    on every replay, with other eager GPU work and synchronisations between replays;
+    phase timing works from inside the graph."""
+    torch = _torch()
+    from paper_2407_06434_amd import omp, workloads
+    w = workloads.batched_256x1024(B=300)
+    dev = torch.device("cuda:0")
+    A = torch.from_numpy(w.A).to(dev)
+    Y = torch.from_numpy(w.Y).to(dev)
+    d = omp.Dictionary(A, prec)
+    print(f"case graph replays {prec}", flush=True)
+    ref = omp.solve(A, Y, w.S, precision=prec, dictionary=d, graph=False)
+    torch.cuda.synchronize()
+    ref = {k: v.cpu().numpy() for k, v in ref._asdict().items() if v is not None}
+    ws = torch.empty(omp.workspace_bytes(w.M, w.N, w.B, w.S, prec, with_dict=True), dtype=torch.uint8, device=dev)
+    out = None
+    other = workloads.custom(64, 256, 50, 8, seed=4)
+    for rep in range(4):
+        timing = {} if rep == 3 else None
+        out = omp.solve(A, Y, w.S, precision=prec, dictionary=d, workspace=ws, out=out, graph=True, timing=timing)
+        torch.cuda.synchronize()
+        got = {k: v.cpu().numpy() for k, v in out._asdict().items() if v is not None}
+        for k in ref:
+            assert np.array_equal(ref[k], got[k]), (rep, k)
+        # eager work between the replays
+        omp.solve(torch.from_numpy(other.A).to(dev), torch.from_numpy(other.Y).to(dev), 8, precision=prec,
+                  graph=False)
+        out.X.zero_()
+        out.support.fill_(-7)
+        torch.cuda.synchronize()
+        if timing is not None:
+            print("graph timing", timing)
+            assert timing["corr"][1] == w.S and timing["update"][1] == w.S and timing["residual"][1] == w.S
+            assert timing["init"][1] == 1 and timing["output"][1] == 1
+            assert all(v[0] > 0 for k, v in timing.items() if v[1] > 0)
