@@ -128,7 +128,8 @@ typedef struct omp_opts {
   int32_t use_graph;            /* 1 (the default of omp_opts_default): the solve's launches are
                                    captured once into a hipGraph, cached per device and per
                                    argument set (every pointer and size of the call), and replayed
-                                   with one graph launch; 0: the kernels are launched one by one */
+                                   with one graph launch; 0: the kernels are launched one by one.
+                                   A call with phase_ms set always launches one by one. */
 } omp_opts_t;
 
 /* Phases reported through omp_opts_t.phase_ms. */

@@ -146,37 +146,21 @@ namespace {
 // the GPU run ahead of the host and idle between launches).
 class PhaseTimer {
  public:
-  PhaseTimer(float *ms, int32_t *launches, hipStream_t st) : ms_(ms), n_(launches), st_(st), rec_(st) {}
+  PhaseTimer(float *ms, int32_t *launches, hipStream_t st) : ms_(ms), n_(launches), st_(st) {}
   bool on() const { return ms_ != nullptr; }
-  // Events are recorded on `s` from now on (the capture stream of a graph).
-  void record_on(hipStream_t s) { rec_ = s; }
-  // Dry mode: run() only notes the phase (the work is already in a cached graph).
-  void set_dry(bool dry) { dry_ = dry; }
   void reset() {
     used_ = 0;
     phases_.clear();
   }
-  // The pool address identifies the events a captured graph records into.
-  static const void *pool_id() { return &pool(); }
-  hipError_t reserve(size_t launches) {
-    if (!ms_) return hipSuccess;
-    hipEvent_t x;
-    return launches ? pool_get(2 * launches - 1, &x) : hipSuccess;
-  }
   template <class F>
   hipError_t run(int phase, F &&launch) {
-    if (!ms_) return dry_ ? hipSuccess : launch();
-    if (dry_) {
-      phases_.push_back(phase);
-      ++used_;
-      return hipSuccess;
-    }
+    if (!ms_) return launch();
     hipEvent_t a = nullptr, b = nullptr;
     hipError_t e = pool_get(2 * used_, &a);
     if (e == hipSuccess) e = pool_get(2 * used_ + 1, &b);
-    if (e == hipSuccess) e = hipEventRecord(a, rec_);
+    if (e == hipSuccess) e = hipEventRecord(a, st_);
     if (e == hipSuccess) e = launch();
-    if (e == hipSuccess) e = hipEventRecord(b, rec_);
+    if (e == hipSuccess) e = hipEventRecord(b, st_);
     if (e == hipSuccess) {
       phases_.push_back(phase);
       ++used_;
@@ -219,8 +203,7 @@ class PhaseTimer {
   }
   float *ms_;
   int32_t *n_;
-  hipStream_t st_, rec_;
-  bool dry_ = false;
+  hipStream_t st_;
   size_t used_ = 0;
   std::vector<int> phases_;
 };
@@ -419,10 +402,10 @@ int omp_solve(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y,
 
   hipError_t e = hipSuccess;
   bool done = false;
-  if (opts->use_graph) {
-    // The whole solve replayed from a hipGraph cached under every argument
-    // (and, when timed, the calling thread's event pool, which the captured
-    // event records write to). On the first use the launches are captured.
+  if (opts->use_graph && !timer.on()) {
+    // The whole solve replayed from a hipGraph cached under every argument. On
+    // the first use the launches are captured. (A timed call launches directly:
+    // events recorded by graph nodes cannot be read back with elapsed times.)
     struct Key {
       const void *A, *Y, *X, *sup, *Sp, *Ep, *st_out, *rn_out, *coef, *dmem, *ws, *pool;
       int64_t M, N, lda, B, ldy;
@@ -441,7 +424,7 @@ int omp_solve(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y,
     key.coef = opts->coef_out;
     key.dmem = opts->dict ? opts->dict->mem : nullptr;
     key.ws = opts->workspace;
-    key.pool = timer.on() ? PhaseTimer::pool_id() : nullptr;
+    key.pool = nullptr;
     key.M = M;
     key.N = N;
     key.lda = lda;
@@ -450,36 +433,22 @@ int omp_solve(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y,
     key.S = S;
     key.prec = prec;
     key.cfg = cfg;
-    key.timed = timer.on() ? 1 : 0;
+    key.timed = 0;
     std::memcpy(&key.eps_bits, &eps, sizeof(float));
-    const size_t launches = (opts->dict ? 0 : 2) + 2 + 3 * (size_t)S;
-    e = timer.reserve(launches);  // events exist before any capture
-    if (e == hipSuccess) {
+    {
       const DictView dp = opts->dict ? dict_view(opts->dict->mem, M, N, prec)
                                      : dict_view(static_cast<char *>(opts->workspace) + wneed, M, N, prec);
       e = prepare_kernels(dp, work_view(opts->workspace, M, N, B, S, prec, cfg), prec, 0);
     }
-    bool captured = false;
     if (e == hipSuccess)
       e = graph_launch_cached(std::string(reinterpret_cast<const char *>(&key), sizeof(key)),
-                              [&](hipStream_t cs) {
-                                captured = true;
-                                timer.record_on(cs);
-                                return enqueue(cs);
-                              },
-                              st);
+                              [&](hipStream_t cs) { return enqueue(cs); }, st);
     if (e == hipSuccess) {
-      if (!captured) {  // cache hit: note the phases of the recorded events
-        timer.set_dry(true);
-        e = enqueue(st);
-        timer.set_dry(false);
-      }
-      done = e == hipSuccess;
+      done = true;
     } else {
       (void)hipGetLastError();  // a failed capture falls back to direct launches
       e = hipSuccess;
     }
-    timer.record_on(st);
   }
   if (!done) {
     timer.reset();
