@@ -569,7 +569,7 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
   // ---- round 1: state, residual norms, keys, support, u (none of these
   // addresses depends on another load)
   int fl = w.flags[b];
-  const int k = w.k[b];
+  const int k = __builtin_amdgcn_readfirstlane(w.k[b]);  // wave-uniform: scalar loop bounds
   const double pn = lane < NSLICE_MAX ? w.pnorm[b * NSLICE_MAX + lane] : 0.0;
   const double pd = (BF16 && lane < NSLICE_MAX) ? w.pdelta[b * NSLICE_MAX + lane] : 0.0;
   // Every stop found below leaves through the `stop` label with these set, so
@@ -693,45 +693,57 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
     z[p] = 0.f;
   }
 
-  // 4. Forward solve V_{k-1} z = g, column by column. Columns are read from
-  //    LDS four at a time, one block ahead of the columns being applied.
+  // 4. Forward solve V_{k-1} z = g, column by column. Column j is applied as
+  //    g_i -= (V_ij / V_jj) g_j on every lane: the column is read masked to the
+  //    rows j < i < k (other lanes add zero) and scaled by the reciprocal
+  //    diagonal while the previous block is applied, so a column costs one
+  //    broadcast and one FMA on the critical path. Finally z_i = g_i / V_ii.
+  //    Columns are handled four at a time, the loop rounded up to a whole
+  //    block (columns j >= k are all zero).
   {
     constexpr int QB = 4;
     float va[QB][RPL], vx[QB][RPL];
 #pragma unroll
-    for (int q = 0; q < QB; ++q)
+    for (int q = 0; q < QB; ++q) {
+      const float rj = readlane(pick(rd, q >> 6), q & 63);
 #pragma unroll
       for (int p = 0; p < RPL; ++p) {
         const int i = lane + 64 * p;
-        va[q][p] = (i > q && i < k) ? Vs[tri[p] + q] : 0.f;
+        const bool in = i > q && i < k;
+        const float v = Vs[in ? tri[p] + q : 0];
+        va[q][p] = in ? v * rj : 0.f;
       }
+    }
     for (int j0 = 0; j0 < k; j0 += QB) {
 #pragma unroll
       for (int q = 0; q < QB; ++q)
 #pragma unroll
         for (int p = 0; p < RPL; ++p) {
           const int i = lane + 64 * p, j = j0 + QB + q;
-          vx[q][p] = (i > j && i < k) ? Vs[tri[p] + j] : 0.f;
+          const bool in = i > j && i < k;
+          vx[q][p] = Vs[in ? tri[p] + j : 0];
         }
 #pragma unroll
       for (int q = 0; q < QB; ++q) {
         const int j = j0 + q;
-        if (j < k) {
-          const int pj = j >> 6, jl = j & 63;
-          const float zj = readlane(pick(g, pj), jl) * readlane(pick(rd, pj), jl);
-          if (lane == jl) put(z, pj, zj);
+        const float gj = readlane(pick(g, j >> 6), j & 63);
 #pragma unroll
-          for (int p = 0; p < RPL; ++p) {
-            const int i = lane + 64 * p;
-            if (i > j && i < k) g[p] = fmaf(-va[q][p], zj, g[p]);
-          }
-        }
+        for (int p = 0; p < RPL; ++p) g[p] = fmaf(-va[q][p], gj, g[p]);
       }
 #pragma unroll
-      for (int q = 0; q < QB; ++q)
+      for (int q = 0; q < QB; ++q) {
+        const int j = j0 + QB + q;
+        const int jc = j < 64 * RPL ? j : 0;
+        const float rj = readlane(pick(rd, jc >> 6), jc & 63);
 #pragma unroll
-        for (int p = 0; p < RPL; ++p) va[q][p] = vx[q][p];
+        for (int p = 0; p < RPL; ++p) {
+          const int i = lane + 64 * p;
+          va[q][p] = (i > j && i < k) ? vx[q][p] * rj : 0.f;
+        }
+      }
     }
+#pragma unroll
+    for (int p = 0; p < RPL; ++p) z[p] = g[p] * rd[p];  // rd is 0 on rows >= k
   }
 
   // 5. Pivot d^2 = ||a_n*||^2 - ||z||^2 in FP64.
@@ -775,56 +787,66 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
   wave_lds_sync();
   const int K = k + 1;
 
-  // 8. Back solve V_K^T x = u, last unknown first; row j-1 is read while row j
-  //    is applied.
+  // 8. Back solve V_K^T x = u, last unknown first. Row j is applied as
+  //    t_i -= (V_ji / V_jj) t_j on every lane (the row is read masked to
+  //    i < j and scaled while the previous block is applied); finally
+  //    x_i = t_i / V_ii. Rows are handled four at a time from the top of the
+  //    block holding row K-1 (rows j >= K are all zero).
   float t[RPL], x[RPL];
 #pragma unroll
   for (int p = 0; p < RPL; ++p) {
     const int i = lane + 64 * p;
     t[p] = i < k ? uo[p] : (i == k ? uk : 0.f);
-    x[p] = 0.f;
   }
   {
-    // rows are read from LDS four at a time, one block ahead of those applied
     constexpr int QB = 4;
+    const int jt = ((K + QB - 1) / QB) * QB - 1;  // top row of the first block
     float va[QB][RPL], vx[QB][RPL];
 #pragma unroll
-    for (int q = 0; q < QB; ++q)
+    for (int q = 0; q < QB; ++q) {
+      const int j = jt - q;
+      const bool row = j < K;
+      const float rj = readlane(pick(rd, j >> 6), j & 63);
 #pragma unroll
       for (int p = 0; p < RPL; ++p) {
-        const int i = lane + 64 * p, j = K - 1 - q;
-        va[q][p] = (j >= 0 && i < j) ? Vs[j * (j + 1) / 2 + i] : 0.f;
+        const int i = lane + 64 * p;
+        const bool in = row && i < j;
+        const float v = Vs[in ? j * (j + 1) / 2 + i : 0];
+        va[q][p] = in ? v * rj : 0.f;
       }
-    for (int j0 = K - 1; j0 >= 0; j0 -= QB) {
+    }
+    for (int j0 = jt; j0 >= 0; j0 -= QB) {
 #pragma unroll
       for (int q = 0; q < QB; ++q)
 #pragma unroll
         for (int p = 0; p < RPL; ++p) {
           const int i = lane + 64 * p, j = j0 - QB - q;
-          vx[q][p] = (j >= 0 && i < j) ? Vs[j * (j + 1) / 2 + i] : 0.f;
+          const bool in = j >= 0 && i < j;
+          vx[q][p] = Vs[in ? j * (j + 1) / 2 + i : 0];
         }
 #pragma unroll
       for (int q = 0; q < QB; ++q) {
         const int j = j0 - q;
-        if (j >= 0) {
-          const int pj = j >> 6, jl = j & 63;
-          const float xj = readlane(pick(t, pj), jl) * readlane(pick(rd, pj), jl);
-          if (lane == jl) put(x, pj, xj);
+        const float tj = readlane(pick(t, j >> 6), j & 63);
 #pragma unroll
-          for (int p = 0; p < RPL; ++p) {
-            const int i = lane + 64 * p;
-            if (i < j) t[p] = fmaf(-va[q][p], xj, t[p]);
-          }
-        }
+        for (int p = 0; p < RPL; ++p) t[p] = fmaf(-va[q][p], tj, t[p]);
       }
 #pragma unroll
-      for (int q = 0; q < QB; ++q)
+      for (int q = 0; q < QB; ++q) {
+        const int j = j0 - QB - q;
+        const int jc = j >= 0 ? j : 0;
+        const float rj = readlane(pick(rd, jc >> 6), jc & 63);
 #pragma unroll
-        for (int p = 0; p < RPL; ++p) va[q][p] = vx[q][p];
+        for (int p = 0; p < RPL; ++p) {
+          const int i = lane + 64 * p;
+          va[q][p] = (j >= 0 && i < j) ? vx[q][p] * rj : 0.f;
+        }
+      }
     }
   }
 #pragma unroll
   for (int p = 0; p < RPL; ++p) {
+    x[p] = t[p] * rd[p];  // rd is 0 on rows >= K
     const int i = lane + 64 * p;
     if (i < K) w.xh[b * S + i] = x[p];
   }
@@ -939,7 +961,7 @@ __global__ __launch_bounds__(256) void k_finalize(WorkView w, int64_t N, float *
   __shared__ float xs[OMP_MAX_S];
   const int64_t b = blockIdx.x;
   const int S = w.S;
-  const int k = w.k[b];
+  const int k = __builtin_amdgcn_readfirstlane(w.k[b]);  // wave-uniform: scalar loop bounds
   for (int j = threadIdx.x; j < S; j += blockDim.x) {
     const int sj = j < k ? w.sup[b * S + j] : -1;
     const float xj = j < k ? w.xh[b * S + j] : 0.f;
