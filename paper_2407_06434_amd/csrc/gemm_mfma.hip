@@ -145,10 +145,29 @@ __global__ __launch_bounds__(T::NTHR) void k_corr_select(
         iv[i][4 * g + 2] = v.z;
         iv[i][4 * g + 3] = v.w;
       }
+    // Keys are staged in LDS as [signal of the tile][KPT] (the main loop ends
+    // with a barrier, so the LDS is free) and written out row by row below:
+    // each signal's KPT keys are contiguous in `part`.
+    uint64_t *stage = reinterpret_cast<uint64_t *>(lds);
 #pragma unroll
     for (int j = 0; j < T::FB; ++j) {
-      const int64_t b = b0 + wb * T::FB * 32 + j * 32 + (lane & 31);
-      uint64_t *dst = part + b * ((int64_t)ntile * KPT) + (int64_t)tn * KPT;
+      const int jt = wb * T::FB * 32 + j * 32 + (lane & 31);  // signal within the tile
+      const int64_t b = b0 + jt;
+      // selected-atom bits of this signal for the wavefront's FN * 32 atoms
+      uint32_t mw[T::FN];
+      {
+        const uint32_t *mrow = mask + b * mwords + (nw0 >> 5);
+        if (T::FN == 4) {
+          const uint4 v = *reinterpret_cast<const uint4 *>(mrow);
+          mw[0] = v.x;
+          mw[T::FN > 1 ? 1 : 0] = v.y;
+          mw[T::FN > 2 ? 2 : 0] = v.z;
+          mw[T::FN > 3 ? 3 : 0] = v.w;
+        } else {
+#pragma unroll
+          for (int i = 0; i < T::FN; ++i) mw[i] = mrow[i];
+        }
+      }
 #pragma unroll
       for (int ig = 0; ig < SPH; ++ig) {
         uint32_t k1 = 0, k2 = 0, k3 = 0;
@@ -170,19 +189,25 @@ __global__ __launch_bounds__(T::NTHR) void k_corr_select(
           }
         }
         const uint32_t ks[3] = {k1, k2, k3};
+        const uint32_t w0 = mw[ig * SUBF], w1 = mw[ig * SUBF + SUBF - 1];
 #pragma unroll
         for (int q = 0; q < NKEEP; ++q) {
           const int loc = 31 - (int)(ks[q] & 31u);   // ii * 16 + r
           const int ii = loc >> 4, r = loc & 15;
           const int row = 8 * (r >> 2) + 4 * h + (r & 3);
           const int64_t n = nw0 + (ig * SUBF + ii) * 32 + row;
-          const bool valid = inv_nu[n] > 0.f && !((mask[b * mwords + (n >> 5)] >> (n & 31)) & 1u);
+          const uint32_t word = ii ? w1 : w0;
+          const bool valid = inv_nu[n] > 0.f && !((word >> row) & 1u);
           const uint64_t score = (uint64_t)(ks[q] & ~31u) << 32;
-          dst[((wn * SPH + ig) * 2 + h) * NKEEP + q] =
+          stage[jt * KPT + ((wn * SPH + ig) * 2 + h) * NKEEP + q] =
               score | (valid ? (uint64_t)(0xFFFFFFFFu - (uint32_t)n) : 0ull);
         }
       }
     }
+    __syncthreads();
+    uint64_t *dst = part + b0 * ((int64_t)ntile * KPT) + (int64_t)tn * KPT;
+    for (int t = threadIdx.x; t < T::TB * KPT; t += T::NTHR)
+      dst[(int64_t)(t / KPT) * ntile * KPT + t % KPT] = stage[t];
     return;
   }
 

@@ -6,11 +6,15 @@
 // A workgroup computes a TN x TB tile with WN x WB wavefronts; each wavefront
 // owns FN x FB fragments of 32 x 32 (v_mfma_f32_32x32x2f32 for FP32,
 // v_mfma_f32_32x32x16_bf16 for BF16). Operands are staged through LDS in
-// 128-byte K slices, double buffered; each lane reads 16-byte chunks. Lane l of
-// a fragment reads row (l mod 32) at chunk (2q + l/32) of the slice; the two
-// halves of the wavefront thus supply the two K sub-blocks an MFMA sums over,
-// and both operands use the same K assignment, so the product sums every k
-// exactly once (the order of summation inside an MFMA is the hardware's).
+// 128-byte K slices, double buffered, with direct global-to-LDS loads (16
+// bytes per lane, no register round trip). A staged row is 8 chunks of 16
+// bytes; chunk c of row r sits at slot c ^ ((r >> 1) & 7) of the row, so the
+// 16 lanes of one LDS read phase (16 consecutive rows, one chunk) hit 16
+// distinct 4-bank groups. Lane l of a fragment reads row (l mod 32) at chunk
+// (2q + l/32) of the slice; the two halves of the wavefront thus supply the two
+// K sub-blocks an MFMA sums over, and both operands use the same K assignment,
+// so the product sums every k exactly once (the order of summation inside an
+// MFMA is the hardware's).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -46,24 +50,34 @@ struct OpBF16 {
   }
 };
 
+typedef __attribute__((address_space(3))) void lds_void_t;
+
 template <int TN_, int TB_, int WN_, int WB_>
 struct Tile {
   static constexpr int TN = TN_, TB = TB_, WN = WN_, WB = WB_;
   static constexpr int NTHR = WN * WB * 64;
+  static constexpr int NW = WN * WB;  // wavefronts
   static constexpr int FN = TN / (32 * WN);
   static constexpr int FB = TB / (32 * WB);
-  static constexpr int CH = 8;       // 16-byte chunks per row per K slice (128 bytes)
-  static constexpr int RS = CH + 1;  // LDS row stride in chunks (one chunk of padding)
-  static constexpr int A_LD = TN * CH / NTHR;
-  static constexpr int B_LD = TB * CH / NTHR;
-  static constexpr int STAGE = (TN + TB) * RS;  // chunks per LDS buffer
+  static constexpr int CH = 8;                 // 16-byte chunks per row per K slice (128 bytes)
+  static constexpr int ROWS = TN + TB;         // staged rows per slice (P rows, then Q rows)
+  static constexpr int STAGE = ROWS * CH;      // chunks per LDS buffer
+  static constexpr int LPW = ROWS / (8 * NW);  // global-to-LDS loads per wavefront per slice (8 rows each)
   static constexpr size_t LDS_BYTES = 2 * STAGE * 16;
   static_assert(FN >= 1 && FB >= 1, "tile too small for the wavefront grid");
-  static_assert(TN * CH % NTHR == 0 && TB * CH % NTHR == 0, "loads must divide evenly");
+  static_assert(ROWS % (8 * NW) == 0 && TN % 8 == 0, "loads must divide evenly");
 };
+
+// Slot of chunk c in staged row r.
+__device__ inline int lds_slot(int r, int c) { return c ^ ((r >> 1) & 7); }
 
 // Main loop: acc += P_tile * Q_tile^T over `nslices` K slices of 128 bytes.
 // P points at the tile's first row, rows `prs` chunks apart; likewise Q.
+// Wavefront w stages rows 8 (i NW + w) .. +7 of every slice with its load i: a
+// load writes 64 consecutive LDS chunks (lane l -> chunk l), so lane l fetches
+// row 8 (i NW + w) + l/8, chunk lds_slot(row, l mod 8). The loads of slice s+1
+// are issued right after the barrier that opens slice s and land while slice s
+// is multiplied. Ends with a barrier, so the caller may reuse the LDS.
 template <class Op, class T>
 __device__ inline void mainloop(const u32x4 *__restrict__ P, int64_t prs, const u32x4 *__restrict__ Q,
                                 int64_t qrs, int nslices, u32x4 *lds, f32x16 (&acc)[T::FN][T::FB]) {
@@ -77,73 +91,60 @@ __device__ inline void mainloop(const u32x4 *__restrict__ P, int64_t prs, const 
 #pragma unroll
     for (int j = 0; j < T::FB; ++j) acc[i][j] = f32x16{};
 
-  u32x4 ra[T::A_LD], rb[T::B_LD];
-  // Stage 0: global -> registers -> LDS buffer 0.
+  // Source of this lane's chunk for each of its loads, at slice 0.
+  const u32x4 *src[T::LPW];
 #pragma unroll
-  for (int i = 0; i < T::A_LD; ++i) {
-    const int idx = tid + i * T::NTHR;
-    ra[i] = P[(int64_t)(idx / T::CH) * prs + (idx % T::CH)];
+  for (int i = 0; i < T::LPW; ++i) {
+    const int row = (i * T::NW + wave) * 8 + (lane >> 3);
+    const int c = lds_slot(row, lane & 7);  // the slot map is an involution
+    src[i] = row < T::TN ? P + (int64_t)row * prs + c : Q + (int64_t)(row - T::TN) * qrs + c;
   }
 #pragma unroll
-  for (int i = 0; i < T::B_LD; ++i) {
-    const int idx = tid + i * T::NTHR;
-    rb[i] = Q[(int64_t)(idx / T::CH) * qrs + (idx % T::CH)];
+  for (int i = 0; i < T::LPW; ++i)
+    __builtin_amdgcn_global_load_lds(reinterpret_cast<const void *>(src[i]),
+                                     (lds_void_t *)(lds + (i * T::NW + wave) * 64), 16, 0, 0);
+
+  // LDS offsets (chunks) of this lane's fragment rows and their slot swizzles.
+  int aoff[T::FN], asw[T::FN], boff[T::FB], bsw[T::FB];
+#pragma unroll
+  for (int i = 0; i < T::FN; ++i) {
+    const int row = wn * T::FN * 32 + i * 32 + r32;
+    aoff[i] = row * T::CH;
+    asw[i] = (row >> 1) & 7;
   }
 #pragma unroll
-  for (int i = 0; i < T::A_LD; ++i) {
-    const int idx = tid + i * T::NTHR;
-    lds[(idx / T::CH) * T::RS + (idx % T::CH)] = ra[i];
+  for (int j = 0; j < T::FB; ++j) {
+    const int row = T::TN + wb * T::FB * 32 + j * 32 + r32;
+    boff[j] = row * T::CH;
+    bsw[j] = (row >> 1) & 7;
   }
-#pragma unroll
-  for (int i = 0; i < T::B_LD; ++i) {
-    const int idx = tid + i * T::NTHR;
-    lds[T::TN * T::RS + (idx / T::CH) * T::RS + (idx % T::CH)] = rb[i];
-  }
-  __syncthreads();
+
   for (int s = 0; s < nslices; ++s) {
     const int buf = s & 1;
-    const bool more = s + 1 < nslices;
-    if (more) {  // prefetch slice s+1 into registers while slice s is multiplied
+    __builtin_amdgcn_s_waitcnt(0);  // this wavefront's loads of slice s have landed ...
+    __syncthreads();                // ... and everyone's; slice s-1 is no longer read
+    if (s + 1 < nslices) {
 #pragma unroll
-      for (int i = 0; i < T::A_LD; ++i) {
-        const int idx = tid + i * T::NTHR;
-        ra[i] = P[(int64_t)(idx / T::CH) * prs + (int64_t)(s + 1) * T::CH + (idx % T::CH)];
-      }
-#pragma unroll
-      for (int i = 0; i < T::B_LD; ++i) {
-        const int idx = tid + i * T::NTHR;
-        rb[i] = Q[(int64_t)(idx / T::CH) * qrs + (int64_t)(s + 1) * T::CH + (idx % T::CH)];
-      }
+      for (int i = 0; i < T::LPW; ++i)
+        __builtin_amdgcn_global_load_lds(reinterpret_cast<const void *>(src[i] + (int64_t)(s + 1) * T::CH),
+                                         (lds_void_t *)(lds + (buf ^ 1) * T::STAGE + (i * T::NW + wave) * 64),
+                                         16, 0, 0);
     }
-    const u32x4 *la = lds + buf * T::STAGE + (wn * T::FN * 32 + r32) * T::RS + h;
-    const u32x4 *lb = lds + buf * T::STAGE + T::TN * T::RS + (wb * T::FB * 32 + r32) * T::RS + h;
+    const u32x4 *L = lds + buf * T::STAGE;
 #pragma unroll
     for (int q = 0; q < T::CH / 2; ++q) {
       u32x4 af[T::FN], bf[T::FB];
 #pragma unroll
-      for (int i = 0; i < T::FN; ++i) af[i] = la[i * 32 * T::RS + 2 * q];
+      for (int i = 0; i < T::FN; ++i) af[i] = L[aoff[i] + ((2 * q + h) ^ asw[i])];
 #pragma unroll
-      for (int j = 0; j < T::FB; ++j) bf[j] = lb[j * 32 * T::RS + 2 * q];
+      for (int j = 0; j < T::FB; ++j) bf[j] = L[boff[j] + ((2 * q + h) ^ bsw[j])];
 #pragma unroll
       for (int i = 0; i < T::FN; ++i)
 #pragma unroll
         for (int j = 0; j < T::FB; ++j) Op::mma(af[i], bf[j], acc[i][j]);
     }
-    if (more) {
-      u32x4 *nb = lds + (buf ^ 1) * T::STAGE;
-#pragma unroll
-      for (int i = 0; i < T::A_LD; ++i) {
-        const int idx = tid + i * T::NTHR;
-        nb[(idx / T::CH) * T::RS + (idx % T::CH)] = ra[i];
-      }
-#pragma unroll
-      for (int i = 0; i < T::B_LD; ++i) {
-        const int idx = tid + i * T::NTHR;
-        nb[T::TN * T::RS + (idx / T::CH) * T::RS + (idx % T::CH)] = rb[i];
-      }
-    }
-    __syncthreads();
   }
+  __syncthreads();
 }
 
 // Row of a 32x32 MFMA result held by (lane, register r): the column is lane % 32.
