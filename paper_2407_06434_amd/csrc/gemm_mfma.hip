@@ -145,6 +145,14 @@ __global__ __launch_bounds__(T::NTHR) void k_corr_select(
         iv[i][4 * g + 2] = v.z;
         iv[i][4 * g + 3] = v.w;
       }
+    // When every atom of the wavefront's rows has a non-zero norm (no zero or
+    // padding atom), a key's validity needs only the selected-atom mask.
+    bool rows_ok = true;
+#pragma unroll
+    for (int i = 0; i < T::FN; ++i)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) rows_ok = rows_ok && iv[i][r] > 0.f;
+    const bool all_rows_ok = __builtin_amdgcn_ballot_w64(!rows_ok) == 0;
     // Keys are staged in LDS as [signal of the tile][KPT] (the main loop ends
     // with a barrier, so the LDS is free) and written out row by row below:
     // each signal's KPT keys are contiguous in `part`.
@@ -197,7 +205,7 @@ __global__ __launch_bounds__(T::NTHR) void k_corr_select(
           const int row = 8 * (r >> 2) + 4 * h + (r & 3);
           const int64_t n = nw0 + (ig * SUBF + ii) * 32 + row;
           const uint32_t word = ii ? w1 : w0;
-          const bool valid = inv_nu[n] > 0.f && !((word >> row) & 1u);
+          const bool valid = (all_rows_ok || inv_nu[n] > 0.f) && !((word >> row) & 1u);
           const uint64_t score = (uint64_t)(ks[q] & ~31u) << 32;
           stage[jt * KPT + ((wn * SPH + ig) * 2 + h) * NKEEP + q] =
               score | (valid ? (uint64_t)(0xFFFFFFFFu - (uint32_t)n) : 0ull);
