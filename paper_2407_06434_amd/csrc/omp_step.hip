@@ -13,7 +13,11 @@
 //   z    = V_{k-1}^{-1} g                 (forward solve, Eq. 5)
 //   d    = sqrt(||a_n*||^2 - ||z||^2)     (new pivot, Eq. 5; FP64 subtraction)
 //   V_k  = [[V_{k-1}, 0], [z^T, d]]       (append one row)
-//   beta = a_n*^T y                       (append to A_k^T y, Eq. 2)
+//   beta = a_n*^T y                       (append to A_k^T y, Eq. 2), evaluated
+//        = a_n*^T r + g^T x_{k-1}         as the exact score of the pick plus the
+//                                         Gram row times the current coefficients
+//                                         (r = y - A_{k-1} x_{k-1}), so that only
+//                                         a_n* and r are read
 //   u_k  = (beta - z^T u_{k-1}) / d       (forward solve V_k u = A_k^T y, one new entry)
 //   x    = V_k^{-T} u                     (back solve)
 //
@@ -111,13 +115,14 @@ __device__ inline double dot4d(const float4 &a, const float4 &v) {
   return (double)a.x * v.x + (double)a.y * v.y + (double)a.z * v.z + (double)a.w * v.w;
 }
 
-// FP64 dot products of up to NA atoms (n[i] < 0: unused) with the vector v
-// and, when TWO, also with y: exact products, FP64 accumulation. The whole
-// wavefront cooperates; each lane keeps CP 16-byte chunks of every operand in
-// flight per pass, and the reductions run interleaved.
-template <int NA, bool TWO, int CP>
-__device__ __attribute__((always_inline)) inline void atom_dots(const DictView &d, const int (&n)[NA], const float4 *__restrict__ v4,
-                                 const float4 *__restrict__ y4, int lane, double (&av)[NA], double (&ay)[NA]) {
+// FP64 dot products of up to NA atoms (n[i] < 0: unused) with the vector v:
+// exact products, FP64 accumulation. The whole wavefront cooperates; each lane
+// keeps CP 16-byte chunks of every operand in flight per pass, and the
+// reductions run interleaved.
+template <int NA, int CP>
+__device__ __attribute__((always_inline)) inline void atom_dots(const DictView &d, const int (&n)[NA],
+                                                                const float4 *__restrict__ v4, int lane,
+                                                                double (&av)[NA]) {
   const int64_t nc4 = d.Mp / 4;
   const float4 *A4 = reinterpret_cast<const float4 *>(d.A32);
   // Every load reads a valid address (unused atoms read row 0, chunks past the
@@ -131,9 +136,9 @@ __device__ __attribute__((always_inline)) inline void atom_dots(const DictView &
     row[i] = (int64_t)(use[i] ? n[i] : 0) * nc4;
   }
 #pragma unroll
-  for (int i = 0; i < NA; ++i) av[i] = ay[i] = 0.0;
+  for (int i = 0; i < NA; ++i) av[i] = 0.0;
   for (int64_t c0 = 0; c0 < nc4; c0 += 64 * CP) {
-    float4 vv[CP], yy[CP], aa[NA][CP];
+    float4 vv[CP], aa[NA][CP];
     bool ok[CP];
 #pragma unroll
     for (int q = 0; q < CP; ++q) {
@@ -141,7 +146,6 @@ __device__ __attribute__((always_inline)) inline void atom_dots(const DictView &
       ok[q] = c < nc4;
       const int64_t cs = ok[q] ? c : 0;
       vv[q] = v4[cs];
-      if (TWO) yy[q] = y4[cs];
 #pragma unroll
       for (int i = 0; i < NA; ++i) aa[i][q] = A4[row[i] + cs];
     }
@@ -151,19 +155,12 @@ __device__ __attribute__((always_inline)) inline void atom_dots(const DictView &
       for (int q = 0; q < CP; ++q) {
         const double pa = dot4d(aa[i][q], vv[q]);
         av[i] += (use[i] && ok[q]) ? pa : 0.0;
-        if (TWO) {
-          const double py = dot4d(aa[i][q], yy[q]);
-          ay[i] += (use[i] && ok[q]) ? py : 0.0;
-        }
       }
   }
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1)
 #pragma unroll
-    for (int i = 0; i < NA; ++i) {
-      av[i] += __shfl_xor(av[i], o);
-      if (TWO) ay[i] += __shfl_xor(ay[i], o);
-    }
+    for (int i = 0; i < NA; ++i) av[i] += __shfl_xor(av[i], o);
 }
 
 typedef __attribute__((address_space(3))) void lds_void_t;
@@ -189,16 +186,16 @@ __device__ inline void wave_lds_sync() {
 // A flush fetches, in one round with the dot products, each candidate's
 // ||a_n||^2 and Gram row G[n, support] (lane holds rows i = lane + 64 p), so
 // that whichever candidate wins, the solve needs no further memory round.
-// Keeps the best exact score, its atom, its a^T y, ||a||^2 and Gram row.
+// Keeps the best exact score, its atom, its signed a^T r, ||a||^2 and Gram row.
 template <int RPL>
 struct RescoreQueue {
   int n0 = -1, n1 = -1;
   double bs = -1.0;
-  double by = 0.0, bnu2 = 0.0;
+  double bar = 0.0, bnu2 = 0.0;
   int bn = 0x7fffffff;
   float bg[RPL];
-  __device__ __attribute__((always_inline)) void flush(const DictView &d, const float4 *r4, const float4 *y4,
-                                                       const int (&si)[RPL], int k, int lane) {
+  __device__ __attribute__((always_inline)) void flush(const DictView &d, const float4 *r4, const int (&si)[RPL],
+                                                       int k, int lane) {
     if (n0 < 0) return;
     const int n[2] = {n0, n1};
     double nu2[2];
@@ -210,8 +207,8 @@ struct RescoreQueue {
       for (int p = 0; p < RPL; ++p)
         gc[i][p] = (n[i] >= 0 && lane + 64 * p < k) ? d.G[(int64_t)n[i] * d.Np + si[p]] : 0.f;
     }
-    double ar[2], ay[2];
-    atom_dots<2, true, 2>(d, n, r4, y4, lane, ar, ay);
+    double ar[2];
+    atom_dots<2, 2>(d, n, r4, lane, ar);
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       if (n[i] < 0) continue;
@@ -219,7 +216,7 @@ struct RescoreQueue {
       if (better(sc, n[i], bs, bn)) {
         bs = sc;
         bn = n[i];
-        by = ay[i];
+        bar = ar[i];
         bnu2 = nu2[i];
 #pragma unroll
         for (int p = 0; p < RPL; ++p) bg[p] = gc[i][p];
@@ -228,12 +225,12 @@ struct RescoreQueue {
     n0 = n1 = -1;
   }
   __device__ __attribute__((always_inline)) void push(int atom, const DictView &d, const float4 *r4,
-                                                      const float4 *y4, const int (&si)[RPL], int k, int lane) {
+                                                      const int (&si)[RPL], int k, int lane) {
     if (n0 < 0) {
       n0 = atom;
     } else {
       n1 = atom;
-      flush(d, r4, y4, si, k, lane);
+      flush(d, r4, si, k, lane);
     }
   }
 };
@@ -288,17 +285,16 @@ __device__ __attribute__((always_inline)) inline void scan_keys(const uint64_t (
 //      can open: they are listed while the keys are scanned for step 1 and
 //      tested against s_w afterwards.
 // The result is the exact argmax of s over the selectable atoms, ties to the
-// lowest index; *beta, *nu2 and g receive a_n*^T y, ||a_n*||^2 and the Gram
+// lowest index; *cdot, *nu2 and g receive a_n*^T r, ||a_n*||^2 and the Gram
 // row G[n*, support] of the pick (fetched in the same round as its score).
 // kv holds the signal's keys when kreg (read in the first memory round).
 template <int RPL>
 __device__ int select_bf16(const DictView &d, const WorkView &w, int64_t b, float smax, double tau,
-                           const int (&si)[RPL], int k, int lane, int *widened, double *beta, double *nu2,
+                           const int (&si)[RPL], int k, int lane, int *widened, double *cdot, double *nu2,
                            float (&g)[RPL], int *clist, const uint64_t (&kv)[KREG], bool kreg) {
   const int nkeys = w.ntile * w.ncand;
   const uint64_t *keys = w.part + b * nkeys;
   const float4 *r4 = reinterpret_cast<const float4 *>(w.R32) + b * (d.Mp / 4);
-  const float4 *y4 = reinterpret_cast<const float4 *>(w.Yp) + b * (d.Mp / 4);
   const double et = 1.0 / 262144.0;  // 2^-18: the epilogue's rounding of listed scores
   const double thr = (double)smax - 2.0 * tau - et * (double)smax;
   const double mthr = (double)smax - 2.0 * tau;
@@ -322,8 +318,8 @@ __device__ int select_bf16(const DictView &d, const WorkView &w, int64_t b, floa
     }
   }
   wave_lds_sync();
-  for (int i = 0; i < ncand; ++i) q.push(__builtin_amdgcn_readfirstlane(clist[i]), d, r4, y4, si, k, lane);
-  q.flush(d, r4, y4, si, k, lane);
+  for (int i = 0; i < ncand; ++i) q.push(__builtin_amdgcn_readfirstlane(clist[i]), d, r4, si, k, lane);
+  q.flush(d, r4, si, k, lane);
 
   // The listed subgroups (all bounding keys if the list overflowed) against
   // the exact winner; an open subgroup is re-scored whole.
@@ -346,11 +342,11 @@ __device__ int select_bf16(const DictView &d, const WorkView &w, int64_t b, floa
         for (int e = 0; e < 4; ++e) {
           const int n = tile * w.tile_atoms + wn * w.wave_atoms + 32 * (ig * w.sub_frags + ii) + 8 * g4 + 4 * hh + e;
           if (d.inv_nu[n] <= 0.f || ((mk[n >> 5] >> (n & 31)) & 1u)) continue;
-          q.push(n, d, r4, y4, si, k, lane);
+          q.push(n, d, r4, si, k, lane);
         }
-    q.flush(d, r4, y4, si, k, lane);
+    q.flush(d, r4, si, k, lane);
   }
-  *beta = q.by;
+  *cdot = q.bar;
   *nu2 = q.bnu2;
 #pragma unroll
   for (int p = 0; p < RPL; ++p) g[p] = q.bg[p];
@@ -578,12 +574,13 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
   double rn = 0.0;
   {
   int si[RPL];
-  float uo[RPL];
+  float uo[RPL], xo[RPL];
 #pragma unroll
   for (int p = 0; p < RPL; ++p) {
     const int i = lane + 64 * p;
     si[p] = i < S ? w.sup[b * S + i] : 0;  // only entries below k are meaningful
     uo[p] = i < S ? w.u[b * S + i] : 0.f;
+    xo[p] = i < S ? w.xh[b * S + i] : 0.f;
   }
   const int nkeys = w.ntile * w.ncand;
   const uint64_t *keys = w.part + b * nkeys;
@@ -636,7 +633,7 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
   }
 #pragma unroll
   for (int p = 0; p < RPL; ++p)
-    if (lane + 64 * p >= k) uo[p] = 0.f;
+    if (lane + 64 * p >= k) uo[p] = xo[p] = 0.f;
 
   // ---- round 2: the packed factor straight into LDS (asynchronous
   // global-to-LDS loads: no registers, no wait until it is read) ...
@@ -650,16 +647,17 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
 
   // ... and the pick: the best key over all atom tiles (largest score, then
   // lowest index), or in the BF16 form the certified exact re-score of the
-  // candidates; beta = a_n*^T y (exact products, FP64 sum). In the FP32 form
+  // candidates; cdot = a_n*^T r (exact products, FP64 sum). In the FP32 form
   // the Gram row of the pick, g_i = G[n*, support_i] (lane holds rows
   // i = lane + 64 p), and ||a_n*||^2 are fetched in this same round.
   int nstar;
   int widened = 0;
-  double beta = 0.0, nu2 = 0.0;
+  double cdot = 0.0, nu2 = 0.0;
   float g[RPL];
+  const float4 *r4 = reinterpret_cast<const float4 *>(w.R32) + b * (d.Mp / 4);
   if (BF16) {
     const double tau = bf16_tau(rn, sqrt(wave_sum(pd)), (double)d.aerr_max[0], d.Mp);
-    nstar = select_bf16<RPL>(d, w, b, __uint_as_float((uint32_t)(kmax >> 32)), tau, si, k, lane, &widened, &beta,
+    nstar = select_bf16<RPL>(d, w, b, __uint_as_float((uint32_t)(kmax >> 32)), tau, si, k, lane, &widened, &cdot,
                              &nu2, g, clist, kv, kreg);
     if (nstar < 0) {
       stopfl = fl | FLAG_DONE | OMP_SIG_EXHAUSTED;
@@ -674,11 +672,15 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
       g[p] = i < k ? d.G[(int64_t)nstar * d.Np + si[p]] : 0.f;
     }
     const int na[1] = {nstar};
-    double ay[1], unused[1];
-    atom_dots<1, false, 4>(d, na, reinterpret_cast<const float4 *>(w.Yp) + b * (d.Mp / 4), nullptr, lane, ay,
-                           unused);
-    beta = ay[0];
+    double ar[1];
+    atom_dots<1, 4>(d, na, r4, lane, ar);
+    cdot = ar[0];
   }
+  // beta = a_n*^T y = a_n*^T r + sum_j G[n*, s_j] x_j (r = y - A_{k-1} x_{k-1})
+  double gx = 0.0;
+#pragma unroll
+  for (int p = 0; p < RPL; ++p) gx += (double)g[p] * (double)xo[p];
+  const double beta = cdot + wave_sum(gx);
   if (widened) fl |= OMP_SIG_WIDENED;
   __builtin_amdgcn_s_waitcnt(0);  // the global-to-LDS loads have landed
   wave_lds_sync();
