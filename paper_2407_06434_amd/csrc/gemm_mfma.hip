@@ -92,13 +92,14 @@ __device__ inline void xcd_tile(int b, int nta, int ntb, int *tn, int *tb) {
 // TOP2 = false (FP32 form): one key per (signal, tile), the tile's winner.
 // TOP2 = true  (BF16 form): each lane keeps, for each "subgroup" of the atoms
 //   it holds for its signal (16 atoms per fragment, SUBF fragments), the three
-//   best scores and writes them as three keys. Inside the loop a candidate is
-//   a 32-bit key (bits(s) with its low 5 bits replaced by 31 - local index),
-//   so keeping the best three is a max and two medians of three; the dropped bits
-//   change s by less than 2^-18 relative, which the certificate accounts for.
-//   All atoms of the subgroup compete; only when the keys are written are
-//   selected, zero-norm and padding atoms marked invalid (low word 0), so the
-//   third key still bounds every atom of the subgroup that is not listed.
+//   best scores and writes them as three keys. A key is 32 bits: bits(s) with
+//   its low 5 bits replaced by 31 - local index, so keeping the best three is a
+//   max and two medians of three; the dropped bits change s by less than 2^-18
+//   relative, which the certificate accounts for. The key's slot gives the
+//   subgroup, its low bits the atom within it. All atoms of the subgroup
+//   compete; only when the keys are written are selected, zero-norm and padding
+//   atoms marked invalid (bit 31 set; s >= 0 leaves that bit free), so the third
+//   key still bounds every atom of the subgroup that is not listed.
 // ---------------------------------------------------------------------------
 template <class Op, class T, bool TOP2>
 __global__ __launch_bounds__(T::NTHR) void k_corr_select(
@@ -155,8 +156,8 @@ __global__ __launch_bounds__(T::NTHR) void k_corr_select(
     const bool all_rows_ok = __builtin_amdgcn_ballot_w64(!rows_ok) == 0;
     // Keys are staged in LDS as [signal of the tile][KPT] (the main loop ends
     // with a barrier, so the LDS is free) and written out row by row below:
-    // each signal's KPT keys are contiguous in `part`.
-    uint64_t *stage = reinterpret_cast<uint64_t *>(lds);
+    // each signal's KPT keys are contiguous in `part` (32-bit keys).
+    uint32_t *stage = reinterpret_cast<uint32_t *>(lds);
 #pragma unroll
     for (int j = 0; j < T::FB; ++j) {
       const int jt = wb * T::FB * 32 + j * 32 + (lane & 31);  // signal within the tile
@@ -206,14 +207,12 @@ __global__ __launch_bounds__(T::NTHR) void k_corr_select(
           const int64_t n = nw0 + (ig * SUBF + ii) * 32 + row;
           const uint32_t word = ii ? w1 : w0;
           const bool valid = (all_rows_ok || inv_nu[n] > 0.f) && !((word >> row) & 1u);
-          const uint64_t score = (uint64_t)(ks[q] & ~31u) << 32;
-          stage[jt * KPT + ((wn * SPH + ig) * 2 + h) * NKEEP + q] =
-              score | (valid ? (uint64_t)(0xFFFFFFFFu - (uint32_t)n) : 0ull);
+          stage[jt * KPT + ((wn * SPH + ig) * 2 + h) * NKEEP + q] = valid ? ks[q] : (ks[q] | 0x80000000u);
         }
       }
     }
     __syncthreads();
-    uint64_t *dst = part + b0 * ((int64_t)ntile * KPT) + (int64_t)tn * KPT;
+    uint32_t *dst = reinterpret_cast<uint32_t *>(part) + b0 * ((int64_t)ntile * KPT) + (int64_t)tn * KPT;
     for (int t = threadIdx.x; t < T::TB * KPT; t += T::NTHR)
       dst[(int64_t)(t / KPT) * ntile * KPT + t % KPT] = stage[t];
     return;

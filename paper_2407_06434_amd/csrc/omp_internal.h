@@ -159,8 +159,8 @@ hipError_t launch_finalize(const DictView &d, const WorkView &w, float *X_out,
 constexpr int NKEEP = 3;
 
 // Tile configuration and output structure of the correlation product.
-//   FP32: one key per (signal, tile): the tile's best atom.
-//   BF16: NKEEP keys (best BF16 scores, descending) per (signal, subgroup). The
+//   FP32: one 64-bit key per (signal, tile): the tile's best atom.
+//   BF16: NKEEP 32-bit keys (best BF16 scores, descending) per (signal, subgroup). The
 //         lane holding signal j in wavefront row wn, half h (lane / 32) owns,
 //         for fragment i, the atoms 32 i + 8 g + 4 h + e (g, e < 4) of its rows;
 //         subgroup ig of that lane is fragments ig*sub_frags .. +sub_frags-1.

@@ -243,22 +243,43 @@ constexpr int MAYBE_CAP = 32;
 // Ints of the candidate list (room for every key, a multiple of 4).
 __host__ __device__ inline int64_t solve_cand_len(int64_t nkeys) { return (nkeys + 3) / 4 * 4; }
 
+// BF16 keys (32 bits): the BF16 score's bits with the low five replaced by
+// 31 - loc (loc = the atom's place in its 32-atom subgroup), bit 31 set when
+// the atom is selected, zero-norm or padding. Key slot t of a signal belongs
+// to subgroup (t / NKEEP) of the correlation tile's layout.
+__device__ inline bool key_valid(uint32_t key) { return !(key >> 31); }
+__device__ inline double key_score(uint32_t key) { return (double)__uint_as_float(key & 0x7FFFFFE0u); }
+__device__ inline int key_loc(uint32_t key) { return 31 - (int)(key & 31u); }
+
+// Atom of subgroup slot `t` (tile t / ncand, subgroup ((wn * subs_per_half +
+// ig) * 2 + h) within it) at place loc = ii * 16 + r: the epilogue's row
+// 8 (r / 4) + 4 h + r % 4 of fragment ig * sub_frags + ii of wavefront row wn.
+__device__ inline int key_atom(const WorkView &w, int t, int loc) {
+  const int tile = t / w.ncand;
+  const int sgl = (t % w.ncand) / NKEEP;
+  const int hh = sgl & 1;
+  const int ig = (sgl >> 1) % w.subs_per_half;
+  const int wn = (sgl >> 1) / w.subs_per_half;
+  const int ii = loc >> 4, r = loc & 15;
+  return tile * w.tile_atoms + wn * w.wave_atoms + 32 * (ig * w.sub_frags + ii) + 8 * (r >> 2) + 4 * hh + (r & 3);
+}
+
 // One batch of keys (KB per lane, key t0 + 64 j + lane in kb[j]): candidates
 // (valid, score >= thr) are appended to clist, subgroups whose bounding key
 // could reach the exact winner (theta (1 + et) >= mthr) to mlist.
 template <int KB>
-__device__ __attribute__((always_inline)) inline void scan_keys(const uint64_t (&kb)[KB], int t0, int nkeys,
+__device__ __attribute__((always_inline)) inline void scan_keys(const uint32_t (&kb)[KB], int t0, int nkeys,
                                                                 double thr, double mthr, double et, int *clist,
                                                                 int *mlist, int &ncand, int &nmaybe) {
 #pragma unroll
   for (int j = 0; j < KB; ++j) {
     const int t = t0 + 64 * j + (int)(threadIdx.x & 63);
-    const double sc = (double)__uint_as_float((uint32_t)(kb[j] >> 32));
-    const bool cand = (kb[j] & 0xFFFFFFFFull) && sc >= thr;
+    const double sc = key_score(kb[j]);
+    const bool cand = key_valid(kb[j]) && sc >= thr;
     const uint64_t m = __ballot(cand);
     const int pos = ncand + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-    if (cand) clist[pos] = (int)(0xFFFFFFFFu - (uint32_t)(kb[j] & 0xFFFFFFFFull));
+    if (cand) clist[pos] = t * 32 + key_loc(kb[j]);
     ncand += __popcll(m);
     const bool maybe = t < nkeys && (t % NKEEP) == NKEEP - 1 && sc * (1.0 + et) >= mthr;
     const uint64_t mm = __ballot(maybe);
@@ -291,9 +312,9 @@ __device__ __attribute__((always_inline)) inline void scan_keys(const uint64_t (
 template <int RPL>
 __device__ int select_bf16(const DictView &d, const WorkView &w, int64_t b, float smax, double tau,
                            const int (&si)[RPL], int k, int lane, int *widened, double *cdot, double *nu2,
-                           float (&g)[RPL], int *clist, const uint64_t (&kv)[KREG], bool kreg) {
+                           float (&g)[RPL], int *clist, const uint32_t (&kv)[KREG], bool kreg) {
   const int nkeys = w.ntile * w.ncand;
-  const uint64_t *keys = w.part + b * nkeys;
+  const uint32_t *keys = reinterpret_cast<const uint32_t *>(w.part) + b * nkeys;
   const float4 *r4 = reinterpret_cast<const float4 *>(w.R32) + b * (d.Mp / 4);
   const double et = 1.0 / 262144.0;  // 2^-18: the epilogue's rounding of listed scores
   const double thr = (double)smax - 2.0 * tau - et * (double)smax;
@@ -307,18 +328,21 @@ __device__ int select_bf16(const DictView &d, const WorkView &w, int64_t b, floa
     scan_keys<KREG>(kv, 0, nkeys, thr, mthr, et, clist, mlist, ncand, nmaybe);
   } else {
     for (int t0 = 0; t0 < nkeys; t0 += 64 * KREG) {
-      uint64_t kb[KREG];
+      uint32_t kb[KREG];
 #pragma unroll
       for (int j = 0; j < KREG; ++j) {
         const int t = t0 + 64 * j + lane;
-        const uint64_t v = keys[t < nkeys ? t : 0];
-        kb[j] = t < nkeys ? v : 0ull;
+        const uint32_t v = keys[t < nkeys ? t : 0];
+        kb[j] = t < nkeys ? v : 0x80000000u;
       }
       scan_keys<KREG>(kb, t0, nkeys, thr, mthr, et, clist, mlist, ncand, nmaybe);
     }
   }
   wave_lds_sync();
-  for (int i = 0; i < ncand; ++i) q.push(__builtin_amdgcn_readfirstlane(clist[i]), d, r4, si, k, lane);
+  for (int i = 0; i < ncand; ++i) {
+    const int e = __builtin_amdgcn_readfirstlane(clist[i]);
+    q.push(key_atom(w, e >> 5, e & 31), d, r4, si, k, lane);
+  }
   q.flush(d, r4, si, k, lane);
 
   // The listed subgroups (all bounding keys if the list overflowed) against
@@ -329,7 +353,7 @@ __device__ int select_bf16(const DictView &d, const WorkView &w, int64_t b, floa
   const int npass = movf ? nkeys / NKEEP : nmaybe;
   for (int i = 0; i < npass; ++i) {
     const int slot = movf ? i * NKEEP + NKEEP - 1 : __builtin_amdgcn_readfirstlane(mlist[i]);
-    const double theta = (double)__uint_as_float((uint32_t)(keys[slot] >> 32));
+    const double theta = key_score(keys[slot]);
     if (!(theta * (1.0 + et) + tau >= q.bs)) continue;
     const int tile = slot / w.ncand;
     const int sgl = (slot % w.ncand) / NKEEP;  // ((wn * subs_per_half + ig) * 2 + h)
@@ -583,22 +607,37 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
     xo[p] = i < S ? w.xh[b * S + i] : 0.f;
   }
   const int nkeys = w.ntile * w.ncand;
-  const uint64_t *keys = w.part + b * nkeys;
-  uint64_t kmax = 0;  // largest valid key (a valid key has a non-zero index word)
+  // FP32 form: the largest valid 64-bit key (a valid key has a non-zero index
+  // word). BF16 form: (score bits << 32) | 1 of the best valid 32-bit key.
+  uint64_t kmax = 0;
   // BF16 form: up to 64 KREG keys stay in registers for the pick
-  uint64_t kv[KREG];
+  uint32_t kv[KREG];
   const bool kreg = BF16 && nkeys <= 64 * KREG;
-  if (kreg) {
+  if (BF16) {
+    const uint32_t *keys = reinterpret_cast<const uint32_t *>(w.part) + b * nkeys;
+    if (kreg) {
 #pragma unroll
-    for (int j = 0; j < KREG; ++j) {
-      const int t = 64 * j + lane;
-      const uint64_t v = keys[t < nkeys ? t : 0];
-      kv[j] = t < nkeys ? v : 0ull;
-      kmax = ((kv[j] & 0xFFFFFFFFull) && kv[j] > kmax) ? kv[j] : kmax;
+      for (int j = 0; j < KREG; ++j) {
+        const int t = 64 * j + lane;
+        const uint32_t v = keys[t < nkeys ? t : 0];
+        kv[j] = t < nkeys ? v : 0x80000000u;
+        const uint64_t m = ((uint64_t)(kv[j] & ~31u) << 32) | 1ull;
+        kmax = (key_valid(kv[j]) && m > kmax) ? m : kmax;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < KREG; ++j) kv[j] = 0x80000000u;
+#pragma unroll 4
+      for (int t = lane; t < nkeys; t += 64) {
+        const uint32_t v = keys[t];
+        const uint64_t m = ((uint64_t)(v & ~31u) << 32) | 1ull;
+        kmax = (key_valid(v) && m > kmax) ? m : kmax;
+      }
     }
   } else {
 #pragma unroll
-    for (int j = 0; j < KREG; ++j) kv[j] = 0ull;
+    for (int j = 0; j < KREG; ++j) kv[j] = 0x80000000u;
+    const uint64_t *keys = w.part + b * nkeys;
 #pragma unroll 4
     for (int t = lane; t < nkeys; t += 64) {
       const uint64_t v = keys[t];
