@@ -228,3 +228,42 @@ def test_graph_replays_match_direct_launches(prec):
             assert timing["corr"][1] == w.S and timing["update"][1] == w.S and timing["residual"][1] == w.S
             assert timing["init"][1] == 1 and timing["output"][1] == 1
             assert all(v[0] > 0 for k, v in timing.items() if v[1] > 0)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_many_atom_tiles_keys_read_in_batches(orc, prec):
+    """N = 8192 gives 768 BF16 keys per signal, more than the solve keeps in registers,
+    so the pick reads its keys again in batches; sampled signals against the oracle."""
+    from paper_2407_06434_amd import workloads
+    w = workloads.custom(256, 8192, 256, 16, seed=21, k_true=12)
+    print(f"case many tiles M=256 N=8192 B=256 S=16 {prec}", flush=True)
+    out = run_gpu(w, prec)
+    idx = np.random.default_rng(2).choice(w.B, 24, replace=False)
+    rep = parity.check(w, out, orc, idx=idx)
+    print(rep)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_clustered_atoms(orc, prec):
+    """Atoms in tight clusters: 32 copies of each of 64 directions, perturbed by 1e-3 of
+    their norm. In the BF16 form the rounding exceeds the gaps between copies, so picks
+    re-score many candidates, subgroups open and the list of possibly open subgroups can
+    overflow; every pick must still be the exact argmax (near-ties below 1e-5 allowed)."""
+    from paper_2407_06434_amd import workloads
+    g = np.random.default_rng(31)
+    M, base, copies, B = 128, 64, 32, 64
+    D = g.normal(size=(base, M))
+    D /= np.linalg.norm(D, axis=1, keepdims=True)
+    A = np.repeat(D, copies, axis=0) + 1e-3 * g.normal(size=(base * copies, M)) / np.sqrt(M)
+    Y = np.zeros((B, M))
+    for b in range(B):
+        atoms = g.choice(base * copies, 4, replace=False)
+        Y[b] = (1.0 + g.random(4)) @ A[atoms] + 1e-3 * g.normal(size=M)
+    w = workloads.Workload("clustered_128x2048", A.astype(np.float32), Y.astype(np.float32), 8, 0.0)
+    print(f"case clustered atoms {prec}", flush=True)
+    out = run_gpu(w, prec)
+    rep = parity.check(w, out, orc)
+    widened = int(np.sum(out["status"] & 64 != 0))
+    print(rep, "widened signals", widened)
+    if prec == "bf16":
+        assert widened > 0
