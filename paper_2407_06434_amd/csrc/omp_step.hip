@@ -988,6 +988,18 @@ __global__ __launch_bounds__(256) void k_residual(DictView d, WorkView w, int LP
   }
 }
 
+// Zero n floats from `row` with the block's threads: 16-byte stores when the
+// row is 16-byte aligned and n a multiple of 4, else 4-byte stores.
+__device__ inline void zero_row(float *row, int64_t n) {
+  if ((n & 3) == 0 && (reinterpret_cast<uintptr_t>(row) & 15) == 0) {
+    float4 *r4 = reinterpret_cast<float4 *>(row);
+    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int64_t c = threadIdx.x; c < n / 4; c += blockDim.x) r4[c] = z;
+  } else {
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) row[i] = 0.f;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Outputs: one 256-thread block per signal. The stop reason follows the
 // oracle's order: a NONFINITE, DEPENDENT or EXHAUSTED stop is reported alone;
@@ -1012,16 +1024,11 @@ __global__ __launch_bounds__(256) void k_finalize(WorkView w, int64_t N, float *
     if (coef_out) coef_out[b * S + j] = xj;
   }
   __syncthreads();
-  if (X_out) {
-    const int64_t mwords = w.Np / 32;
-    for (int64_t n = threadIdx.x; n < N; n += blockDim.x) {
-      float v = 0.f;
-      if ((w.mask[b * mwords + n / 32] >> (n & 31)) & 1u) {
-        for (int j = 0; j < k; ++j)
-          if (ss[j] == n) v = xs[j];
-      }
-      X_out[b * N + n] = v;
-    }
+  if (X_out) {  // zero the row, then scatter the k coefficients (the barrier orders the two)
+    float *row = X_out + b * N;
+    zero_row(row, N);
+    __syncthreads();
+    for (int j = threadIdx.x; j < k; j += blockDim.x) row[ss[j]] = xs[j];
   }
   if (threadIdx.x == 0) {
     const int fl = w.flags[b];
@@ -1050,7 +1057,7 @@ hipError_t allow_lds(K kernel, size_t bytes) {
 __global__ __launch_bounds__(256) void k_densify(const int32_t *__restrict__ support, const float *__restrict__ coef,
                                                  int S, int64_t N, float *__restrict__ X_out) {
   const int64_t b = blockIdx.x;
-  for (int64_t n = threadIdx.x; n < N; n += blockDim.x) X_out[b * N + n] = 0.f;
+  zero_row(X_out + b * N, N);
   __syncthreads();
   for (int j = threadIdx.x; j < S; j += blockDim.x) {
     const int n = support[b * S + j];
