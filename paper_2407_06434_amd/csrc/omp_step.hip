@@ -442,19 +442,50 @@ __device__ void init_column(const WorkView &w, int64_t b, const float *__restric
                             float eb, int idle, int lane) {
   double s = 0.0, dl = 0.0;
   int finite = 1;
-  for (int64_t m = lane; m < w.Mp; m += 64) {
-    const float v = (y && m < M) ? y[m] : 0.f;
-    finite &= isfinite(v) ? 1 : 0;
-    const float vz = isfinite(v) ? v : 0.f;
-    w.Yp[b * w.Mp + m] = vz;
-    w.R32[b * w.Mp + m] = vz;
-    if (w.R16) {
-      const uint16_t h = f32_to_bf16_rne(vz);
-      w.R16[b * w.Mp + m] = h;
-      const double dv = (double)vz - (double)__uint_as_float((uint32_t)h << 16);
-      dl += dv * dv;
+  if ((M & 3) == 0 && (reinterpret_cast<uintptr_t>(y) & 15) == 0) {
+    // 16-byte chunks (a chunk lies wholly inside or wholly past the signal)
+    const float4 *y4 = reinterpret_cast<const float4 *>(y);
+    float4 *Y4 = reinterpret_cast<float4 *>(w.Yp + b * w.Mp);
+    float4 *R4 = reinterpret_cast<float4 *>(w.R32 + b * w.Mp);
+    for (int64_t c = lane; c < w.Mp / 4; c += 64) {
+      float4 v = (y && 4 * c < M) ? y4[c] : make_float4(0.f, 0.f, 0.f, 0.f);
+      finite &= (isfinite(v.x) && isfinite(v.y) && isfinite(v.z) && isfinite(v.w)) ? 1 : 0;
+      v.x = isfinite(v.x) ? v.x : 0.f;
+      v.y = isfinite(v.y) ? v.y : 0.f;
+      v.z = isfinite(v.z) ? v.z : 0.f;
+      v.w = isfinite(v.w) ? v.w : 0.f;
+      Y4[c] = v;
+      R4[c] = v;
+      if (w.R16) {
+        ushort4 h;
+        h.x = f32_to_bf16_rne(v.x);
+        h.y = f32_to_bf16_rne(v.y);
+        h.z = f32_to_bf16_rne(v.z);
+        h.w = f32_to_bf16_rne(v.w);
+        reinterpret_cast<ushort4 *>(w.R16 + b * w.Mp)[c] = h;
+        const double d0 = (double)v.x - (double)__uint_as_float((uint32_t)h.x << 16);
+        const double d1 = (double)v.y - (double)__uint_as_float((uint32_t)h.y << 16);
+        const double d2 = (double)v.z - (double)__uint_as_float((uint32_t)h.z << 16);
+        const double d3 = (double)v.w - (double)__uint_as_float((uint32_t)h.w << 16);
+        dl += d0 * d0 + d1 * d1 + d2 * d2 + d3 * d3;
+      }
+      s += (double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z + (double)v.w * v.w;
     }
-    s += (double)vz * (double)vz;
+  } else {
+    for (int64_t m = lane; m < w.Mp; m += 64) {
+      const float v = (y && m < M) ? y[m] : 0.f;
+      finite &= isfinite(v) ? 1 : 0;
+      const float vz = isfinite(v) ? v : 0.f;
+      w.Yp[b * w.Mp + m] = vz;
+      w.R32[b * w.Mp + m] = vz;
+      if (w.R16) {
+        const uint16_t h = f32_to_bf16_rne(vz);
+        w.R16[b * w.Mp + m] = h;
+        const double dv = (double)vz - (double)__uint_as_float((uint32_t)h << 16);
+        dl += dv * dv;
+      }
+      s += (double)vz * (double)vz;
+    }
   }
   const int64_t mwords = w.Np / 32;
   for (int64_t t = lane; t < mwords; t += 64) w.mask[b * mwords + t] = 0u;
