@@ -267,26 +267,41 @@ __device__ inline int key_atom(const WorkView &w, int t, int loc) {
 // One batch of keys (KB per lane, key t0 + 64 j + lane in kb[j]): candidates
 // (valid, score >= thr) are appended to clist, subgroups whose bounding key
 // could reach the exact winner (theta (1 + et) >= mthr) to mlist.
+// Bits of the largest float <= x, for x >= 0 (0 for x <= 0): a score s (a
+// non-negative float, compared through its bits, which order like the values)
+// satisfies s >= x exactly when bits(s) >= this, up to the floats in
+// [result, x), which are taken as well.
+__device__ inline uint32_t float_bits_floor(double x) {
+  if (!(x > 0.0)) return 0u;
+  float f = (float)x;
+  if ((double)f > x) f = __uint_as_float(__float_as_uint(f) - 1u);
+  return __float_as_uint(f);
+}
+
 template <int KB>
 __device__ __attribute__((always_inline)) inline void scan_keys(const uint32_t (&kb)[KB], int t0, int nkeys,
-                                                                double thr, double mthr, double et, int *clist,
+                                                                uint32_t thr_bits, uint32_t mthr_bits, int *clist,
                                                                 int *mlist, int &ncand, int &nmaybe) {
 #pragma unroll
   for (int j = 0; j < KB; ++j) {
     const int t = t0 + 64 * j + (int)(threadIdx.x & 63);
-    const double sc = key_score(kb[j]);
-    const bool cand = key_valid(kb[j]) && sc >= thr;
+    const uint32_t sb = kb[j] & 0x7FFFFFE0u;  // score bits
+    const bool cand = key_valid(kb[j]) && sb >= thr_bits;
     const uint64_t m = __ballot(cand);
-    const int pos = ncand + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                           __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-    if (cand) clist[pos] = t * 32 + key_loc(kb[j]);
-    ncand += __popcll(m);
-    const bool maybe = t < nkeys && (t % NKEEP) == NKEEP - 1 && sc * (1.0 + et) >= mthr;
+    if (m) {
+      const int pos = ncand + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+      if (cand) clist[pos] = t * 32 + key_loc(kb[j]);
+      ncand += __popcll(m);
+    }
+    const bool maybe = t < nkeys && (t % NKEEP) == NKEEP - 1 && sb >= mthr_bits;
     const uint64_t mm = __ballot(maybe);
-    const int mpos = nmaybe + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mm >> 32),
-                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)mm, 0u));
-    if (maybe && mpos < MAYBE_CAP) mlist[mpos] = t;
-    nmaybe += __popcll(mm);
+    if (mm) {
+      const int mpos = nmaybe + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mm >> 32),
+                                                               __builtin_amdgcn_mbcnt_lo((uint32_t)mm, 0u));
+      if (maybe && mpos < MAYBE_CAP) mlist[mpos] = t;
+      nmaybe += __popcll(mm);
+    }
   }
 }
 
@@ -319,13 +334,17 @@ __device__ int select_bf16(const DictView &d, const WorkView &w, int64_t b, floa
   const double et = 1.0 / 262144.0;  // 2^-18: the epilogue's rounding of listed scores
   const double thr = (double)smax - 2.0 * tau - et * (double)smax;
   const double mthr = (double)smax - 2.0 * tau;
+  // the same tests on score bits: s >= thr, and s (1 + et) >= mthr taken as
+  // s >= mthr / (1 + et) lowered by 1e-12 relative (a superset of the list)
+  const uint32_t thr_bits = float_bits_floor(thr);
+  const uint32_t mthr_bits = float_bits_floor(mthr / (1.0 + et) * (1.0 - 1e-12));
   int *mlist = clist + solve_cand_len(nkeys);
   RescoreQueue<RPL> q;
   // Candidates and possibly open subgroups, from the keys in registers or, for
   // more keys than that, read again KREG per lane at a time.
   int ncand = 0, nmaybe = 0;
   if (kreg) {
-    scan_keys<KREG>(kv, 0, nkeys, thr, mthr, et, clist, mlist, ncand, nmaybe);
+    scan_keys<KREG>(kv, 0, nkeys, thr_bits, mthr_bits, clist, mlist, ncand, nmaybe);
   } else {
     for (int t0 = 0; t0 < nkeys; t0 += 64 * KREG) {
       uint32_t kb[KREG];
@@ -335,7 +354,7 @@ __device__ int select_bf16(const DictView &d, const WorkView &w, int64_t b, floa
         const uint32_t v = keys[t < nkeys ? t : 0];
         kb[j] = t < nkeys ? v : 0x80000000u;
       }
-      scan_keys<KREG>(kb, t0, nkeys, thr, mthr, et, clist, mlist, ncand, nmaybe);
+      scan_keys<KREG>(kb, t0, nkeys, thr_bits, mthr_bits, clist, mlist, ncand, nmaybe);
     }
   }
   wave_lds_sync();
