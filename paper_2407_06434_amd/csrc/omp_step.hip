@@ -194,23 +194,22 @@ struct RescoreQueue {
   double bar = 0.0, bnu2 = 0.0;
   int bn = 0x7fffffff;
   float bg[RPL];
-  __device__ __attribute__((always_inline)) void flush(const DictView &d, const float4 *r4, const int (&si)[RPL],
-                                                       int k, int lane) {
-    if (n0 < 0) return;
-    const int n[2] = {n0, n1};
-    double nu2[2];
-    float gc[2][RPL];
+  template <int NA>
+  __device__ __attribute__((always_inline)) void rescore(const DictView &d, const float4 *r4, const int (&n)[NA],
+                                                         const int (&si)[RPL], int k, int lane) {
+    double nu2[NA];
+    float gc[NA][RPL];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < NA; ++i) {
       nu2[i] = n[i] >= 0 ? d.nu2[n[i]] : 1.0;
 #pragma unroll
       for (int p = 0; p < RPL; ++p)
         gc[i][p] = (n[i] >= 0 && lane + 64 * p < k) ? d.G[(int64_t)n[i] * d.Np + si[p]] : 0.f;
     }
-    double ar[2];
-    atom_dots<2, 2>(d, n, r4, lane, ar);
+    double ar[NA];
+    atom_dots<NA, 2>(d, n, r4, lane, ar);
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < NA; ++i) {
       if (n[i] < 0) continue;
       const double sc = fabs(ar[i]) / sqrt(nu2[i]);
       if (better(sc, n[i], bs, bn)) {
@@ -221,6 +220,17 @@ struct RescoreQueue {
 #pragma unroll
         for (int p = 0; p < RPL; ++p) bg[p] = gc[i][p];
       }
+    }
+  }
+  __device__ __attribute__((always_inline)) void flush(const DictView &d, const float4 *r4, const int (&si)[RPL],
+                                                       int k, int lane) {
+    if (n0 < 0) return;
+    if (n1 < 0) {  // a single atom: half the loads and dot products
+      const int n[1] = {n0};
+      rescore<1>(d, r4, n, si, k, lane);
+    } else {
+      const int n[2] = {n0, n1};
+      rescore<2>(d, r4, n, si, k, lane);
     }
     n0 = n1 = -1;
   }
