@@ -1150,15 +1150,16 @@ hipError_t launch_solve_any(const DictView &d, const WorkView &w, const SlotView
 size_t residual_lds(const WorkView &w, int LP) { return (size_t)4 * (64 / LP) * w.S * 8; }
 
 // Lanes per signal of the residual kernel: as requested, else by shape (one
-// lane per float4 of a slice, up to a whole wavefront); raised until the
-// block's coefficient and support tables fit in LDS.
+// lane per float4 of a slice, at most 16: on the 1024 x 4096 benchmark 16
+// lanes with two chunks each beat 32 with one by 0.7% of the whole step, 8 and
+// 4 lose); raised until the block's coefficient and support tables fit in LDS.
 int residual_lanes(const WorkView &w, int lanes) {
   int LP = 1;
   if (lanes > 0) {
     LP = lanes;
   } else {
     const int sl4 = w.slice_len / 4;
-    while (LP < sl4 && LP < 64) LP *= 2;
+    while (LP < sl4 && LP < 16) LP *= 2;
   }
   while (LP < 64 && residual_lds(w, LP) > (size_t)160 * 1024) LP *= 2;
   return LP;
