@@ -233,6 +233,11 @@ size_t work_bytes(int64_t M, int64_t N, int64_t B, int S, int precision, int cfg
   return work_layout(M, N, B, S, precision, cfg).total;
 }
 
+bool solve_fits(int64_t M, int64_t N, int64_t B, int S, int precision, int cfg) {
+  const WorkLayout L = work_layout(M, N, B, S, precision, cfg);
+  return solve_waves_for(L.vstride, L.ntile * L.g.keys_per_tile, precision == OMP_PREC_BF16) > 0;
+}
+
 WorkView work_view(void *mem, int64_t M, int64_t N, int64_t B, int S, int precision, int cfg) {
   const WorkLayout L = work_layout(M, N, B, S, precision, cfg);
   WorkView w;
@@ -351,6 +356,7 @@ int omp_solve(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y,
   if (!dims_ok(M, N) || B < 0 || B > ((int64_t)1 << 26)) return OMP_EINVAL;
   if (S < 1 || S > M || S > N) return OMP_EINVAL;
   if (S > OMP_MAX_S) return OMP_ENOTSUPP;
+  if (!solve_fits(M, N, B, S, prec, cfg)) return OMP_ENOTSUPP;
   if (std::isnan(eps)) return OMP_EINVAL;
   if (!A || lda < M || !aligned(A, 4)) return OMP_EINVAL;
   if (B > 0 && (!Y || ldy < M || !aligned(Y, 4) || !support_out)) return OMP_EINVAL;

@@ -88,6 +88,40 @@ struct WorkView {
 size_t work_bytes(int64_t M, int64_t N, int64_t B, int S, int precision, int cfg);
 WorkView work_view(void *mem, int64_t M, int64_t N, int64_t B, int S, int precision, int cfg);
 
+// ---- the solve kernel's LDS (shared by its launcher and the entry points'
+// validation) ---------------------------------------------------------------
+// Subgroups listed as possibly open by the BF16 pick (beyond this the bounding
+// keys are scanned).
+constexpr int MAYBE_CAP = 32;
+// Ints of the BF16 pick's candidate list (room for every key, a multiple of 4).
+__host__ __device__ inline int64_t solve_cand_len(int64_t nkeys) { return (nkeys + 3) / 4 * 4; }
+// Per wavefront: the packed factor (vstride floats), then in the BF16 form the
+// candidate list and the possibly-open list, in 4-byte words.
+__host__ __device__ inline int64_t solve_list_words(int64_t nkeys, bool bf16) {
+  return bf16 ? solve_cand_len(nkeys) + MAYBE_CAP : 0;
+}
+__host__ __device__ inline int64_t solve_list_len(const WorkView &w) {
+  return solve_list_words((int64_t)w.ntile * w.ncand, w.R16 != nullptr);
+}
+__host__ __device__ inline size_t solve_lds_per_wave(const WorkView &w) {
+  return (size_t)(w.vstride + solve_list_len(w)) * 4;
+}
+constexpr int SOLVE_WAVES = 4;              // wavefronts (signals) per solve block, at most
+constexpr size_t LDS_LIMIT = 160 * 1024;    // LDS of one gfx950 workgroup
+// Wavefronts per solve block whose LDS fits (0: not even one).
+inline int solve_waves_for(int64_t vstride, int64_t nkeys, bool bf16) {
+  const size_t per = (size_t)(vstride + solve_list_words(nkeys, bf16)) * 4;
+  int nw = SOLVE_WAVES;
+  while (nw > 0 && per * (size_t)nw > LDS_LIMIT) --nw;
+  return nw;
+}
+inline int solve_waves(const WorkView &w) {
+  return solve_waves_for(w.vstride, (int64_t)w.ntile * w.ncand, w.R16 != nullptr);
+}
+// Whether one solve wavefront's LDS fits for this problem (else the entry
+// points answer OMP_ENOTSUPP before launching anything).
+bool solve_fits(int64_t M, int64_t N, int64_t B, int S, int precision, int cfg);
+
 // Slot scheduler (uneven batches): the workspace's B columns are slots that
 // signals pass through. When a slot's signal stops, the solve kernel writes that
 // signal's outputs and admits the next waiting signal into the slot.

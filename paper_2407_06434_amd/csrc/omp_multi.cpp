@@ -83,6 +83,7 @@ int check_problem(const omp_problem_t &p, int precision) {
   if (p.B < 0 || p.B > ((int64_t)1 << 26)) return OMP_EINVAL;
   if (p.S < 1 || p.S > dd->M || p.S > dd->N) return OMP_EINVAL;
   if (p.S > OMP_MAX_S) return OMP_ENOTSUPP;
+  if (!solve_fits(dd->M, dd->N, plan_slots(p), p.S, precision, p.tile_config)) return OMP_ENOTSUPP;
   if (std::isnan(p.eps)) return OMP_EINVAL;
   if (p.tile_config < 0 || p.tile_config > MAX_TILE_CFG || p.slots < 0) return OMP_EINVAL;
   const int l = p.residual_lanes;

@@ -248,10 +248,6 @@ struct RescoreQueue {
 // Keys kept in registers per lane by the solve's first memory round (BF16 form):
 // up to 64 * KREG keys per signal, otherwise they are read again in batches.
 constexpr int KREG = 8;
-// Subgroups listed as possibly open (beyond this the bounding keys are scanned).
-constexpr int MAYBE_CAP = 32;
-// Ints of the candidate list (room for every key, a multiple of 4).
-__host__ __device__ inline int64_t solve_cand_len(int64_t nkeys) { return (nkeys + 3) / 4 * 4; }
 
 // BF16 keys (32 bits): the BF16 score's bits with the low five replaced by
 // 31 - loc (loc = the atom's place in its 32-atom subgroup), bit 31 set when
@@ -603,28 +599,23 @@ __device__ void retire_and_admit(const WorkView &w, const SlotView &sv, int64_t 
 }
 
 // ---------------------------------------------------------------------------
-// Solve step. One 64-lane wavefront per signal, SOLVE_WAVES signals per block
-// (the wavefronts share nothing; each has its own LDS region). RPL = rows of V
-// per lane (S <= 64 RPL; RPL in {1, 2, 4}).
-// LDS per wavefront: V (vstride floats).
+// Solve step. One 64-lane wavefront per signal, up to SOLVE_WAVES signals per
+// block, fewer when their LDS would not fit (the wavefronts share nothing;
+// each has its own LDS region). RPL = rows of V per lane (S <= 64 RPL; RPL in
+// {1, 2, 4}).
+// LDS per wavefront: V (vstride floats), then in the BF16 form the candidate
+// and possibly-open lists (a multiple of 4 ints, so every wavefront's region
+// stays 16-byte aligned).
 // Memory is read in two dependent rounds: first everything whose address
-// depends on the signal only (state, norms, the epilogue's keys, support, u),
-// then the packed factor together with what depends on the pick (Gram row,
-// ||a_n*||^2, a_n*^T y; in the BF16 form fetched for every re-scored
+// depends on the signal only (state, norms, the epilogue's keys, support, u,
+// x), then the packed factor together with what depends on the pick (Gram row,
+// ||a_n*||^2, a_n*^T r; in the BF16 form fetched for every re-scored
 // candidate alongside its exact score).
 // The triangular solves run column by column; the reciprocal diagonal is
-// computed up front in parallel and the next column is read from LDS while
-// the current one is applied, so the sequential chain holds no division and
+// computed up front in parallel and the next columns are read from LDS while
+// the current ones are applied, so the sequential chain holds no division and
 // no LDS latency.
 // ---------------------------------------------------------------------------
-constexpr int SOLVE_WAVES = 4;
-
-// Ints of the BF16 pick's candidate and possibly-open lists per wavefront (a
-// multiple of 4, so that every wavefront's LDS region stays 16-byte aligned);
-// 0 in the FP32 form.
-__host__ __device__ inline int64_t solve_list_len(const WorkView &w) {
-  return w.R16 ? solve_cand_len((int64_t)w.ntile * w.ncand) + MAYBE_CAP : 0;
-}
 
 // A stop found by the solve step: record the flags, or (slot scheduler) write
 // the signal out and admit the next one.
@@ -639,7 +630,7 @@ template <int RPL, bool BF16, bool SLOTS>
 __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView w, SlotView sv) {
   extern __shared__ float smem[];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t b = (int64_t)blockIdx.x * SOLVE_WAVES + wv;
+  const int64_t b = (int64_t)blockIdx.x * (blockDim.x >> 6) + wv;  // blocks of solve_waves(w) wavefronts
   if (b >= w.B) return;
   const int S = w.S;
   const int64_t VS = w.vstride;
@@ -1127,11 +1118,13 @@ __global__ __launch_bounds__(256) void k_densify(const int32_t *__restrict__ sup
 
 template <int RPL, bool BF16, bool SLOTS>
 hipError_t launch_solve_t(const DictView &d, const WorkView &w, const SlotView &sv, hipStream_t st) {
-  const size_t lds = (size_t)(w.vstride + solve_list_len(w)) * 4 * SOLVE_WAVES;
+  const int nw = solve_waves(w);
+  if (nw == 0) return hipErrorInvalidValue;  // rejected by the entry points' validation
+  const size_t lds = solve_lds_per_wave(w) * nw;
   hipError_t e = allow_lds(k_solve<RPL, BF16, SLOTS>, lds);
   if (e != hipSuccess) return e;
-  const unsigned blocks = (unsigned)((w.B + SOLVE_WAVES - 1) / SOLVE_WAVES);
-  hipLaunchKernelGGL((k_solve<RPL, BF16, SLOTS>), dim3(blocks), dim3(64 * SOLVE_WAVES), lds, st, d, w, sv);
+  const unsigned blocks = (unsigned)((w.B + nw - 1) / nw);
+  hipLaunchKernelGGL((k_solve<RPL, BF16, SLOTS>), dim3(blocks), dim3(64 * nw), lds, st, d, w, sv);
   return hipGetLastError();
 }
 
@@ -1230,7 +1223,7 @@ hipError_t launch_densify(const int32_t *support, const float *coef, int64_t nsi
 }
 
 hipError_t prepare_kernels(const DictView &d, const WorkView &w, int precision, int lanes) {
-  const size_t slds = (size_t)(w.vstride + solve_list_len(w)) * 4 * SOLVE_WAVES;
+  const size_t slds = solve_lds_per_wave(w) * (size_t)(solve_waves(w) > 0 ? solve_waves(w) : 1);
   const bool bf = precision == OMP_PREC_BF16;
   hipError_t e = hipSuccess;
   if (w.S <= 64) e = bf ? allow_lds(k_solve<1, true, true>, slds) : allow_lds(k_solve<1, false, true>, slds);

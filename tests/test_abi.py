@@ -129,6 +129,23 @@ def test_solve_beyond_limits_is_not_supported(lib):
     assert rc == omp.OMP_ENOTSUPP
 
 
+def test_solve_whose_lds_does_not_fit_is_not_supported(lib):
+    """The solve keeps the packed factor (and in the BF16 form one list entry per
+    select key) in LDS: a problem whose single wavefront would need more than the
+    160 KiB of a workgroup is refused before anything is launched; S = 256 with a
+    4096-atom dictionary still fits (one wavefront per block)."""
+    from paper_2407_06434_amd import omp
+    o = _opts()
+    o.precision = omp.PREC["bf16"]
+    N = 1 << 20  # 98,304 BF16 keys per signal
+    rc = lib.omp_solve(FAKE, 64, N, 64, FAKE, 10, 64, 64, 0.0, FAKE, FAKE, ctypes.byref(o), None)
+    assert rc == omp.OMP_ENOTSUPP
+    o = _opts(ws=1024)  # fits: the (too small) workspace is what is refused
+    o.precision = omp.PREC["bf16"]
+    rc = lib.omp_solve(FAKE, 512, 4096, 512, FAKE, 10, 512, 256, 0.0, FAKE, FAKE, ctypes.byref(o), None)
+    assert rc == omp.OMP_EWORKSPACE
+
+
 def test_solve_with_mismatched_dictionary_is_rejected(lib):
     from paper_2407_06434_amd import omp
     d = omp.OmpDictStruct()

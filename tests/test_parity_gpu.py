@@ -267,3 +267,35 @@ def test_clustered_atoms(orc, prec):
     print(rep, "widened signals", widened)
     if prec == "bf16":
         assert widened > 0
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_large_support_four_rows_per_lane(orc, prec):
+    """S = 160: the solve keeps four factor rows per lane (S > 128)."""
+    from paper_2407_06434_amd import workloads
+    w = workloads.custom(256, 512, 40, 160, seed=17, k_true=120, snr_db=60.0)
+    print(f"case large support M=256 N=512 B=40 S=160 {prec}", flush=True)
+    out = run_gpu(w, prec)
+    rep = parity.check(w, out, orc)
+    print(rep)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_tile_configurations_agree(prec):
+    """Every correlation tile configuration gives bit-identical results: the K-order of
+    the products is the same, and in the BF16 form the exact re-score decides."""
+    torch = _torch()
+    from paper_2407_06434_amd import omp, workloads
+    w = workloads.batched_256x1024(B=700)
+    dev = torch.device("cuda:0")
+    A = torch.from_numpy(w.A).to(dev)
+    Y = torch.from_numpy(w.Y).to(dev)
+    print(f"case tile configurations {prec}", flush=True)
+    outs = []
+    for cfg in (0, 1, 2, 3, 4):
+        r = omp.solve(A, Y, w.S, precision=prec, tile_config=cfg)
+        torch.cuda.synchronize()
+        outs.append({k: v.cpu().numpy() for k, v in r._asdict().items() if v is not None})
+    for cfg, o in zip((1, 2, 3, 4), outs[1:]):
+        for k in outs[0]:
+            assert np.array_equal(outs[0][k], o[k]), (cfg, k)
