@@ -299,3 +299,15 @@ def test_tile_configurations_agree(prec):
     for cfg, o in zip((1, 2, 3, 4), outs[1:]):
         for k in outs[0]:
             assert np.array_equal(outs[0][k], o[k]), (cfg, k)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_largest_support(orc, prec):
+    """S = OMP_MAX_S = 256: four factor rows per lane and one wavefront per solve block
+    (the packed factor alone takes 129 KiB of LDS)."""
+    from paper_2407_06434_amd import workloads
+    w = workloads.custom(320, 640, 6, 256, seed=23, k_true=200, snr_db=60.0)
+    print(f"case largest support M=320 N=640 B=6 S=256 {prec}", flush=True)
+    out = run_gpu(w, prec)
+    rep = parity.check(w, out, orc)
+    print(rep)
