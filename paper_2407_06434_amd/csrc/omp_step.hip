@@ -72,11 +72,6 @@ __device__ inline float pick(const float (&a)[R], int p) {
   for (int i = 1; i < R; ++i) v = (p == i) ? a[i] : v;
   return v;
 }
-template <int R>
-__device__ inline void put(float (&a)[R], int p, float v) {
-#pragma unroll
-  for (int i = 0; i < R; ++i) a[i] = (p == i) ? v : a[i];
-}
 
 __device__ inline float readlane(float v, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
