@@ -163,7 +163,13 @@ size_t omp_workspace_size(int64_t M, int64_t N, int64_t B, int32_t S, const omp_
  *   opts         host, required (workspace).
  * Ties in the argmax go to the lowest atom index. Atoms of zero norm are never
  * selected. Column norms need not be 1: selection divides by ||a_n||, and x is
- * in the scale of the caller's A (Appendix A of the paper). */
+ * in the scale of the caller's A (Appendix A of the paper).
+ * Returns OMP_OK after enqueueing; OMP_EINVAL / OMP_EWORKSPACE for bad
+ * arguments or workspace; OMP_ENOTSUPP when S > OMP_MAX_S or when one signal's
+ * solve state (the packed Cholesky factor, S(S+1)/2 floats, plus in the BF16
+ * form one word per select key, about 6 N / 64) exceeds the 160 KiB of LDS of
+ * a workgroup; OMP_EDEVICE for a HIP error or a device other than gfx950.
+ * Nothing is enqueued when the return is not OMP_OK. */
 int omp_solve(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y, int64_t B,
               int64_t ldy, int32_t S, float eps, float *X_out, int32_t *support_out,
               const omp_opts_t *opts, void *stream);
