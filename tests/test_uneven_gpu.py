@@ -140,3 +140,17 @@ def test_tune_and_determinism():
     for x, y, w in zip(a, b, ws):
         _same(x, y)
         _same(x, _plain(w, "bf16"))
+
+
+def test_slots_with_large_support():
+    """S = 150 through the slot scheduler (three solve wavefronts per block): identical
+    to the plain batched solve with the same per-signal caps."""
+    from paper_2407_06434_amd import workloads
+    w = workloads.custom(256, 512, 300, 150, seed=29, k_true=100, snr_db=60.0)
+    w.S_per_signal = np.random.default_rng(5).integers(100, 151, size=w.B).astype(np.int32)
+    w.eps_per_signal = np.zeros(w.B, np.float32)
+    print("case slots S=150", flush=True)
+    from paper_2407_06434_amd import omp
+    for prec in ("fp32", "bf16"):
+        outs = omp.solve_multi(_problems([w], prec, dense=True, slots=256), precision=prec)
+        _same(_to_np(outs[0]), _plain(w, prec), keys=("support", "coef", "status", "rnorm", "X"))
