@@ -48,19 +48,59 @@ __device__ inline uint16_t f32_to_bf16_rne(float f) {
   return (uint16_t)(u >> 16);
 }
 
+// Cross-lane moves within 16-lane rows by DPP (no LDS round trip): the two
+// 32-bit halves of a 64-bit value move together.
+template <int CTRL>
+__device__ inline uint64_t dpp64(uint64_t v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), CTRL, 0xF, 0xF, false);
+  return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+template <int CTRL>
+__device__ inline double dppd(double v) {
+  return __longlong_as_double((long long)dpp64<CTRL>((uint64_t)__double_as_longlong(v)));
+}
+__device__ inline uint64_t readlane64(uint64_t v, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+  return ((uint64_t)hi << 32) | lo;
+}
+// DPP controls: swap neighbours (quad_perm 1,0,3,2), swap pairs (quad_perm
+// 2,3,0,1), reverse 8 lanes (row_half_mirror), reverse 16 lanes (row_mirror).
+constexpr int DPP_XOR1 = 0xB1, DPP_XOR2 = 0x4E, DPP_HALF_MIRROR = 0x141, DPP_MIRROR = 0x140;
+
+// Sum over the 64 lanes, returned to every lane: each 16-lane row is reduced
+// by four DPP steps (after them every lane of a row holds the row's sum), then
+// the four row sums are read out and added in a fixed order. Must be called
+// with every lane active.
 __device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
-  return v;
+  v += dppd<DPP_XOR1>(v);
+  v += dppd<DPP_XOR2>(v);
+  v += dppd<DPP_HALF_MIRROR>(v);
+  v += dppd<DPP_MIRROR>(v);
+  const double r0 = __longlong_as_double((long long)readlane64((uint64_t)__double_as_longlong(v), 0));
+  const double r1 = __longlong_as_double((long long)readlane64((uint64_t)__double_as_longlong(v), 16));
+  const double r2 = __longlong_as_double((long long)readlane64((uint64_t)__double_as_longlong(v), 32));
+  const double r3 = __longlong_as_double((long long)readlane64((uint64_t)__double_as_longlong(v), 48));
+  return (r0 + r1) + (r2 + r3);
 }
 
 __device__ inline uint64_t wave_max(uint64_t v) {
+  uint64_t w = dpp64<DPP_XOR1>(v);
+  v = w > v ? w : v;
+  w = dpp64<DPP_XOR2>(v);
+  v = w > v ? w : v;
+  w = dpp64<DPP_HALF_MIRROR>(v);
+  v = w > v ? w : v;
+  w = dpp64<DPP_MIRROR>(v);
+  v = w > v ? w : v;
+  uint64_t m = readlane64(v, 0);
 #pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) {
-    const uint64_t w = __shfl_xor(v, o);
-    v = w > v ? w : v;
+  for (int r = 16; r < 64; r += 16) {
+    const uint64_t x = readlane64(v, r);
+    m = x > m ? x : m;
   }
-  return v;
+  return m;
 }
 
 // Select element p (wave-uniform) of a small per-lane register array without
@@ -153,9 +193,7 @@ __device__ __attribute__((always_inline)) inline void atom_dots(const DictView &
       }
   }
 #pragma unroll
-  for (int o = 32; o >= 1; o >>= 1)
-#pragma unroll
-    for (int i = 0; i < NA; ++i) av[i] += __shfl_xor(av[i], o);
+  for (int i = 0; i < NA; ++i) av[i] = wave_sum(av[i]);
 }
 
 typedef __attribute__((address_space(3))) void lds_void_t;
