@@ -1062,7 +1062,13 @@ __global__ __launch_bounds__(256) void k_residual(DictView d, WorkView w, int LP
     }
     nrm += (double)r.x * r.x + (double)r.y * r.y + (double)r.z * r.z + (double)r.w * r.w;
   }
-  for (int o = LP / 2; o >= 1; o >>= 1) {
+  // sum over the item's LP lanes (aligned groups): DPP within rows, then
+  // permutes across rows for LP > 16
+  if (LP >= 2) { nrm += dppd<DPP_XOR1>(nrm); if (BF16) dlt += dppd<DPP_XOR1>(dlt); }
+  if (LP >= 4) { nrm += dppd<DPP_XOR2>(nrm); if (BF16) dlt += dppd<DPP_XOR2>(dlt); }
+  if (LP >= 8) { nrm += dppd<DPP_HALF_MIRROR>(nrm); if (BF16) dlt += dppd<DPP_HALF_MIRROR>(dlt); }
+  if (LP >= 16) { nrm += dppd<DPP_MIRROR>(nrm); if (BF16) dlt += dppd<DPP_MIRROR>(dlt); }
+  for (int o = 16; o < LP; o <<= 1) {
     nrm += __shfl_xor(nrm, o);
     if (BF16) dlt += __shfl_xor(dlt, o);
   }
