@@ -674,6 +674,8 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
   // addresses depends on another load)
   int fl = w.flags[b];
   const int k = __builtin_amdgcn_readfirstlane(w.k[b]);  // wave-uniform: scalar loop bounds
+  const float eps_b = w.epsb[b];  // read here, with the rest of round 1
+  const int S_b = w.Sb[b];
   const double pn = lane < NSLICE_MAX ? w.pnorm[b * NSLICE_MAX + lane] : 0.0;
   const double pd = (BF16 && lane < NSLICE_MAX) ? w.pdelta[b * NSLICE_MAX + lane] : 0.0;
   // Every stop found below leaves through the `stop` label with these set, so
@@ -745,7 +747,7 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
 
   // 0. Stop test on the current residual (Algorithm 1 stops once ||r|| <= eps).
   rn = sqrt(wave_sum(pn));
-  if (rn <= (double)w.epsb[b]) {
+  if (rn <= (double)eps_b) {
     stopfl = fl | FLAG_DONE;
     goto stop;
   }
@@ -907,7 +909,9 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
     w.sup[b * S + k] = nstar;
     w.u[b * S + k] = uk;
     const int64_t mwords = d.Np / 32;
-    w.mask[b * mwords + nstar / 32] |= 1u << (nstar & 31);
+    // no returned value: the wavefront does not wait for this update
+    __hip_atomic_fetch_or(&w.mask[b * mwords + nstar / 32], 1u << (nstar & 31), __ATOMIC_RELAXED,
+                          __HIP_MEMORY_SCOPE_AGENT);
   }
   wave_lds_sync();
   const int K = k + 1;
@@ -979,7 +983,7 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
   // 9. New state; the residual kernel picks the signal up through FLAG_NEWX.
   if (lane == 0) {
     fl |= FLAG_NEWX;
-    if (K >= w.Sb[b]) fl |= FLAG_DONE;
+    if (K >= S_b) fl |= FLAG_DONE;
     w.k[b] = K;
     w.flags[b] = fl;
   }
