@@ -25,7 +25,7 @@
 // ||r||^2 accumulated in FP64 per slice of the signal. The signal is cut into
 // up to 8 slices of M and workgroup i works on slice i mod 8: workgroups are
 // dispatched round-robin over the 8 XCDs, so every XCD only ever gathers its
-// own eighth of the dictionary's columns, which then stays in its L2.
+// own eighth of every atom (one slice of M), which then stays in its L2.
 //
 // The paper's code re-factorised A_k^T A_k at every step and names the
 // Cholesky update as its next step (Section 3.6); this file implements that
