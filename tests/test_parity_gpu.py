@@ -311,3 +311,37 @@ def test_largest_support(orc, prec):
     out = run_gpu(w, prec)
     rep = parity.check(w, out, orc)
     print(rep)
+
+
+def test_random_shapes_sweep(orc):
+    """Sixteen seeded random problems (M in 8..900, N up to 4000, B up to 400, S up to
+    200 but at most the true sparsity, 20-30 dB, both forms, every tile configuration,
+    per-signal S_b and eps_b at random), 12 sampled signals each against the oracle."""
+    torch = _torch()
+    from paper_2407_06434_amd import omp, workloads
+    g = np.random.default_rng(2024)
+    dev = torch.device("cuda:0")
+    for case in range(16):
+        M = int(g.integers(8, 900))
+        N = int(g.integers(M // 2 + 1, 4000))
+        B = int(g.integers(1, 400))
+        S = int(g.integers(1, min(M, N, 200 if M <= 300 else 96) + 1))
+        kt = int(max(1, min(M // 3, S + int(g.integers(0, 4)))))
+        S = min(S, kt)
+        prec = PRECS[case % 2]
+        cfg = int(g.integers(0, 5))
+        w = workloads.custom(M, N, B, S, seed=3000 + case, k_true=kt, snr_db=float(g.choice([20.0, 30.0])))
+        kw = {}
+        if g.random() < 0.3:
+            w.S_per_signal = g.integers(0, S + 1, size=B).astype(np.int32)
+            kw["S_per_signal"] = torch.from_numpy(w.S_per_signal).to(dev)
+        if g.random() < 0.3:
+            w.eps_per_signal = (g.random(B) * 0.5 * np.linalg.norm(w.Y.astype(np.float64), axis=1)).astype(np.float32)
+            kw["eps_per_signal"] = torch.from_numpy(w.eps_per_signal).to(dev)
+        print(f"case {case}: M={M} N={N} B={B} S={S} {prec} cfg={cfg}", flush=True)
+        r = omp.solve(torch.from_numpy(w.A).to(dev), torch.from_numpy(w.Y).to(dev), S, 0.0, precision=prec,
+                      tile_config=cfg, **kw)
+        torch.cuda.synchronize()
+        out = {k: v.cpu().numpy() for k, v in r._asdict().items() if v is not None}
+        rep = parity.check(w, out, orc, idx=np.sort(g.choice(B, min(B, 12), replace=False)))
+        print("   ", rep)
