@@ -175,6 +175,27 @@ def run_gpu(w, precision, steps, warmup):
                 graph_equals_direct=same)
 
 
+def run_per_signal_loop(w, precision, n=32):
+    """Ablation A1 of the paper (batching) on these kernels: the first n signals of the
+    batch solved one call per signal (B = 1, kernels launched one by one, as a host loop
+    over signals would), against the batched step's throughput. Results must equal the
+    batched ones."""
+    import torch
+    from paper_2407_06434_amd import omp
+    dev = torch.device("cuda:0")
+    A = torch.from_numpy(w.A).to(dev)
+    Y = torch.from_numpy(w.Y[:n].copy()).to(dev)
+    d = omp.Dictionary(A, precision)
+    outs = [omp.solve(A, Y[i:i + 1], w.S, w.eps, precision=precision, dictionary=d, graph=False) for i in range(2)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = [omp.solve(A, Y[i:i + 1], w.S, w.eps, precision=precision, dictionary=d, graph=False) for i in range(n)]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sup = np.concatenate([o.support.cpu().numpy() for o in outs])
+    return dict(wall=wall, n=n, support=sup)
+
+
 def run_uneven(precision, steps, warmup, B_each=10000):
     """Uneven batch: two dictionaries (128x512, 512x2048), 10,000 signals each, per-signal
     S_i in 4..64 and eps_i = 1e-2 ||y_i||, solved in one slot-scheduled call after the
@@ -400,6 +421,15 @@ def main():
         line["same_supports_vs_fp32"] = f"{sum(same)}/{w.B}"
         log(f"fp32: {fsps:.0f} signals/s; same supports {sum(same)}/{w.B}")
     line["widened_signals"] = int(np.sum((g["res"]["status"] & 64) != 0))
+    loop = run_per_signal_loop(w, args.precision)
+    loop_sps = loop["n"] / loop["wall"]
+    line["ablation_batching"] = {
+        "per_signal_loop": {"value": round(loop_sps, 1), "unit": "signals/s", "signals": loop["n"]},
+        "batched": {"value": round(sps, 1), "unit": "signals/s"},
+        "speedup": round(sps / loop_sps, 1),
+        "identical_supports": bool(np.array_equal(loop["support"], g["res"]["support"][: loop["n"]])),
+    }
+    log(f"ablation (batching): {line['ablation_batching']}")
 
     if not args.no_uneven:
         u = run_uneven(args.precision, max(3, args.steps // 2), 1)
