@@ -196,6 +196,24 @@ def run_per_signal_loop(w, precision, n=32):
     return dict(wall=wall, n=n, support=sup)
 
 
+def run_gram_on_the_fly(w, precision, steps=3):
+    """Ablation A2 of the paper (Gram precomputation) on these kernels: the same step
+    with each pick's Gram row computed from the atoms instead of read from G."""
+    import torch
+    from paper_2407_06434_amd import omp
+    dev = torch.device("cuda:0")
+    A = torch.from_numpy(w.A).to(dev)
+    Y = torch.from_numpy(w.Y).to(dev)
+    d = omp.Dictionary(A, precision)
+    out = omp.solve(A, Y, w.S, w.eps, precision=precision, dictionary=d, gram_on_the_fly=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = omp.solve(A, Y, w.S, w.eps, precision=precision, dictionary=d, out=out, gram_on_the_fly=True)
+    torch.cuda.synchronize()
+    return dict(wall=(time.perf_counter() - t0) / steps, support=out.support.cpu().numpy())
+
+
 def run_uneven(precision, steps, warmup, B_each=10000):
     """Uneven batch: two dictionaries (128x512, 512x2048), 10,000 signals each, per-signal
     S_i in 4..64 and eps_i = 1e-2 ||y_i||, solved in one slot-scheduled call after the
@@ -430,6 +448,16 @@ def main():
         "identical_supports": bool(np.array_equal(loop["support"], g["res"]["support"][: loop["n"]])),
     }
     log(f"ablation (batching): {line['ablation_batching']}")
+    gf = run_gram_on_the_fly(w, args.precision)
+    same_gf = [set(a.tolist()) == set(b.tolist()) for a, b in zip(gf["support"], g["res"]["support"])]
+    line["ablation_gram"] = {
+        "gram_rows_from_atoms": {"value": round(w.B / gf["wall"], 1), "unit": "signals/s",
+                                 "ms_per_step": round(1e3 * gf["wall"], 3)},
+        "prepared_gram": {"value": round(sps, 1), "unit": "signals/s"},
+        "speedup": round(sps / (w.B / gf["wall"]), 2),
+        "same_supports": f"{sum(same_gf)}/{w.B}",
+    }
+    log(f"ablation (Gram): {line['ablation_gram']}")
 
     if not args.no_uneven:
         u = run_uneven(args.precision, max(3, args.steps // 2), 1)

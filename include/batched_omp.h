@@ -130,6 +130,10 @@ typedef struct omp_opts {
                                    argument set (every pointer and size of the call), and replayed
                                    with one graph launch; 0: the kernels are launched one by one.
                                    A call with phase_ms set always launches one by one. */
+  int32_t gram_on_the_fly;      /* ablation A2 of the paper (measurement only): 1 = the solve
+                                   computes the Gram row A_S^T a_n* of each pick from the atoms
+                                   (exact products, FP64 sums) instead of reading the prepared
+                                   Gram matrix; 0 (default) reads it. Other values: OMP_EINVAL. */
 } omp_opts_t;
 
 /* Phases reported through omp_opts_t.phase_ms. */

@@ -271,6 +271,7 @@ WorkView work_view(void *mem, int64_t M, int64_t N, int64_t B, int S, int precis
   w.u = at<float>(mem, L.u);
   w.xh = at<float>(mem, L.xh);
   w.V = at<float>(mem, L.V);
+  w.gram_fly = 0;
   return w;
 }
 
@@ -353,6 +354,7 @@ int omp_solve(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y,
   if (prec != OMP_PREC_FP32 && prec != OMP_PREC_BF16) return OMP_EINVAL;
   const int cfg = opts->tile_config;
   if (cfg < 0 || cfg > MAX_TILE_CFG) return OMP_EINVAL;
+  if (opts->gram_on_the_fly != 0 && opts->gram_on_the_fly != 1) return OMP_EINVAL;
   if (!dims_ok(M, N) || B < 0 || B > ((int64_t)1 << 26)) return OMP_EINVAL;
   if (S < 1 || S > M || S > N) return OMP_EINVAL;
   if (S > OMP_MAX_S) return OMP_ENOTSUPP;
@@ -390,7 +392,8 @@ int omp_solve(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y,
       if (e == hipSuccess) e = timer.run(OMP_PHASE_DICT, [&] { return launch_gram(d, cs); });
       if (e != hipSuccess) return e;
     }
-    const WorkView w = work_view(opts->workspace, M, N, B, S, prec, cfg);
+    WorkView w = work_view(opts->workspace, M, N, B, S, prec, cfg);
+    w.gram_fly = opts->gram_on_the_fly;
     e = timer.run(OMP_PHASE_INIT, [&] {
       return launch_init(Y, ldy, opts->S_per_signal, opts->eps_per_signal, eps, d, w, prec, cs);
     });
@@ -415,7 +418,7 @@ int omp_solve(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y,
     struct Key {
       const void *A, *Y, *X, *sup, *Sp, *Ep, *st_out, *rn_out, *coef, *dmem, *ws, *pool;
       int64_t M, N, lda, B, ldy;
-      int32_t S, prec, cfg, timed;
+      int32_t S, prec, cfg, gram_fly;
       uint32_t eps_bits, pad;
     } key;
     std::memset(&key, 0, sizeof(key));
@@ -439,7 +442,7 @@ int omp_solve(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y,
     key.S = S;
     key.prec = prec;
     key.cfg = cfg;
-    key.timed = 0;
+    key.gram_fly = opts->gram_on_the_fly;
     std::memcpy(&key.eps_bits, &eps, sizeof(float));
     {
       const DictView dp = opts->dict ? dict_view(opts->dict->mem, M, N, prec)

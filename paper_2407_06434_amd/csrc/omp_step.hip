@@ -227,6 +227,7 @@ struct RescoreQueue {
   double bar = 0.0, bnu2 = 0.0;
   int bn = 0x7fffffff;
   float bg[RPL];
+  bool gram = true;  // false: the winner's Gram row is computed after the pick
   template <int NA>
   __device__ __attribute__((always_inline)) void rescore(const DictView &d, const float4 *r4, const int (&n)[NA],
                                                          const int (&si)[RPL], int k, int lane) {
@@ -237,7 +238,7 @@ struct RescoreQueue {
       nu2[i] = n[i] >= 0 ? d.nu2[n[i]] : 1.0;
 #pragma unroll
       for (int p = 0; p < RPL; ++p)
-        gc[i][p] = (n[i] >= 0 && lane + 64 * p < k) ? d.G[(int64_t)n[i] * d.Np + si[p]] : 0.f;
+        gc[i][p] = (gram && n[i] >= 0 && lane + 64 * p < k) ? d.G[(int64_t)n[i] * d.Np + si[p]] : 0.f;
     }
     double ar[NA];
     atom_dots<NA, 2>(d, n, r4, lane, ar);
@@ -344,6 +345,26 @@ __device__ __attribute__((always_inline)) inline void scan_keys(const uint32_t (
   }
 }
 
+// Ablation of the Gram precomputation: g_i = a_{s_i}^T a_n* for the rows i < k
+// this lane holds, from the FP32 atoms (exact products, FP64 sum, rounded to
+// FP32 like the stored Gram).
+template <int RPL>
+__device__ void gram_row_from_atoms(const DictView &d, int nstar, const int (&si)[RPL], int k, int lane,
+                                    float (&g)[RPL]) {
+  const int64_t nc4 = d.Mp / 4;
+  const float4 *A4 = reinterpret_cast<const float4 *>(d.A32);
+  const float4 *an = A4 + (int64_t)nstar * nc4;
+#pragma unroll
+  for (int p = 0; p < RPL; ++p) {
+    const int i = lane + 64 * p;
+    const bool use = i < k;
+    const float4 *as = A4 + (int64_t)(use ? si[p] : 0) * nc4;
+    double acc = 0.0;
+    for (int64_t c = 0; c < nc4; ++c) acc += dot4d(as[c], an[c]);
+    g[p] = use ? (float)acc : 0.f;
+  }
+}
+
 // BF16 form of the pick. The epilogue left, per subgroup of atoms, keys for
 // its NKEEP best BF16 scores, each score rounded down by less than 2^-18
 // relative (et below); keys of selected, zero or padding atoms carry their
@@ -379,6 +400,7 @@ __device__ int select_bf16(const DictView &d, const WorkView &w, int64_t b, floa
   const uint32_t mthr_bits = float_bits_floor(mthr / (1.0 + et) * (1.0 - 1e-12));
   int *mlist = clist + solve_cand_len(nkeys);
   RescoreQueue<RPL> q;
+  q.gram = !w.gram_fly;
   // Candidates and possibly open subgroups, from the keys in registers or, for
   // more keys than that, read again KREG per lane at a time.
   int ncand = 0, nmaybe = 0;
@@ -794,13 +816,14 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
 #pragma unroll
     for (int p = 0; p < RPL; ++p) {
       const int i = lane + 64 * p;
-      g[p] = i < k ? d.G[(int64_t)nstar * d.Np + si[p]] : 0.f;
+      g[p] = (i < k && !w.gram_fly) ? d.G[(int64_t)nstar * d.Np + si[p]] : 0.f;
     }
     const int na[1] = {nstar};
     double ar[1];
     atom_dots<1, 4>(d, na, r4, lane, ar);
     cdot = ar[0];
   }
+  if (w.gram_fly) gram_row_from_atoms<RPL>(d, nstar, si, k, lane, g);
   // beta = a_n*^T y = a_n*^T r + sum_j G[n*, s_j] x_j (r = y - A_{k-1} x_{k-1})
   double gx = 0.0;
 #pragma unroll

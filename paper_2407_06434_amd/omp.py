@@ -57,7 +57,8 @@ class OmpOptsStruct(ctypes.Structure):
                 ("coef_out", ctypes.c_void_p), ("dict", ctypes.POINTER(OmpDictStruct)),
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
                 ("phase_ms", ctypes.POINTER(ctypes.c_float)),
-                ("phase_launches", ctypes.POINTER(ctypes.c_int32)), ("use_graph", ctypes.c_int32)]
+                ("phase_launches", ctypes.POINTER(ctypes.c_int32)), ("use_graph", ctypes.c_int32),
+                ("gram_on_the_fly", ctypes.c_int32)]
 
 
 class OmpProblemStruct(ctypes.Structure):
@@ -207,7 +208,8 @@ def solve(A: torch.Tensor, Y: torch.Tensor, S: int, eps: float = 0.0, *, precisi
           dictionary: Optional[Dictionary] = None, S_per_signal: Optional[torch.Tensor] = None,
           eps_per_signal: Optional[torch.Tensor] = None, dense: bool = True,
           workspace: Optional[torch.Tensor] = None, out: Optional[Result] = None, stream=None,
-          timing: Optional[dict] = None, tile_config: int = 0, graph: bool = True) -> Result:
+          timing: Optional[dict] = None, tile_config: int = 0, graph: bool = True,
+          gram_on_the_fly: bool = False) -> Result:
     """Batched OMP (Algorithm 1) on the GPU.
 
     A: (N, M) float32 atom-major dictionary; Y: (B, M) float32 signals.
@@ -218,6 +220,8 @@ def solve(A: torch.Tensor, Y: torch.Tensor, S: int, eps: float = 0.0, *, precisi
     with HIP events inside the library, the call waits for the stream, and
     timing[phase] accumulates (milliseconds, launches) per phase. With `graph` (default)
     the library replays the solve from a captured hipGraph cached per argument set.
+    `gram_on_the_fly` (ablation only) computes each pick's Gram row from the atoms
+    instead of reading the prepared Gram matrix.
     """
     _check_matrix(A, "A")
     N, M = A.shape
@@ -230,6 +234,7 @@ def solve(A: torch.Tensor, Y: torch.Tensor, S: int, eps: float = 0.0, *, precisi
     o.precision = PREC[precision]
     o.tile_config = int(tile_config)
     o.use_graph = 1 if graph else 0
+    o.gram_on_the_fly = 1 if gram_on_the_fly else 0
     if dictionary is not None:
         if dictionary.A is not A or dictionary.precision != precision:
             raise ValueError("dictionary was prepared for another A or precision")

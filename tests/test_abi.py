@@ -121,6 +121,14 @@ def test_solve_rejects_small_or_missing_workspace(lib):
     assert rc == omp.OMP_EWORKSPACE
 
 
+def test_solve_rejects_bad_ablation_flag(lib):
+    from paper_2407_06434_amd import omp
+    o = _opts()
+    o.gram_on_the_fly = 2
+    rc = lib.omp_solve(FAKE, 64, 256, 64, FAKE, 10, 64, 8, 0.0, FAKE, FAKE, ctypes.byref(o), None)
+    assert rc == omp.OMP_EINVAL
+
+
 def test_solve_beyond_limits_is_not_supported(lib):
     from paper_2407_06434_amd import omp
     o = _opts()

@@ -345,3 +345,23 @@ def test_random_shapes_sweep(orc):
         out = {k: v.cpu().numpy() for k, v in r._asdict().items() if v is not None}
         rep = parity.check(w, out, orc, idx=np.sort(g.choice(B, min(B, 12), replace=False)))
         print("   ", rep)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_gram_rows_on_the_fly(orc, prec):
+    """Ablation A2: Gram rows computed from the atoms give the oracle's picks and the same
+    supports as the prepared Gram matrix."""
+    torch = _torch()
+    from paper_2407_06434_amd import omp, workloads
+    w = workloads.batched_256x1024(B=300)
+    dev = torch.device("cuda:0")
+    A = torch.from_numpy(w.A).to(dev)
+    Y = torch.from_numpy(w.Y).to(dev)
+    print(f"case Gram rows on the fly {prec}", flush=True)
+    a = omp.solve(A, Y, w.S, precision=prec)
+    b = omp.solve(A, Y, w.S, precision=prec, gram_on_the_fly=True)
+    torch.cuda.synchronize()
+    out = {k: v.cpu().numpy() for k, v in b._asdict().items() if v is not None}
+    rep = parity.check(w, out, orc, idx=np.arange(0, w.B, 10))
+    print(rep)
+    assert np.array_equal(a.support.cpu().numpy(), out["support"])
