@@ -196,20 +196,22 @@ def run_per_signal_loop(w, precision, n=32):
     return dict(wall=wall, n=n, support=sup)
 
 
-def run_gram_on_the_fly(w, precision, steps=3):
-    """Ablation A2 of the paper (Gram precomputation) on these kernels: the same step
-    with each pick's Gram row computed from the atoms instead of read from G."""
+def run_ablation(w, precision, steps=3, **flags):
+    """Ablations A2 and A3 of the paper on these kernels: the same step with one design
+    choice undone (`gram_on_the_fly`: each pick's Gram row computed from the atoms
+    instead of read from G; `refactor`: the Cholesky factor rebuilt at every step
+    instead of extended by one row)."""
     import torch
     from paper_2407_06434_amd import omp
     dev = torch.device("cuda:0")
     A = torch.from_numpy(w.A).to(dev)
     Y = torch.from_numpy(w.Y).to(dev)
     d = omp.Dictionary(A, precision)
-    out = omp.solve(A, Y, w.S, w.eps, precision=precision, dictionary=d, gram_on_the_fly=True)
+    out = omp.solve(A, Y, w.S, w.eps, precision=precision, dictionary=d, **flags)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        out = omp.solve(A, Y, w.S, w.eps, precision=precision, dictionary=d, out=out, gram_on_the_fly=True)
+        out = omp.solve(A, Y, w.S, w.eps, precision=precision, dictionary=d, out=out, **flags)
     torch.cuda.synchronize()
     return dict(wall=(time.perf_counter() - t0) / steps, support=out.support.cpu().numpy())
 
@@ -370,6 +372,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch (slot scheduler) measurement")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal measurement")
+    ap.add_argument("--no-ablations", action="store_true",
+                    help="skip the ablation runs (per-signal loop, Gram rows from atoms, re-factorisation)")
     ap.add_argument("--learned-train", type=int, default=262144, help="training signals for the learned proposal")
     ap.add_argument("--learned-epochs", type=int, default=20)
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -439,25 +443,29 @@ def main():
         line["same_supports_vs_fp32"] = f"{sum(same)}/{w.B}"
         log(f"fp32: {fsps:.0f} signals/s; same supports {sum(same)}/{w.B}")
     line["widened_signals"] = int(np.sum((g["res"]["status"] & 64) != 0))
-    loop = run_per_signal_loop(w, args.precision)
-    loop_sps = loop["n"] / loop["wall"]
-    line["ablation_batching"] = {
-        "per_signal_loop": {"value": round(loop_sps, 1), "unit": "signals/s", "signals": loop["n"]},
-        "batched": {"value": round(sps, 1), "unit": "signals/s"},
-        "speedup": round(sps / loop_sps, 1),
-        "identical_supports": bool(np.array_equal(loop["support"], g["res"]["support"][: loop["n"]])),
-    }
-    log(f"ablation (batching): {line['ablation_batching']}")
-    gf = run_gram_on_the_fly(w, args.precision)
-    same_gf = [set(a.tolist()) == set(b.tolist()) for a, b in zip(gf["support"], g["res"]["support"])]
-    line["ablation_gram"] = {
-        "gram_rows_from_atoms": {"value": round(w.B / gf["wall"], 1), "unit": "signals/s",
-                                 "ms_per_step": round(1e3 * gf["wall"], 3)},
-        "prepared_gram": {"value": round(sps, 1), "unit": "signals/s"},
-        "speedup": round(sps / (w.B / gf["wall"]), 2),
-        "same_supports": f"{sum(same_gf)}/{w.B}",
-    }
-    log(f"ablation (Gram): {line['ablation_gram']}")
+    if not args.no_ablations:
+        loop = run_per_signal_loop(w, args.precision)
+        loop_sps = loop["n"] / loop["wall"]
+        line["ablation_batching"] = {
+            "per_signal_loop": {"value": round(loop_sps, 1), "unit": "signals/s", "signals": loop["n"]},
+            "batched": {"value": round(sps, 1), "unit": "signals/s"},
+            "speedup": round(sps / loop_sps, 1),
+            "identical_supports": bool(np.array_equal(loop["support"], g["res"]["support"][: loop["n"]])),
+        }
+        log(f"ablation (batching): {line['ablation_batching']}")
+        for key, flag, name, base in (("ablation_gram", "gram_on_the_fly", "gram_rows_from_atoms", "prepared_gram"),
+                                      ("ablation_cholesky", "refactor", "refactorised_each_step",
+                                       "progressive_update")):
+            ab = run_ablation(w, args.precision, **{flag: True})
+            same_ab = [set(a.tolist()) == set(b.tolist()) for a, b in zip(ab["support"], g["res"]["support"])]
+            line[key] = {
+                name: {"value": round(w.B / ab["wall"], 1), "unit": "signals/s",
+                       "ms_per_step": round(1e3 * ab["wall"], 3)},
+                base: {"value": round(sps, 1), "unit": "signals/s"},
+                "speedup": round(sps / (w.B / ab["wall"]), 2),
+                "same_supports": f"{sum(same_ab)}/{w.B}",
+            }
+            log(f"{key}: {line[key]}")
 
     if not args.no_uneven:
         u = run_uneven(args.precision, max(3, args.steps // 2), 1)

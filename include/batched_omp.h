@@ -134,6 +134,11 @@ typedef struct omp_opts {
                                    computes the Gram row A_S^T a_n* of each pick from the atoms
                                    (exact products, FP64 sums) instead of reading the prepared
                                    Gram matrix; 0 (default) reads it. Other values: OMP_EINVAL. */
+  int32_t refactor;             /* ablation A3 (measurement only): 1 = the solve rebuilds the
+                                   Cholesky factor of A_S^T A_S from the Gram entries at every
+                                   step (O(k^3)) instead of appending one row to the stored factor
+                                   (O(k^2)); u = V^{-1} A_S^T y keeps its incremental form.
+                                   0 (default): the progressive update. Other values: OMP_EINVAL. */
 } omp_opts_t;
 
 /* Phases reported through omp_opts_t.phase_ms. */

@@ -272,6 +272,7 @@ WorkView work_view(void *mem, int64_t M, int64_t N, int64_t B, int S, int precis
   w.xh = at<float>(mem, L.xh);
   w.V = at<float>(mem, L.V);
   w.gram_fly = 0;
+  w.refactor = 0;
   return w;
 }
 
@@ -355,6 +356,7 @@ int omp_solve(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y,
   const int cfg = opts->tile_config;
   if (cfg < 0 || cfg > MAX_TILE_CFG) return OMP_EINVAL;
   if (opts->gram_on_the_fly != 0 && opts->gram_on_the_fly != 1) return OMP_EINVAL;
+  if (opts->refactor != 0 && opts->refactor != 1) return OMP_EINVAL;
   if (!dims_ok(M, N) || B < 0 || B > ((int64_t)1 << 26)) return OMP_EINVAL;
   if (S < 1 || S > M || S > N) return OMP_EINVAL;
   if (S > OMP_MAX_S) return OMP_ENOTSUPP;
@@ -394,6 +396,7 @@ int omp_solve(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y,
     }
     WorkView w = work_view(opts->workspace, M, N, B, S, prec, cfg);
     w.gram_fly = opts->gram_on_the_fly;
+    w.refactor = opts->refactor;
     e = timer.run(OMP_PHASE_INIT, [&] {
       return launch_init(Y, ldy, opts->S_per_signal, opts->eps_per_signal, eps, d, w, prec, cs);
     });
@@ -418,7 +421,7 @@ int omp_solve(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y,
     struct Key {
       const void *A, *Y, *X, *sup, *Sp, *Ep, *st_out, *rn_out, *coef, *dmem, *ws, *pool;
       int64_t M, N, lda, B, ldy;
-      int32_t S, prec, cfg, gram_fly;
+      int32_t S, prec, cfg, gram_fly, refactor, pad2;
       uint32_t eps_bits, pad;
     } key;
     std::memset(&key, 0, sizeof(key));
@@ -443,6 +446,7 @@ int omp_solve(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y,
     key.prec = prec;
     key.cfg = cfg;
     key.gram_fly = opts->gram_on_the_fly;
+    key.refactor = opts->refactor;
     std::memcpy(&key.eps_bits, &eps, sizeof(float));
     {
       const DictView dp = opts->dict ? dict_view(opts->dict->mem, M, N, prec)

@@ -84,6 +84,7 @@ struct WorkView {
   int64_t vstride; // floats per signal in V: S(S+1)/2 rounded up to a multiple of 4
   float *V;       // [Bp][vstride] packed lower-triangular Cholesky factor, row by row
   int gram_fly;   // 1: Gram rows of the picks computed from the atoms (ablation A2)
+  int refactor;   // 1: the factor of A_S^T A_S rebuilt from the Gram at every step (ablation A3)
 };
 
 size_t work_bytes(int64_t M, int64_t N, int64_t B, int S, int precision, int cfg);

@@ -345,6 +345,41 @@ __device__ __attribute__((always_inline)) inline void scan_keys(const uint32_t (
   }
 }
 
+// Ablation A3 (re-factorisation instead of the progressive update): the packed
+// lower triangle of G[S, S] in LDS is replaced by its Cholesky factor, column
+// by column (left-looking: lane i forms row i's dot product with row j in
+// FP64, the pivot comes from lane j).
+template <int RPL>
+__device__ void cholesky_lds(float *Vs, int k, int lane) {
+  for (int j = 0; j < k; ++j) {
+    const int tj = j * (j + 1) / 2;
+    double sp[RPL];
+#pragma unroll
+    for (int p = 0; p < RPL; ++p) {
+      const int i = lane + 64 * p;
+      const int ti = i * (i + 1) / 2;
+      double acc = 0.0;
+      if (i >= j && i < k)
+        for (int q = 0; q < j; ++q) acc += (double)Vs[ti + q] * (double)Vs[tj + q];
+      sp[p] = acc;
+    }
+    double sj = sp[0];
+#pragma unroll
+    for (int p = 1; p < RPL; ++p) sj = ((j >> 6) == p) ? sp[p] : sj;
+    sj = __longlong_as_double((long long)readlane64((uint64_t)__double_as_longlong(sj), j & 63));
+    const double piv = fmax((double)Vs[tj + j] - sj, 1e-300);
+    const double djj = sqrt(piv);
+#pragma unroll
+    for (int p = 0; p < RPL; ++p) {
+      const int i = lane + 64 * p;
+      const int ti = i * (i + 1) / 2;
+      if (i > j && i < k) Vs[ti + j] = (float)(((double)Vs[ti + j] - sp[p]) / djj);
+      if (i == j) Vs[tj + j] = (float)djj;
+    }
+    wave_lds_sync();
+  }
+}
+
 // Ablation of the Gram precomputation: g_i = a_{s_i}^T a_n* for the rows i < k
 // this lane holds, from the FP32 atoms (exact products, FP64 sum, rounded to
 // FP32 like the stored Gram).
@@ -784,7 +819,18 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
 
   // ---- round 2: the packed factor straight into LDS (asynchronous
   // global-to-LDS loads: no registers, no wait until it is read) ...
-  {
+  if (w.refactor) {
+    // ablation A3: the Gram block G[S, S] (packed lower triangle) instead of the
+    // stored factor; it is factorised below
+    const int nv = k * (k + 1) / 2;
+    for (int t = lane; t < nv; t += 64) {
+      int i = (int)((sqrtf(8.f * (float)t + 1.f) - 1.f) * 0.5f);
+      while ((i + 1) * (i + 2) / 2 <= t) ++i;
+      while (i * (i + 1) / 2 > t) --i;
+      const int j = t - i * (i + 1) / 2;
+      Vs[t] = d.G[(int64_t)w.sup[b * S + i] * d.Np + w.sup[b * S + j]];
+    }
+  } else {
     const int nv4 = (k * (k + 1) / 2 + 3) / 4;
     const float4 *V4 = reinterpret_cast<const float4 *>(w.V + b * VS);
     float4 *Vs4 = reinterpret_cast<float4 *>(Vs);
@@ -832,6 +878,7 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
   if (widened) fl |= OMP_SIG_WIDENED;
   __builtin_amdgcn_s_waitcnt(0);  // the global-to-LDS loads have landed
   wave_lds_sync();
+  if (w.refactor) cholesky_lds<RPL>(Vs, k, lane);
 
   float z[RPL], rd[RPL];
   int tri[RPL];  // i (i + 1) / 2: start of row i in the packed factor

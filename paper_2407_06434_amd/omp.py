@@ -58,7 +58,7 @@ class OmpOptsStruct(ctypes.Structure):
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
                 ("phase_ms", ctypes.POINTER(ctypes.c_float)),
                 ("phase_launches", ctypes.POINTER(ctypes.c_int32)), ("use_graph", ctypes.c_int32),
-                ("gram_on_the_fly", ctypes.c_int32)]
+                ("gram_on_the_fly", ctypes.c_int32), ("refactor", ctypes.c_int32)]
 
 
 class OmpProblemStruct(ctypes.Structure):
@@ -209,7 +209,7 @@ def solve(A: torch.Tensor, Y: torch.Tensor, S: int, eps: float = 0.0, *, precisi
           eps_per_signal: Optional[torch.Tensor] = None, dense: bool = True,
           workspace: Optional[torch.Tensor] = None, out: Optional[Result] = None, stream=None,
           timing: Optional[dict] = None, tile_config: int = 0, graph: bool = True,
-          gram_on_the_fly: bool = False) -> Result:
+          gram_on_the_fly: bool = False, refactor: bool = False) -> Result:
     """Batched OMP (Algorithm 1) on the GPU.
 
     A: (N, M) float32 atom-major dictionary; Y: (B, M) float32 signals.
@@ -221,7 +221,9 @@ def solve(A: torch.Tensor, Y: torch.Tensor, S: int, eps: float = 0.0, *, precisi
     timing[phase] accumulates (milliseconds, launches) per phase. With `graph` (default)
     the library replays the solve from a captured hipGraph cached per argument set.
     `gram_on_the_fly` (ablation only) computes each pick's Gram row from the atoms
-    instead of reading the prepared Gram matrix.
+    instead of reading the prepared Gram matrix; `refactor` (ablation only) rebuilds
+    the Cholesky factor of the support's Gram block at every step instead of
+    appending one row to it.
     """
     _check_matrix(A, "A")
     N, M = A.shape
@@ -235,6 +237,7 @@ def solve(A: torch.Tensor, Y: torch.Tensor, S: int, eps: float = 0.0, *, precisi
     o.tile_config = int(tile_config)
     o.use_graph = 1 if graph else 0
     o.gram_on_the_fly = 1 if gram_on_the_fly else 0
+    o.refactor = 1 if refactor else 0
     if dictionary is not None:
         if dictionary.A is not A or dictionary.precision != precision:
             raise ValueError("dictionary was prepared for another A or precision")

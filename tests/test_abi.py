@@ -48,7 +48,7 @@ def test_version_and_strings(lib):
 def test_struct_layout_matches_header():
     from paper_2407_06434_amd import omp
     assert ctypes.sizeof(omp.OmpDictStruct) == 64
-    assert ctypes.sizeof(omp.OmpOptsStruct) == 8 + 8 * 7 + 8 + 16 + 8
+    assert ctypes.sizeof(omp.OmpOptsStruct) == 8 + 8 * 7 + 8 + 16 + 16
 
 
 def _opts(ws=1 << 30, prec=0):
@@ -125,6 +125,10 @@ def test_solve_rejects_bad_ablation_flag(lib):
     from paper_2407_06434_amd import omp
     o = _opts()
     o.gram_on_the_fly = 2
+    rc = lib.omp_solve(FAKE, 64, 256, 64, FAKE, 10, 64, 8, 0.0, FAKE, FAKE, ctypes.byref(o), None)
+    assert rc == omp.OMP_EINVAL
+    o = _opts()
+    o.refactor = -1
     rc = lib.omp_solve(FAKE, 64, 256, 64, FAKE, 10, 64, 8, 0.0, FAKE, FAKE, ctypes.byref(o), None)
     assert rc == omp.OMP_EINVAL
 

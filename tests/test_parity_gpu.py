@@ -365,3 +365,29 @@ def test_gram_rows_on_the_fly(orc, prec):
     rep = parity.check(w, out, orc, idx=np.arange(0, w.B, 10))
     print(rep)
     assert np.array_equal(a.support.cpu().numpy(), out["support"])
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("S", [32, 150])
+def test_refactorisation_each_step(orc, prec, S):
+    """Ablation A3: the factor rebuilt from the Gram block at every step (one and three
+    rows per lane) gives the oracle's picks, and nearly always the progressive
+    update's supports (they differ only in rounding)."""
+    torch = _torch()
+    from paper_2407_06434_amd import omp, workloads
+    w = (workloads.batched_256x1024(B=200) if S <= 32
+         else workloads.custom(256, 512, 40, S, seed=17, k_true=120, snr_db=60.0))
+    dev = torch.device("cuda:0")
+    A = torch.from_numpy(w.A).to(dev)
+    Y = torch.from_numpy(w.Y).to(dev)
+    print(f"case refactorisation {prec} S={S}", flush=True)
+    a = omp.solve(A, Y, w.S, precision=prec)
+    b = omp.solve(A, Y, w.S, precision=prec, refactor=True)
+    torch.cuda.synchronize()
+    out = {k: v.cpu().numpy() for k, v in b._asdict().items() if v is not None}
+    rep = parity.check(w, out, orc, idx=np.arange(0, w.B, 10))
+    print(rep)
+    same = np.mean([set(x.tolist()) == set(y.tolist()) for x, y in zip(a.support.cpu().numpy(), out["support"])])
+    print("same supports as the progressive update:", same)
+    assert same >= 0.95
+
