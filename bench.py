@@ -338,6 +338,48 @@ def run_learned(n_train, epochs, n_eval=65536, log=None):
                       "labels_and_features_s": round(label_s, 2), "host_generation_s": round(gen_s, 2)}}
 
 
+SWEEP_N = (64, 128, 256, 512, 1024, 2048, 4096, 8192)
+SWEEP_B = (10, 50, 100, 500, 1000, 5000, 10000)
+SWEEP_S = (8, 32, 64)
+
+
+def run_sweep(precision, steps=3, warmup=1):
+    """The paper's parameter sweep (Section 4, parameter sweep) as a speed map of these
+    kernels: N in 64..8192, B in 10..10000, S in {8, 32, 64}, M = N/4, cells with S > M
+    left out (OMP cannot pick more than M independent atoms). Each (N, S) draws one
+    N(0, 1/M) dictionary and 10,000 S-sparse signals at 30 dB SNR; a cell of batch B
+    solves the first B of them. Signals/s over `steps` calls replayed from the graph."""
+    import torch
+    from paper_2407_06434_amd import omp, workloads
+    dev = torch.device("cuda:0")
+    cells = []
+    for N in SWEEP_N:
+        M = N // 4
+        for S in SWEEP_S:
+            if S > M:
+                continue
+            w = workloads.custom(M, N, max(SWEEP_B), S, seed=N + S)
+            A = torch.from_numpy(w.A).to(dev)
+            Yall = torch.from_numpy(w.Y).to(dev)
+            d = omp.Dictionary(A, precision)
+            for B in SWEEP_B:
+                Y = Yall[:B].contiguous()
+                out = None
+                for _ in range(warmup):
+                    out = omp.solve(A, Y, S, precision=precision, dictionary=d, out=out)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(steps):
+                    out = omp.solve(A, Y, S, precision=precision, dictionary=d, out=out)
+                torch.cuda.synchronize()
+                dt = (time.perf_counter() - t0) / steps
+                cells.append({"N": N, "M": M, "B": B, "S": S, "ms_per_call": round(1e3 * dt, 4),
+                              "signals_per_s": round(B / dt, 1)})
+                log(f"sweep N={N} M={M} B={B} S={S}: {1e3 * dt:.3f} ms, {B / dt:.0f} signals/s")
+            del d, A, Yall
+    return cells
+
+
 def cpu_baseline(w, target_s):
     """The oracle, as it stands, on the first n signals of the same workload."""
     import oracle
@@ -372,6 +414,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch (slot scheduler) measurement")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal measurement")
+    ap.add_argument("--sweep", action="store_true",
+                    help="instead of the benchmark step, run the paper's parameter sweep and print its speed map")
     ap.add_argument("--no-ablations", action="store_true",
                     help="skip the ablation runs (per-signal loop, Gram rows from atoms, re-factorisation)")
     ap.add_argument("--learned-train", type=int, default=262144, help="training signals for the learned proposal")
@@ -380,9 +424,15 @@ def main():
                     help="first run one plain device copy of this many MiB (scale reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               f"(the batch would shard by signals with no in-loop communication).", file=sys.stderr)
         sys.exit(2)
+
+    if args.sweep:
+        cells = run_sweep(args.precision)
+        print(json.dumps({"metric": "parameter_sweep", "unit": "signals/s", "dtype": args.precision,
+                          "data": "synthetic", "steps": 3, "cells": cells}), flush=True)
+        return
 
     from paper_2407_06434_amd import workloads
 

@@ -36,7 +36,7 @@ SIG_MASK = 0xFF
 
 
 def check(w, gpu: dict, orc, idx=None, tie=1e-5, coef_tol=1e-4, stop_tol=1e-5, threads=None,
-          S_per=None, eps_per=None, eps=None, raise_on_fail=True) -> dict:
+          S_per=None, eps_per=None, eps=None, raise_on_fail=True, residual_rounding=False) -> dict:
     B = w.Y.shape[0]
     idx = np.arange(B) if idx is None else np.asarray(idx)
     A = w.A
@@ -59,6 +59,7 @@ def check(w, gpu: dict, orc, idx=None, tie=1e-5, coef_tol=1e-4, stop_tol=1e-5, t
     rep = orc.omp(A, Y, S, eps, S_per_signal=Sp, eps_per_signal=Ep, prefix=g_sup,
                   nprefix=g_k.astype(np.int32), threads=threads)
 
+    rh0 = rep["rnorm_hist"][:, 0]
     fails = []
     near_ties = 0
     exact_support = 0
@@ -74,8 +75,15 @@ def check(w, gpu: dict, orc, idx=None, tie=1e-5, coef_tol=1e-4, stop_tol=1e-5, t
         ratio = np.where(sb > 0, sp / np.where(sb > 0, sb, 1), 1.0)
         worst_ratio = min(worst_ratio, float(ratio.min()) if k else 1.0)
         tied = ratio < 1.0
-        if np.any(ratio < 1.0 - tie):
-            j = int(np.argmax(ratio < 1.0 - tie))
+        tol = np.full(k, tie)
+        if residual_rounding and k:
+            # The GPU's residual r = y - A_S x is formed in FP32: its error is about
+            # (j + 1) u ||y|| at pick j, so two scores closer than twice that are
+            # ordered by rounding (it matters once ||r|| nears the rounding level of
+            # y, e.g. when S = M fills the signal space).
+            tol = tie + 2.0 * np.arange(1, k + 1) * 2.0 ** -24 * rh0[i] / np.maximum(sb, 1e-300)
+        if np.any(ratio < 1.0 - tol):
+            j = int(np.argmax(ratio < 1.0 - tol))
             fails.append((b, f"pick {j} atom {sup[j]} scores {ratio[j]:.8f} of the best atom "
                              f"{rep['idx_best'][i, j]}"))
         near_ties += int(tied.sum())

@@ -302,6 +302,21 @@ def test_tile_configurations_agree(prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("M,N", [(16, 64), (32, 128), (64, 256)])
+def test_support_fills_the_signal_space(orc, prec, M, N):
+    """S = M with S-sparse signals (the parameter sweep's S = M cells): the last pick
+    makes the least-squares system square. The last picks are taken on residuals that
+    can be within a few units of FP32 rounding of y, so their ties are judged against
+    the FP32 residual's rounding error."""
+    from paper_2407_06434_amd import workloads
+    w = workloads.custom(M, N, 48, M, seed=M, k_true=M)
+    print(f"case S = M = {M} N={N} B=48 {prec}", flush=True)
+    out = run_gpu(w, prec)
+    rep = parity.check(w, out, orc, residual_rounding=True)
+    print(rep)
+
+
+@pytest.mark.parametrize("prec", PRECS)
 def test_largest_support(orc, prec):
     """S = OMP_MAX_S = 256: four factor rows per lane and one wavefront per solve block
     (the packed factor alone takes 129 KiB of LDS)."""
