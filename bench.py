@@ -338,6 +338,42 @@ def run_learned(n_train, epochs, n_eval=65536, log=None):
                       "labels_and_features_s": round(label_s, 2), "host_generation_s": round(gen_s, 2)}}
 
 
+def run_gram_domain(steps=3, warmup=1):
+    """Tall dictionary (the face-recognition shape 8064 x 1207, S = 30, B = 1200): the
+    Gram-domain form (P = A^T y once, correlations from P and G) against the
+    residual-vector forms, FP32 and BF16, on the same prepared dictionaries. Signals/s
+    over graph-replayed calls; supports compared with the FP32 residual-vector form."""
+    import torch
+    from paper_2407_06434_amd import omp, workloads
+    dev = torch.device("cuda:0")
+    w = workloads.face_8064x1207()
+    A = torch.from_numpy(w.A).to(dev)
+    Y = torch.from_numpy(w.Y).to(dev)
+    res = {}
+    for name, prec, gd in (("gram_domain_fp32", "fp32", True), ("residual_fp32", "fp32", False),
+                           ("residual_bf16", "bf16", False)):
+        d = omp.Dictionary(A, prec)
+        out = None
+        for _ in range(warmup):
+            out = omp.solve(A, Y, w.S, precision=prec, dictionary=d, out=out, gram_domain=gd)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            out = omp.solve(A, Y, w.S, precision=prec, dictionary=d, out=out, gram_domain=gd)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        res[name] = dict(value=round(w.B / dt, 1), ms_per_call=round(1e3 * dt, 3), support=out.support.cpu().numpy())
+        del d
+    ref = res["residual_fp32"]["support"]
+    line = {"workload": f"{w.name}_B{w.B}_S{w.S}", "unit": "signals/s"}
+    for name, r in res.items():
+        same = sum(set(a.tolist()) == set(b.tolist()) for a, b in zip(r.pop("support"), ref))
+        line[name] = dict(r, same_supports_as_residual_fp32=f"{same}/{w.B}")
+    line["speedup_vs_residual_fp32"] = round(line["gram_domain_fp32"]["value"] / line["residual_fp32"]["value"], 2)
+    line["speedup_vs_residual_bf16"] = round(line["gram_domain_fp32"]["value"] / line["residual_bf16"]["value"], 2)
+    return line
+
+
 SWEEP_N = (64, 128, 256, 512, 1024, 2048, 4096, 8192)
 SWEEP_B = (10, 50, 100, 500, 1000, 5000, 10000)
 SWEEP_S = (8, 32, 64)
@@ -416,6 +452,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal measurement")
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the benchmark step, run the paper's parameter sweep and print its speed map")
+    ap.add_argument("--no-gram-domain", action="store_true",
+                    help="skip the Gram-domain measurement on the tall face-recognition shape")
     ap.add_argument("--no-ablations", action="store_true",
                     help="skip the ablation runs (per-signal loop, Gram rows from atoms, re-factorisation)")
     ap.add_argument("--learned-train", type=int, default=262144, help="training signals for the learned proposal")
@@ -517,6 +555,10 @@ def main():
             }
             log(f"{key}: {line[key]}")
 
+    if not args.no_gram_domain:
+        gd = run_gram_domain()
+        line["gram_domain"] = gd
+        log(f"gram domain: {gd}")
     if not args.no_uneven:
         u = run_uneven(args.precision, max(3, args.steps // 2), 1)
         line["uneven"] = u

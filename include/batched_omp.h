@@ -139,6 +139,18 @@ typedef struct omp_opts {
                                    step (O(k^3)) instead of appending one row to the stored factor
                                    (O(k^2)); u = V^{-1} A_S^T y keeps its incremental form.
                                    0 (default): the progressive update. Other values: OMP_EINVAL. */
+  int32_t gram_domain;          /* 1 = Gram-domain form for tall dictionaries (M >= N; the
+                                   scikit-learn Gram solver the paper's Section 2.1 describes):
+                                   P = A^T y is formed once per signal by one product, and each
+                                   step takes its correlations as c = P - G[:, S] x (O(N k) per
+                                   signal, no M-length residual), beta = P[n*], and the residual
+                                   norm as ||r||^2 = ||y||^2 - sum_i u_i^2 (FP64 running sum; its
+                                   rounding grows as u ||y||^2 / ||r|| when ||r|| << ||y||, so an
+                                   eps near the noise floor of y may stop a step apart from the
+                                   residual-vector form). Same picks as the default form up to
+                                   rounding. FP32 precision only (else OMP_EINVAL); the workspace
+                                   grows by B_pad * N_pad * 4 bytes (omp_workspace_size with the
+                                   same opts). 0 (default): residual vectors. */
 } omp_opts_t;
 
 /* Phases reported through omp_opts_t.phase_ms. */

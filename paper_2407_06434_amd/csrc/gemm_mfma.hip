@@ -22,19 +22,23 @@ namespace bomp {
 namespace {
 
 // ---------------------------------------------------------------------------
-// Gram matrix: G[n][m] = sum_k A32[n][k] A32[m][k], FP32 in and out.
+// Stored FP32 products C[n][m] = sum_k X[n][k] Z[m][k] (rows of X and Z both
+// Mp floats long, ntn tiles of X rows): the Gram matrix G = A32 A32^T, and in
+// the Gram-domain form P = R32 A32^T (signal-major, the correlations of every
+// signal with every atom). Lanes 0-31 of a fragment row store 32 consecutive
+// columns.
 // ---------------------------------------------------------------------------
 using GramTile = Tile<128, 128, 2, 2>;
 
-__global__ __launch_bounds__(GramTile::NTHR) void k_gram(const float *__restrict__ A32, int64_t Mp,
-                                                         int64_t Np, float *__restrict__ G) {
+__global__ __launch_bounds__(GramTile::NTHR) void k_gram(const float *__restrict__ X, const float *__restrict__ Z,
+                                                         int64_t Mp, int ntn, float *__restrict__ G,
+                                                         int64_t ldg) {
   using T = GramTile;
   extern __shared__ u32x4 lds[];
-  const int ntn = (int)(Np / T::TN);
   const int tn = blockIdx.x % ntn, tm = blockIdx.x / ntn;
   const int64_t rs = Mp / 4;  // row stride in 16-byte chunks
-  const u32x4 *P = reinterpret_cast<const u32x4 *>(A32) + (int64_t)tn * T::TN * rs;
-  const u32x4 *Q = reinterpret_cast<const u32x4 *>(A32) + (int64_t)tm * T::TB * rs;
+  const u32x4 *P = reinterpret_cast<const u32x4 *>(X) + (int64_t)tn * T::TN * rs;
+  const u32x4 *Q = reinterpret_cast<const u32x4 *>(Z) + (int64_t)tm * T::TB * rs;
   f32x16 acc[T::FN][T::FB];
   mainloop<OpF32, T>(P, rs, Q, rs, (int)(rs / T::CH), lds, acc);
 
@@ -48,7 +52,7 @@ __global__ __launch_bounds__(GramTile::NTHR) void k_gram(const float *__restrict
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int64_t row = (int64_t)tn * T::TN + wn * T::FN * 32 + i * 32 + frag_row(lane, r);
-        G[row * Np + col] = acc[i][j][r];
+        G[row * ldg + col] = acc[i][j][r];
       }
     }
 }
@@ -320,7 +324,20 @@ hipError_t launch_gram(const DictView &d, hipStream_t st) {
   hipError_t e = set_lds(k_gram, T::LDS_BYTES);
   if (e != hipSuccess) return e;
   const int nt = (int)(d.Np / T::TN);
-  hipLaunchKernelGGL(k_gram, dim3(nt * nt), dim3(T::NTHR), T::LDS_BYTES, st, d.A32, d.Mp, d.Np, d.G);
+  hipLaunchKernelGGL(k_gram, dim3(nt * nt), dim3(T::NTHR), T::LDS_BYTES, st, d.A32, d.A32, d.Mp, nt, d.G,
+                     d.Np);
+  return hipGetLastError();
+}
+
+hipError_t launch_project(const DictView &d, const WorkView &w, hipStream_t st) {
+  using T = GramTile;
+  static_assert(BPAD % T::TN == 0 && NPAD % T::TB == 0, "padded sizes must be whole tiles");
+  if (!w.P || w.Bp % T::TN || d.Np % T::TB || w.Mp != d.Mp || w.Np != d.Np) return hipErrorInvalidValue;
+  hipError_t e = set_lds(k_gram, T::LDS_BYTES);
+  if (e != hipSuccess) return e;
+  const int ntb = (int)(w.Bp / T::TN), nta = (int)(d.Np / T::TB);
+  hipLaunchKernelGGL(k_gram, dim3(ntb * nta), dim3(T::NTHR), T::LDS_BYTES, st, w.R32, d.A32, d.Mp, ntb, w.P,
+                     d.Np);
   return hipGetLastError();
 }
 

@@ -61,10 +61,10 @@ struct WorkLayout {
   int ntile;
   int nslice, slice_len;
   int64_t vstride;
-  size_t Yp, R32, R16, part, mask, k, flags, pnorm, pdelta, Sb, epsb, sup, u, xh, V, total;
+  size_t Yp, R32, R16, part, mask, k, flags, pnorm, pdelta, Sb, epsb, sup, u, xh, V, P, total;
 };
 
-WorkLayout work_layout(int64_t M, int64_t N, int64_t B, int S, int precision, int cfg) {
+WorkLayout work_layout(int64_t M, int64_t N, int64_t B, int S, int precision, int cfg, bool gram_dom = false) {
   WorkLayout L;
   L.Mp = round_up(M, KPAD);
   L.Np = round_up(N, NPAD);
@@ -92,6 +92,7 @@ WorkLayout work_layout(int64_t M, int64_t N, int64_t B, int S, int precision, in
   L.xh = c.take<float>(Bp * Sz);
   L.vstride = round_up((int64_t)(Sz * (Sz + 1) / 2), 4);
   L.V = c.take<float>(Bp * (size_t)L.vstride);
+  L.P = gram_dom ? c.take<float>(Bp * (size_t)L.Np) : 0;
   L.total = (c.off + ALIGN - 1) / ALIGN * ALIGN;
   return L;
 }
@@ -229,8 +230,8 @@ DictView dict_view(void *mem, int64_t M, int64_t N, int precision) {
   return d;
 }
 
-size_t work_bytes(int64_t M, int64_t N, int64_t B, int S, int precision, int cfg) {
-  return work_layout(M, N, B, S, precision, cfg).total;
+size_t work_bytes(int64_t M, int64_t N, int64_t B, int S, int precision, int cfg, bool gram_dom) {
+  return work_layout(M, N, B, S, precision, cfg, gram_dom).total;
 }
 
 bool solve_fits(int64_t M, int64_t N, int64_t B, int S, int precision, int cfg) {
@@ -238,8 +239,8 @@ bool solve_fits(int64_t M, int64_t N, int64_t B, int S, int precision, int cfg) 
   return solve_waves_for(L.vstride, L.ntile * L.g.keys_per_tile, precision == OMP_PREC_BF16) > 0;
 }
 
-WorkView work_view(void *mem, int64_t M, int64_t N, int64_t B, int S, int precision, int cfg) {
-  const WorkLayout L = work_layout(M, N, B, S, precision, cfg);
+WorkView work_view(void *mem, int64_t M, int64_t N, int64_t B, int S, int precision, int cfg, bool gram_dom) {
+  const WorkLayout L = work_layout(M, N, B, S, precision, cfg, gram_dom);
   WorkView w;
   w.B = B;
   w.Bp = L.Bp;
@@ -273,6 +274,9 @@ WorkView work_view(void *mem, int64_t M, int64_t N, int64_t B, int S, int precis
   w.V = at<float>(mem, L.V);
   w.gram_fly = 0;
   w.refactor = 0;
+  w.gram_dom = gram_dom ? 1 : 0;
+  w.P = gram_dom ? at<float>(mem, L.P) : nullptr;
+  if (gram_dom) w.ntile = 1;  // one key per signal, from the Gram-domain select
   return w;
 }
 
@@ -341,7 +345,7 @@ size_t omp_workspace_size(int64_t M, int64_t N, int64_t B, int32_t S, const omp_
   if (prec != OMP_PREC_FP32 && prec != OMP_PREC_BF16) return 0;
   const int cfg = opts ? opts->tile_config : 0;
   if (cfg < 0 || cfg > MAX_TILE_CFG) return 0;
-  size_t total = work_bytes(M, N, B, S, prec, cfg);
+  size_t total = work_bytes(M, N, B, S, prec, cfg, opts && opts->gram_domain == 1);
   if (!opts || !opts->dict) total += dict_bytes(M, N, prec);
   return total;
 }
@@ -357,6 +361,9 @@ int omp_solve(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y,
   if (cfg < 0 || cfg > MAX_TILE_CFG) return OMP_EINVAL;
   if (opts->gram_on_the_fly != 0 && opts->gram_on_the_fly != 1) return OMP_EINVAL;
   if (opts->refactor != 0 && opts->refactor != 1) return OMP_EINVAL;
+  if (opts->gram_domain != 0 && opts->gram_domain != 1) return OMP_EINVAL;
+  if (opts->gram_domain && prec != OMP_PREC_FP32) return OMP_EINVAL;
+  const bool gdom = opts->gram_domain == 1;
   if (!dims_ok(M, N) || B < 0 || B > ((int64_t)1 << 26)) return OMP_EINVAL;
   if (S < 1 || S > M || S > N) return OMP_EINVAL;
   if (S > OMP_MAX_S) return OMP_ENOTSUPP;
@@ -370,7 +377,7 @@ int omp_solve(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y,
         !dd->mem)
       return OMP_EINVAL;
   }
-  const size_t wneed = work_bytes(M, N, B, S, prec, cfg);
+  const size_t wneed = work_bytes(M, N, B, S, prec, cfg, gdom);
   const size_t need = wneed + (opts->dict ? 0 : dict_bytes(M, N, prec));
   if (!opts->workspace || opts->workspace_bytes < need || !aligned(opts->workspace, ALIGN))
     return OMP_EWORKSPACE;
@@ -394,13 +401,20 @@ int omp_solve(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y,
       if (e == hipSuccess) e = timer.run(OMP_PHASE_DICT, [&] { return launch_gram(d, cs); });
       if (e != hipSuccess) return e;
     }
-    WorkView w = work_view(opts->workspace, M, N, B, S, prec, cfg);
+    WorkView w = work_view(opts->workspace, M, N, B, S, prec, cfg, gdom);
     w.gram_fly = opts->gram_on_the_fly;
     w.refactor = opts->refactor;
     e = timer.run(OMP_PHASE_INIT, [&] {
       return launch_init(Y, ldy, opts->S_per_signal, opts->eps_per_signal, eps, d, w, prec, cs);
     });
+    if (gdom && e == hipSuccess) e = timer.run(OMP_PHASE_INIT, [&] { return launch_project(d, w, cs); });
     for (int it = 0; it < S && e == hipSuccess; ++it) {
+      if (gdom) {
+        // Gram-domain form: correlations from P and G; no residual vectors
+        e = timer.run(OMP_PHASE_CORR, [&] { return launch_gram_select(d, w, cs); });
+        if (e == hipSuccess) e = timer.run(OMP_PHASE_UPDATE, [&] { return launch_solve(d, w, prec, cs); });
+        continue;
+      }
       e = timer.run(OMP_PHASE_CORR, [&] { return launch_corr_select(d, w, prec, cs); });
       if (e == hipSuccess) e = timer.run(OMP_PHASE_UPDATE, [&] { return launch_solve(d, w, prec, cs); });
       if (e == hipSuccess) e = timer.run(OMP_PHASE_RESIDUAL, [&] { return launch_residual(d, w, prec, cs); });
@@ -421,7 +435,7 @@ int omp_solve(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y,
     struct Key {
       const void *A, *Y, *X, *sup, *Sp, *Ep, *st_out, *rn_out, *coef, *dmem, *ws, *pool;
       int64_t M, N, lda, B, ldy;
-      int32_t S, prec, cfg, gram_fly, refactor, pad2;
+      int32_t S, prec, cfg, gram_fly, refactor, gram_dom;
       uint32_t eps_bits, pad;
     } key;
     std::memset(&key, 0, sizeof(key));
@@ -447,6 +461,7 @@ int omp_solve(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y,
     key.cfg = cfg;
     key.gram_fly = opts->gram_on_the_fly;
     key.refactor = opts->refactor;
+    key.gram_dom = opts->gram_domain;
     std::memcpy(&key.eps_bits, &eps, sizeof(float));
     {
       const DictView dp = opts->dict ? dict_view(opts->dict->mem, M, N, prec)

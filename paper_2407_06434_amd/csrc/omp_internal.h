@@ -85,10 +85,14 @@ struct WorkView {
   float *V;       // [Bp][vstride] packed lower-triangular Cholesky factor, row by row
   int gram_fly;   // 1: Gram rows of the picks computed from the atoms (ablation A2)
   int refactor;   // 1: the factor of A_S^T A_S rebuilt from the Gram at every step (ablation A3)
+  int gram_dom;   // 1: Gram-domain form (correlations from P and G, no residual vectors)
+  float *P;       // [Bp][Np] Gram-domain form: P = Y A^T, the correlations of y (else nullptr)
 };
 
-size_t work_bytes(int64_t M, int64_t N, int64_t B, int S, int precision, int cfg);
-WorkView work_view(void *mem, int64_t M, int64_t N, int64_t B, int S, int precision, int cfg);
+// `gram_dom` adds the Gram-domain form's P buffer to the layout.
+size_t work_bytes(int64_t M, int64_t N, int64_t B, int S, int precision, int cfg, bool gram_dom = false);
+WorkView work_view(void *mem, int64_t M, int64_t N, int64_t B, int S, int precision, int cfg,
+                   bool gram_dom = false);
 
 // ---- the solve kernel's LDS (shared by its launcher and the entry points'
 // validation) ---------------------------------------------------------------
@@ -167,6 +171,10 @@ hipError_t launch_init(const float *Y, int64_t ldy, const int32_t *S_per, const 
                        hipStream_t st);
 // Correlation A^T R with the fused select epilogue -> w.part.
 hipError_t launch_corr_select(const DictView &d, const WorkView &w, int precision, hipStream_t st);
+// Gram-domain form: P = R32 A32^T (R32 holds y after the init) through the FP32 MFMA product.
+hipError_t launch_project(const DictView &d, const WorkView &w, hipStream_t st);
+// Gram-domain form: c = P - G[:, S] x for every live signal, its best atom's key -> w.part[b].
+hipError_t launch_gram_select(const DictView &d, const WorkView &w, hipStream_t st);
 // One OMP step per live signal: stop test, pick, Cholesky append, both solves.
 hipError_t launch_solve(const DictView &d, const WorkView &w, int precision, hipStream_t st);
 // Residual r = y - A_S x (and its BF16 copy and per-slice norms) for the signals just updated.

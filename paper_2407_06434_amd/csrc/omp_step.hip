@@ -864,17 +864,20 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
       const int i = lane + 64 * p;
       g[p] = (i < k && !w.gram_fly) ? d.G[(int64_t)nstar * d.Np + si[p]] : 0.f;
     }
-    const int na[1] = {nstar};
-    double ar[1];
-    atom_dots<1, 4>(d, na, r4, lane, ar);
-    cdot = ar[0];
+    if (!w.gram_dom) {  // the Gram-domain form keeps no residual vectors
+      const int na[1] = {nstar};
+      double ar[1];
+      atom_dots<1, 4>(d, na, r4, lane, ar);
+      cdot = ar[0];
+    }
   }
   if (w.gram_fly) gram_row_from_atoms<RPL>(d, nstar, si, k, lane, g);
   // beta = a_n*^T y = a_n*^T r + sum_j G[n*, s_j] x_j (r = y - A_{k-1} x_{k-1})
   double gx = 0.0;
 #pragma unroll
   for (int p = 0; p < RPL; ++p) gx += (double)g[p] * (double)xo[p];
-  const double beta = cdot + wave_sum(gx);
+  double beta = cdot + wave_sum(gx);
+  if (w.gram_dom) beta = (double)w.P[b * w.Np + nstar];  // the stored a_n*^T y
   if (widened) fl |= OMP_SIG_WIDENED;
   __builtin_amdgcn_s_waitcnt(0);  // the global-to-LDS loads have landed
   wave_lds_sync();
@@ -961,6 +964,13 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
   for (int p = 0; p < RPL; ++p) zu += (double)z[p] * (double)uo[p];
   zu = wave_sum(zu);
   const float uk = (float)((beta - zu) / (double)dk);
+  if (w.gram_dom && lane == 0) {
+    // Gram-domain form: ||r_k||^2 = ||r_{k-1}||^2 - u_k^2 (u_k is y's component
+    // along the new orthonormal direction), kept in FP64 where the residual
+    // kernel would have left the slice norms
+    const double ud = (beta - zu) / (double)dk;
+    w.pnorm[b * NSLICE_MAX] = fmax(rn * rn - ud * ud, 0.0);
+  }
 
   // 7. Append row k of V, u_k and n* (LDS and memory).
   const int64_t rk = (int64_t)k * (k + 1) / 2;
@@ -1061,6 +1071,52 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
   return;
 stop:
   stop_signal<SLOTS>(w, sv, b, stopfl, k, rn, lane);
+}
+
+// ---------------------------------------------------------------------------
+// Gram-domain select (tall dictionaries; the Gram solver of Section 2.1): the
+// correlations of the current residual are c_n = P[b][n] - sum_j G[s_j][n] x_j
+// (P = A^T y once per signal; G is symmetric, so row s_j of G is its column),
+// scored |c_n| / ||a_n|| over the atoms not yet selected, and the best atom's
+// key (the FP32 correlation epilogue's key format) goes to w.part[b]. One
+// 256-lane block per live signal; lane t takes atoms t, t + 256, ... so that
+// every G row is read in whole 1 KiB runs.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_gram_select(DictView d, WorkView w) {
+  __shared__ int ss[OMP_MAX_S];
+  __shared__ float xs[OMP_MAX_S];
+  __shared__ uint64_t best[4];
+  const int64_t b = blockIdx.x;
+  if (w.flags[b] & FLAG_DONE) return;  // the whole block leaves
+  const int k = __builtin_amdgcn_readfirstlane(w.k[b]);
+  const int S = w.S;
+  for (int j = threadIdx.x; j < k; j += blockDim.x) {
+    ss[j] = w.sup[b * S + j];
+    xs[j] = w.xh[b * S + j];
+  }
+  __syncthreads();
+  const int64_t Np = d.Np;
+  const float *Pb = w.P + b * Np;
+  const uint32_t *mk = w.mask + b * (Np / 32);
+  uint64_t kbest = 0;
+  for (int64_t n = threadIdx.x; n < Np; n += blockDim.x) {
+    float c = Pb[n];
+    for (int j = 0; j < k; ++j) c = fmaf(-d.G[(int64_t)ss[j] * Np + n], xs[j], c);
+    const float iv = d.inv_nu[n];
+    const bool taken = (mk[n >> 5] >> (n & 31)) & 1u;
+    if (iv > 0.f && !taken) {
+      const uint64_t key = ((uint64_t)__float_as_uint(fabsf(c) * iv) << 32) | (0xFFFFFFFFull - (uint64_t)n);
+      kbest = key > kbest ? key : kbest;
+    }
+  }
+  kbest = wave_max(kbest);
+  if ((threadIdx.x & 63) == 0) best[threadIdx.x >> 6] = kbest;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t m = best[0];
+    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) m = best[i] > m ? best[i] : m;
+    w.part[b] = m;  // one key per signal (ntile = ncand = 1 in this form)
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1321,6 +1377,13 @@ hipError_t launch_residual_lp(const DictView &d, const WorkView &w, int precisio
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_residual<false>, grid, block, lds, st, d, w, LP);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_select(const DictView &d, const WorkView &w, hipStream_t st) {
+  if (!w.gram_dom || !w.P || w.ntile != 1 || w.ncand != 1 || w.R16 || w.Np != d.Np || w.S > OMP_MAX_S)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_gram_select, dim3((unsigned)w.B), dim3(256), 0, st, d, w);
   return hipGetLastError();
 }
 

@@ -58,7 +58,8 @@ class OmpOptsStruct(ctypes.Structure):
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
                 ("phase_ms", ctypes.POINTER(ctypes.c_float)),
                 ("phase_launches", ctypes.POINTER(ctypes.c_int32)), ("use_graph", ctypes.c_int32),
-                ("gram_on_the_fly", ctypes.c_int32), ("refactor", ctypes.c_int32)]
+                ("gram_on_the_fly", ctypes.c_int32), ("refactor", ctypes.c_int32),
+                ("gram_domain", ctypes.c_int32)]
 
 
 class OmpProblemStruct(ctypes.Structure):
@@ -209,7 +210,7 @@ def solve(A: torch.Tensor, Y: torch.Tensor, S: int, eps: float = 0.0, *, precisi
           eps_per_signal: Optional[torch.Tensor] = None, dense: bool = True,
           workspace: Optional[torch.Tensor] = None, out: Optional[Result] = None, stream=None,
           timing: Optional[dict] = None, tile_config: int = 0, graph: bool = True,
-          gram_on_the_fly: bool = False, refactor: bool = False) -> Result:
+          gram_on_the_fly: bool = False, refactor: bool = False, gram_domain: bool = False) -> Result:
     """Batched OMP (Algorithm 1) on the GPU.
 
     A: (N, M) float32 atom-major dictionary; Y: (B, M) float32 signals.
@@ -223,7 +224,9 @@ def solve(A: torch.Tensor, Y: torch.Tensor, S: int, eps: float = 0.0, *, precisi
     `gram_on_the_fly` (ablation only) computes each pick's Gram row from the atoms
     instead of reading the prepared Gram matrix; `refactor` (ablation only) rebuilds
     the Cholesky factor of the support's Gram block at every step instead of
-    appending one row to it.
+    appending one row to it. `gram_domain` (FP32 only; for tall dictionaries, M >= N)
+    takes each step's correlations from P = A^T y and the Gram matrix instead of from
+    residual vectors.
     """
     _check_matrix(A, "A")
     N, M = A.shape
@@ -238,6 +241,7 @@ def solve(A: torch.Tensor, Y: torch.Tensor, S: int, eps: float = 0.0, *, precisi
     o.use_graph = 1 if graph else 0
     o.gram_on_the_fly = 1 if gram_on_the_fly else 0
     o.refactor = 1 if refactor else 0
+    o.gram_domain = 1 if gram_domain else 0
     if dictionary is not None:
         if dictionary.A is not A or dictionary.precision != precision:
             raise ValueError("dictionary was prepared for another A or precision")

@@ -148,6 +148,16 @@ def bf16_1024x4096(B: int = 4096) -> Workload:
                     true_support=sup, true_values=vals, sigma=sig)
 
 
+def face_8064x1207(B: int = 1200) -> Workload:
+    """Tall dictionary of the face-recognition shape (8064-pixel images, 1207 training
+    faces, S=30, B=1.2K; Section 4.2): unit-norm N(0,1/M) atoms standing in for the
+    normalised face images, 30-sparse +-(1+|N|) x at 30 dB SNR."""
+    A64 = gaussian_dictionary(8064, 1207, 1004, "unit")
+    Y, sup, vals, sig = sparse_signals(A64, B, np.full(B, 30), 2004, "pm", snr_db=30.0)
+    return Workload("face_8064x1207", A64.astype(np.float32), Y, 30, 0.0,
+                    true_support=sup, true_values=vals, sigma=sig)
+
+
 def uneven_pair(B_each: int = 10000):
     """Two dictionaries (128x512 and 512x2048, N(0,1/M)); per-signal S_i ~ U{4..64};
     true sparsity S_i; noise at 60 dB; eps_i = 1e-2 ||y_i||. Returns two Workloads."""

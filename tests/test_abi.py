@@ -131,6 +131,28 @@ def test_solve_rejects_bad_ablation_flag(lib):
     o.refactor = -1
     rc = lib.omp_solve(FAKE, 64, 256, 64, FAKE, 10, 64, 8, 0.0, FAKE, FAKE, ctypes.byref(o), None)
     assert rc == omp.OMP_EINVAL
+    o = _opts()
+    o.gram_domain = 3
+    rc = lib.omp_solve(FAKE, 64, 256, 64, FAKE, 10, 64, 8, 0.0, FAKE, FAKE, ctypes.byref(o), None)
+    assert rc == omp.OMP_EINVAL
+
+
+def test_gram_domain_form(lib):
+    """The Gram-domain form is FP32 only, and its workspace holds P (B_pad x N_pad floats)."""
+    from paper_2407_06434_amd import omp
+    o = _opts()
+    o.gram_domain = 1
+    o.precision = omp.PREC["bf16"]
+    rc = lib.omp_solve(FAKE, 64, 256, 64, FAKE, 10, 64, 8, 0.0, FAKE, FAKE, ctypes.byref(o), None)
+    assert rc == omp.OMP_EINVAL
+    a = omp.OmpOptsStruct()
+    lib.omp_opts_default(ctypes.byref(a))
+    g = omp.OmpOptsStruct()
+    lib.omp_opts_default(ctypes.byref(g))
+    g.gram_domain = 1
+    s0 = lib.omp_workspace_size(2048, 1000, 300, 30, ctypes.byref(a))
+    s1 = lib.omp_workspace_size(2048, 1000, 300, 30, ctypes.byref(g))
+    assert s1 - s0 >= 512 * 1024 * 4
 
 
 def test_solve_beyond_limits_is_not_supported(lib):

@@ -406,3 +406,54 @@ def test_refactorisation_each_step(orc, prec, S):
     print("same supports as the progressive update:", same)
     assert same >= 0.95
 
+
+@pytest.mark.parametrize("M,N,B,S,eps_frac", [(512, 128, 100, 20, 0.0), (300, 300, 64, 40, 0.0),
+                                              (1000, 700, 90, 30, 0.0), (640, 260, 77, 24, 0.05)])
+def test_gram_domain_form(orc, M, N, B, S, eps_frac):
+    """Gram-domain form (tall dictionaries): correlations from P = A^T y and G, no residual
+    vectors; the oracle's picks and, up to near-ties, the residual-vector form's supports.
+    With eps_frac > 0 every signal gets eps_b = eps_frac ||y_b|| (the running ||r||^2
+    decides the stop)."""
+    torch = _torch()
+    from paper_2407_06434_amd import omp, workloads
+    w = workloads.custom(M, N, B, S, seed=M + N, k_true=S, column_norm="unit")
+    kw = {}
+    if eps_frac > 0:
+        w.eps_per_signal = (eps_frac * np.linalg.norm(w.Y.astype(np.float64), axis=1)).astype(np.float32)
+    dev = torch.device("cuda:0")
+    A = torch.from_numpy(w.A).to(dev)
+    Y = torch.from_numpy(w.Y).to(dev)
+    if eps_frac > 0:
+        kw["eps_per_signal"] = torch.from_numpy(w.eps_per_signal).to(dev)
+    print(f"case Gram-domain form M={M} N={N} B={B} S={S} eps_frac={eps_frac}", flush=True)
+    a = omp.solve(A, Y, w.S, precision="fp32", **kw)
+    g = omp.solve(A, Y, w.S, precision="fp32", gram_domain=True, **kw)
+    torch.cuda.synchronize()
+    out = {k: v.cpu().numpy() for k, v in g._asdict().items() if v is not None}
+    rep = parity.check(w, out, orc)
+    print(rep)
+    same = np.mean([set(x.tolist()) == set(y.tolist()) for x, y in zip(a.support.cpu().numpy(), out["support"])])
+    print("same supports as the residual-vector form:", same)
+    assert same >= 0.95
+
+
+def test_gram_domain_face_shape_sampled(orc):
+    """The face-recognition shape (8064 x 1207, S = 30, B = 1200) in the Gram-domain form,
+    24 sampled signals against the oracle; graph replays equal direct launches."""
+    torch = _torch()
+    from paper_2407_06434_amd import omp, workloads
+    w = workloads.face_8064x1207()
+    dev = torch.device("cuda:0")
+    A = torch.from_numpy(w.A).to(dev)
+    Y = torch.from_numpy(w.Y).to(dev)
+    print("case Gram-domain form 8064x1207 B=1200 S=30", flush=True)
+    d = omp.Dictionary(A, "fp32")
+    g1 = omp.solve(A, Y, w.S, precision="fp32", dictionary=d, gram_domain=True)
+    g2 = omp.solve(A, Y, w.S, precision="fp32", dictionary=d, gram_domain=True, graph=False)
+    torch.cuda.synchronize()
+    assert torch.equal(g1.support, g2.support) and torch.equal(g1.coef, g2.coef)
+    out = {k: v.cpu().numpy() for k, v in g1._asdict().items() if v is not None}
+    idx = np.sort(np.random.default_rng(5).choice(w.B, 24, replace=False))
+    rep = parity.check(w, out, orc, idx=idx)
+    print(rep)
+
