@@ -20,7 +20,8 @@ def _torch():
     return torch
 
 
-def run_gpu(w, precision="fp32", dense=True, S_per=None, eps_per=None, dictionary=False, A_pad=0, Y_pad=0):
+def run_gpu(w, precision="fp32", dense=True, S_per=None, eps_per=None, dictionary=False, A_pad=0, Y_pad=0,
+            gram_domain=False):
     torch = _torch()
     from paper_2407_06434_amd import omp
     dev = torch.device("cuda:0")
@@ -40,7 +41,7 @@ def run_gpu(w, precision="fp32", dense=True, S_per=None, eps_per=None, dictionar
     if eps_per is not None:
         kw["eps_per_signal"] = torch.from_numpy(np.asarray(eps_per, np.float32)).to(dev)
     d = omp.Dictionary(A, precision) if dictionary else None
-    res = omp.solve(A, Y, w.S, w.eps, precision=precision, dictionary=d, dense=dense, **kw)
+    res = omp.solve(A, Y, w.S, w.eps, precision=precision, dictionary=d, dense=dense, gram_domain=gram_domain, **kw)
     torch.cuda.synchronize()
     out = dict(support=res.support.cpu().numpy(), coef=res.coef.cpu().numpy(),
                status=res.status.cpu().numpy(), rnorm=res.rnorm.cpu().numpy())
@@ -50,6 +51,13 @@ def run_gpu(w, precision="fp32", dense=True, S_per=None, eps_per=None, dictionar
 
 
 PRECS = ["fp32", "bf16"]
+# every form of the solve: the two precisions of the residual-vector form and the
+# Gram-domain form (FP32)
+FORMS = ["fp32", "bf16", "gram"]
+
+
+def _form(f):
+    return ("fp32", True) if f == "gram" else (f, False)
 
 
 @pytest.mark.parametrize("prec", PRECS)
@@ -124,9 +132,10 @@ def test_bf16_same_supports_as_fp32_full_batch(orc):
     assert rel < 1e-4
 
 
-@pytest.mark.parametrize("prec", PRECS)
-def test_edge_cases(orc, prec):
+@pytest.mark.parametrize("form", FORMS)
+def test_edge_cases(orc, form):
     """y = 0, non-finite y, eps >= ||y||, per-signal S and eps, a dependent atom, a zero atom."""
+    prec, gd = _form(form)
     from paper_2407_06434_amd import workloads
     w = workloads.custom(48, 160, 12, 8, seed=3, k_true=6)
     w.A[17] = 0.0            # zero-norm atom: never selectable
@@ -139,8 +148,8 @@ def test_edge_cases(orc, prec):
     eps_per[6] = 1e9                                   # eps >= ||y||: k = 0
     eps_per[7] = 0.3 * np.linalg.norm(w.Y[7].astype(np.float64))
     w.S_per_signal, w.eps_per_signal = S_per, eps_per
-    print("case edge cases", flush=True)
-    out = run_gpu(w, prec, S_per=S_per, eps_per=eps_per)
+    print(f"case edge cases {form}", flush=True)
+    out = run_gpu(w, prec, S_per=S_per, eps_per=eps_per, gram_domain=gd)
     rep = parity.check(w, out, orc)
     print(rep)
     st = out["status"]
@@ -151,9 +160,10 @@ def test_edge_cases(orc, prec):
     assert not np.any(out["support"] == 17)
 
 
-@pytest.mark.parametrize("prec", PRECS)
-def test_dependent_atom_stops(orc, prec):
+@pytest.mark.parametrize("form", FORMS)
+def test_dependent_atom_stops(orc, form):
     """Two atoms 1e-4 rad apart: the second pick is dependent and is not appended."""
+    prec, gd = _form(form)
     from paper_2407_06434_amd import workloads
     a0 = np.zeros(64); a0[0] = 1.0
     a1 = np.zeros(64); a1[0] = 1.0; a1[1] = 1e-4
@@ -161,7 +171,8 @@ def test_dependent_atom_stops(orc, prec):
     A = np.zeros((128, 64)); A[0] = a0; A[1] = a1
     y = a1 + 0.01 * np.eye(64)[2]
     w = workloads.Workload("dep", A.astype(np.float32), y[None].astype(np.float32), 2, 0.0)
-    out = run_gpu(w, prec)
+    print(f"case dependent atom {form}", flush=True)
+    out = run_gpu(w, prec, gram_domain=gd)
     rep = parity.check(w, out, orc)
     print(rep)
     assert out["status"][0] & 4 and out["status"][0] >> 8 == 1
