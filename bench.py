@@ -364,8 +364,32 @@ def run_gram_domain(steps=3, warmup=1):
         dt = (time.perf_counter() - t0) / steps
         res[name] = dict(value=round(w.B / dt, 1), ms_per_call=round(1e3 * dt, 3), support=out.support.cpu().numpy())
         del d
+    # per-kernel figures of the Gram-domain form: one more call with the library's
+    # HIP events around every launch (direct launches)
+    d = omp.Dictionary(A, "fp32")
+    tim = {}
+    omp.solve(A, Y, w.S, precision="fp32", dictionary=d, gram_domain=True, timing=tim)
+    del d
+    Np = -(-w.N // 256) * 256
+    kavg = (w.S - 1) / 2.0  # support size averaged over the S steps (every signal runs S steps here)
+    ms, n = tim["corr"]
+    sel_ms = ms / max(n, 1)
+    hbm_min = w.B * (4 * Np + Np / 8 + 8)  # P row, mask, key
+    g_rows = w.B * 4 * Np * kavg           # G rows of the support, served by the caches
+    ums, un = tim["update"]
+    ims, inn = tim["init"]
+    kernels = {
+        "k_gram_select": dict(bound="l2", avg_launch_ms=round(sel_ms, 5), launches=n,
+                              hbm_min_bytes_per_launch=float(f"{hbm_min:.5e}"),
+                              hbm_min_GBps=round(hbm_min / (sel_ms * 1e-3) / 1e9, 1),
+                              g_row_bytes_per_launch=float(f"{g_rows:.5e}"),
+                              g_row_GBps=round(g_rows / (sel_ms * 1e-3) / 1e9, 1)),
+        "k_solve": dict(avg_launch_ms=round(ums / max(un, 1), 5), launches=un),
+        "init_and_projection": dict(total_ms=round(ims, 4), launches=inn,
+                                    projection_flop=float(f"{2.0 * (-(-w.B // 256) * 256) * Np * w.M:.5e}")),
+    }
     ref = res["residual_fp32"]["support"]
-    line = {"workload": f"{w.name}_B{w.B}_S{w.S}", "unit": "signals/s"}
+    line = {"workload": f"{w.name}_B{w.B}_S{w.S}", "unit": "signals/s", "kernels": kernels}
     for name, r in res.items():
         same = sum(set(a.tolist()) == set(b.tolist()) for a, b in zip(r.pop("support"), ref))
         line[name] = dict(r, same_supports_as_residual_fp32=f"{same}/{w.B}")
@@ -452,6 +476,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal measurement")
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the benchmark step, run the paper's parameter sweep and print its speed map")
+    ap.add_argument("--only-gram-domain", action="store_true",
+                    help="run only the Gram-domain measurement on the face-recognition shape and print it")
     ap.add_argument("--no-gram-domain", action="store_true",
                     help="skip the Gram-domain measurement on the tall face-recognition shape")
     ap.add_argument("--no-ablations", action="store_true",
@@ -466,6 +492,9 @@ def main():
               f"(the batch would shard by signals with no in-loop communication).", file=sys.stderr)
         sys.exit(2)
 
+    if args.only_gram_domain:
+        print(json.dumps(dict(metric="gram_domain", data="synthetic", **run_gram_domain())), flush=True)
+        return
     if args.sweep:
         cells = run_sweep(args.precision)
         print(json.dumps({"metric": "parameter_sweep", "unit": "signals/s", "dtype": args.precision,

@@ -26,21 +26,27 @@ namespace {
 // Mp floats long, ntn tiles of X rows): the Gram matrix G = A32 A32^T, and in
 // the Gram-domain form P = R32 A32^T (signal-major, the correlations of every
 // signal with every atom). Lanes 0-31 of a fragment row store 32 consecutive
-// columns.
+// columns. With several K chunks (split K) workgroup chunk c sums the K slices
+// [c * csl, (c + 1) * csl) and stores into its own partial matrix
+// G + c * cstride; k_sum_chunks then adds the partials in chunk order.
 // ---------------------------------------------------------------------------
 using GramTile = Tile<128, 128, 2, 2>;
 
 __global__ __launch_bounds__(GramTile::NTHR) void k_gram(const float *__restrict__ X, const float *__restrict__ Z,
-                                                         int64_t Mp, int ntn, float *__restrict__ G,
-                                                         int64_t ldg) {
+                                                         int64_t Mp, int ntn, int ntm, int csl,
+                                                         float *__restrict__ G, int64_t ldg, int64_t cstride) {
   using T = GramTile;
   extern __shared__ u32x4 lds[];
-  const int tn = blockIdx.x % ntn, tm = blockIdx.x / ntn;
+  const int tile = blockIdx.x % (ntn * ntm), chunk = blockIdx.x / (ntn * ntm);
+  const int tn = tile % ntn, tm = tile / ntn;
   const int64_t rs = Mp / 4;  // row stride in 16-byte chunks
-  const u32x4 *P = reinterpret_cast<const u32x4 *>(X) + (int64_t)tn * T::TN * rs;
-  const u32x4 *Q = reinterpret_cast<const u32x4 *>(Z) + (int64_t)tm * T::TB * rs;
+  const int nsl = (int)(rs / T::CH), s0 = chunk * csl;
+  const int cnt = nsl - s0 < csl ? nsl - s0 : csl;  // >= 1 (checked by the launchers)
+  const u32x4 *P = reinterpret_cast<const u32x4 *>(X) + (int64_t)tn * T::TN * rs + (int64_t)s0 * T::CH;
+  const u32x4 *Q = reinterpret_cast<const u32x4 *>(Z) + (int64_t)tm * T::TB * rs + (int64_t)s0 * T::CH;
+  G += (int64_t)chunk * cstride;
   f32x16 acc[T::FN][T::FB];
-  mainloop<OpF32, T>(P, rs, Q, rs, (int)(rs / T::CH), lds, acc);
+  mainloop<OpF32, T>(P, rs, Q, rs, cnt, lds, acc);
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wn = wave % T::WN, wb = wave / T::WN;
@@ -324,9 +330,26 @@ hipError_t launch_gram(const DictView &d, hipStream_t st) {
   hipError_t e = set_lds(k_gram, T::LDS_BYTES);
   if (e != hipSuccess) return e;
   const int nt = (int)(d.Np / T::TN);
-  hipLaunchKernelGGL(k_gram, dim3(nt * nt), dim3(T::NTHR), T::LDS_BYTES, st, d.A32, d.A32, d.Mp, nt, d.G,
-                     d.Np);
+  const int nsl = (int)(d.Mp / 4 / T::CH);
+  hipLaunchKernelGGL(k_gram, dim3(nt * nt), dim3(T::NTHR), T::LDS_BYTES, st, d.A32, d.A32, d.Mp, nt, nt, nsl,
+                     d.G, d.Np, (int64_t)0);
   return hipGetLastError();
+}
+
+// P[i] = sum over chunks c, in chunk order, of Pk[c][i]; four floats per lane.
+__global__ __launch_bounds__(256) void k_sum_chunks(const float4 *__restrict__ Pk, int chunks, int64_t n4,
+                                                    float4 *__restrict__ P) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n4) return;
+  float4 a = Pk[i];
+  for (int c = 1; c < chunks; ++c) {
+    const float4 v = Pk[(int64_t)c * n4 + i];
+    a.x += v.x;
+    a.y += v.y;
+    a.z += v.z;
+    a.w += v.w;
+  }
+  P[i] = a;
 }
 
 hipError_t launch_project(const DictView &d, const WorkView &w, hipStream_t st) {
@@ -336,8 +359,17 @@ hipError_t launch_project(const DictView &d, const WorkView &w, hipStream_t st) 
   hipError_t e = set_lds(k_gram, T::LDS_BYTES);
   if (e != hipSuccess) return e;
   const int ntb = (int)(w.Bp / T::TN), nta = (int)(d.Np / T::TB);
-  hipLaunchKernelGGL(k_gram, dim3(ntb * nta), dim3(T::NTHR), T::LDS_BYTES, st, w.R32, d.A32, d.Mp, ntb, w.P,
-                     d.Np);
+  const int nsl = (int)(d.Mp / 4 / T::CH), ks = w.pchunks;
+  const int csl = ks >= 1 ? (nsl + ks - 1) / ks : 0;
+  if (ks < 1 || (ks > 1 && !w.Pk) || nsl - (ks - 1) * csl < 1) return hipErrorInvalidValue;
+  const int64_t n = w.Bp * d.Np;
+  hipLaunchKernelGGL(k_gram, dim3(ntb * nta * ks), dim3(T::NTHR), T::LDS_BYTES, st, w.R32, d.A32, d.Mp, ntb, nta,
+                     csl, ks > 1 ? w.Pk : w.P, d.Np, n);
+  e = hipGetLastError();
+  if (e != hipSuccess || ks == 1) return e;
+  const int64_t n4 = n / 4;
+  hipLaunchKernelGGL(k_sum_chunks, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, st,
+                     reinterpret_cast<const float4 *>(w.Pk), ks, n4, reinterpret_cast<float4 *>(w.P));
   return hipGetLastError();
 }
 

@@ -61,7 +61,8 @@ struct WorkLayout {
   int ntile;
   int nslice, slice_len;
   int64_t vstride;
-  size_t Yp, R32, R16, part, mask, k, flags, pnorm, pdelta, Sb, epsb, sup, u, xh, V, P, total;
+  size_t Yp, R32, R16, part, mask, k, flags, pnorm, pdelta, Sb, epsb, sup, u, xh, V, P, Pk, total;
+  int pchunks;
 };
 
 WorkLayout work_layout(int64_t M, int64_t N, int64_t B, int S, int precision, int cfg, bool gram_dom = false) {
@@ -93,6 +94,8 @@ WorkLayout work_layout(int64_t M, int64_t N, int64_t B, int S, int precision, in
   L.vstride = round_up((int64_t)(Sz * (Sz + 1) / 2), 4);
   L.V = c.take<float>(Bp * (size_t)L.vstride);
   L.P = gram_dom ? c.take<float>(Bp * (size_t)L.Np) : 0;
+  L.pchunks = gram_dom ? project_chunks(L.Bp, L.Np, L.Mp) : 1;
+  L.Pk = L.pchunks > 1 ? c.take<float>((size_t)L.pchunks * Bp * (size_t)L.Np) : 0;
   L.total = (c.off + ALIGN - 1) / ALIGN * ALIGN;
   return L;
 }
@@ -276,6 +279,8 @@ WorkView work_view(void *mem, int64_t M, int64_t N, int64_t B, int S, int precis
   w.refactor = 0;
   w.gram_dom = gram_dom ? 1 : 0;
   w.P = gram_dom ? at<float>(mem, L.P) : nullptr;
+  w.pchunks = L.pchunks;
+  w.Pk = L.pchunks > 1 ? at<float>(mem, L.Pk) : nullptr;
   if (gram_dom) w.ntile = 1;  // one key per signal, from the Gram-domain select
   return w;
 }

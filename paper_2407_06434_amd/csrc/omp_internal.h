@@ -87,7 +87,19 @@ struct WorkView {
   int refactor;   // 1: the factor of A_S^T A_S rebuilt from the Gram at every step (ablation A3)
   int gram_dom;   // 1: Gram-domain form (correlations from P and G, no residual vectors)
   float *P;       // [Bp][Np] Gram-domain form: P = Y A^T, the correlations of y (else nullptr)
+  float *Pk;      // [pchunks][Bp][Np] split-K partial products of P (pchunks > 1), else nullptr
+  int pchunks;    // K chunks of the P product (1: no split)
 };
+
+// K chunks of the Gram-domain form's product P = Y A^T on 128 x 128 tiles: split
+// until about 512 workgroups run, each chunk keeping at least 16 K slices of 32
+// floats (so every chunk is non-empty), at most 8 chunks.
+inline int project_chunks(int64_t Bp, int64_t Np, int64_t Mp) {
+  const int64_t tiles = (Bp / 128) * (Np / 128), nsl = Mp / 32;
+  int ks = 1;
+  while (ks < 8 && tiles * ks < 512 && nsl / (ks * 2) >= 16) ks *= 2;
+  return ks;
+}
 
 // `gram_dom` adds the Gram-domain form's P buffer to the layout.
 size_t work_bytes(int64_t M, int64_t N, int64_t B, int S, int precision, int cfg, bool gram_dom = false);
