@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <algorithm>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -80,7 +81,9 @@ WorkLayout work_layout(int64_t M, int64_t N, int64_t B, int S, int precision, in
   L.Yp = c.take<float>(Bp * L.Mp);
   L.R32 = c.take<float>(Bp * L.Mp);
   L.R16 = precision == OMP_PREC_BF16 ? c.take<uint16_t>(Bp * L.Mp) : 0;
-  L.part = c.take<uint64_t>(Bp * L.ntile * L.g.keys_per_tile);
+  // (the Gram-domain select writes GSLICE keys per signal)
+  L.part = c.take<uint64_t>(Bp * (size_t)std::max<int64_t>((int64_t)L.ntile * L.g.keys_per_tile,
+                                                            gram_dom ? GSLICE : 1));
   L.mask = c.take<uint32_t>(Bp * (L.Np / 32));
   L.k = c.take<int32_t>(Bp);
   L.flags = c.take<int32_t>(Bp);
@@ -281,7 +284,7 @@ WorkView work_view(void *mem, int64_t M, int64_t N, int64_t B, int S, int precis
   w.P = gram_dom ? at<float>(mem, L.P) : nullptr;
   w.pchunks = L.pchunks;
   w.Pk = L.pchunks > 1 ? at<float>(mem, L.Pk) : nullptr;
-  if (gram_dom) w.ntile = 1;  // one key per signal, from the Gram-domain select
+  if (gram_dom) w.ntile = GSLICE;  // one key per (signal, atom slice) from the Gram-domain select
   return w;
 }
 

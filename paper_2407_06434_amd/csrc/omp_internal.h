@@ -91,6 +91,10 @@ struct WorkView {
   int pchunks;    // K chunks of the P product (1: no split)
 };
 
+// Gram-domain select: the atoms are split into this many contiguous slices, one
+// per XCD, each giving one key per signal.
+constexpr int GSLICE = 8;
+
 // K chunks of the Gram-domain form's product P = Y A^T on 128 x 128 tiles: split
 // until about 512 workgroups run, each chunk keeping at least 16 K slices of 32
 // floats (so every chunk is non-empty), at most 8 chunks.

@@ -1077,46 +1077,81 @@ stop:
 // Gram-domain select (tall dictionaries; the Gram solver of Section 2.1): the
 // correlations of the current residual are c_n = P[b][n] - sum_j G[s_j][n] x_j
 // (P = A^T y once per signal; G is symmetric, so row s_j of G is its column),
-// scored |c_n| / ||a_n|| over the atoms not yet selected, and the best atom's
-// key (the FP32 correlation epilogue's key format) goes to w.part[b]. One
-// 256-lane block per live signal; lane t takes atoms t, t + 256, ... so that
-// every G row is read in whole 1 KiB runs.
+// scored |c_n| / ||a_n|| over the atoms not yet selected, each slice's best
+// atom carried by its key (the FP32 correlation epilogue's key format) in
+// w.part[b][slice]. One wavefront per (signal, atom slice); workgroup i runs
+// on XCD i mod 8 and takes slice i mod GSLICE, so an XCD reads only its
+// 1/GSLICE of the columns of G (L2-resident), in runs of 64 consecutive atoms.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_gram_select(DictView d, WorkView w) {
+__global__ __launch_bounds__(64) void k_gram_select(DictView d, WorkView w) {
   __shared__ int ss[OMP_MAX_S];
   __shared__ float xs[OMP_MAX_S];
-  __shared__ uint64_t best[4];
-  const int64_t b = blockIdx.x;
-  if (w.flags[b] & FLAG_DONE) return;  // the whole block leaves
+  const int64_t b = blockIdx.x / GSLICE;
+  const int x = blockIdx.x % GSLICE;
+  const int lane = threadIdx.x;
+  if (w.flags[b] & FLAG_DONE) return;  // the whole wavefront leaves
   const int k = __builtin_amdgcn_readfirstlane(w.k[b]);
   const int S = w.S;
-  for (int j = threadIdx.x; j < k; j += blockDim.x) {
+  for (int j = lane; j < k; j += 64) {
     ss[j] = w.sup[b * S + j];
     xs[j] = w.xh[b * S + j];
   }
   __syncthreads();
-  const int64_t Np = d.Np;
+  const int64_t Np = d.Np, len = Np / GSLICE;
   const float *Pb = w.P + b * Np;
   const uint32_t *mk = w.mask + b * (Np / 32);
+  // NA atoms per lane at a time and four support rows per round, so that 4 NA
+  // independent loads are in flight before their FMAs (c_n accumulates in
+  // support order). Addresses past the slice are clamped to its last atom and
+  // their results dropped.
+  constexpr int NA = 4;
+  const int64_t end = (x + 1) * len;
   uint64_t kbest = 0;
-  for (int64_t n = threadIdx.x; n < Np; n += blockDim.x) {
-    float c = Pb[n];
-    for (int j = 0; j < k; ++j) c = fmaf(-d.G[(int64_t)ss[j] * Np + n], xs[j], c);
-    const float iv = d.inv_nu[n];
-    const bool taken = (mk[n >> 5] >> (n & 31)) & 1u;
-    if (iv > 0.f && !taken) {
-      const uint64_t key = ((uint64_t)__float_as_uint(fabsf(c) * iv) << 32) | (0xFFFFFFFFull - (uint64_t)n);
-      kbest = key > kbest ? key : kbest;
+  for (int64_t n0 = x * len + lane; n0 < end; n0 += 64 * NA) {
+    int64_t nn[NA];
+    float c[NA];
+#pragma unroll
+    for (int a = 0; a < NA; ++a) {
+      const int64_t n = n0 + 64 * a;
+      nn[a] = n < end ? n : end - 1;
+      c[a] = Pb[nn[a]];
+    }
+    int j = 0;
+    for (; j + 4 <= k; j += 4) {
+      const float *g0 = d.G + (int64_t)ss[j] * Np, *g1 = d.G + (int64_t)ss[j + 1] * Np;
+      const float *g2 = d.G + (int64_t)ss[j + 2] * Np, *g3 = d.G + (int64_t)ss[j + 3] * Np;
+      float v[4][NA];
+#pragma unroll
+      for (int a = 0; a < NA; ++a) {
+        v[0][a] = g0[nn[a]];
+        v[1][a] = g1[nn[a]];
+        v[2][a] = g2[nn[a]];
+        v[3][a] = g3[nn[a]];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int a = 0; a < NA; ++a) c[a] = fmaf(-v[q][a], xs[j + q], c[a]);
+    }
+    for (; j < k; ++j) {
+      const float *g0 = d.G + (int64_t)ss[j] * Np;
+#pragma unroll
+      for (int a = 0; a < NA; ++a) c[a] = fmaf(-g0[nn[a]], xs[j], c[a]);
+    }
+#pragma unroll
+    for (int a = 0; a < NA; ++a) {
+      const int64_t n = n0 + 64 * a;
+      if (n >= end) continue;
+      const float iv = d.inv_nu[n];
+      const bool taken = (mk[n >> 5] >> (n & 31)) & 1u;
+      if (iv > 0.f && !taken) {
+        const uint64_t key = ((uint64_t)__float_as_uint(fabsf(c[a]) * iv) << 32) | (0xFFFFFFFFull - (uint64_t)n);
+        kbest = key > kbest ? key : kbest;
+      }
     }
   }
   kbest = wave_max(kbest);
-  if ((threadIdx.x & 63) == 0) best[threadIdx.x >> 6] = kbest;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint64_t m = best[0];
-    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) m = best[i] > m ? best[i] : m;
-    w.part[b] = m;  // one key per signal (ntile = ncand = 1 in this form)
-  }
+  if (lane == 0) w.part[b * GSLICE + x] = kbest;  // ntile = GSLICE keys per signal in this form
 }
 
 // ---------------------------------------------------------------------------
@@ -1381,9 +1416,10 @@ hipError_t launch_residual_lp(const DictView &d, const WorkView &w, int precisio
 }
 
 hipError_t launch_gram_select(const DictView &d, const WorkView &w, hipStream_t st) {
-  if (!w.gram_dom || !w.P || w.ntile != 1 || w.ncand != 1 || w.R16 || w.Np != d.Np || w.S > OMP_MAX_S)
+  if (!w.gram_dom || !w.P || w.ntile != GSLICE || w.ncand != 1 || w.R16 || w.Np != d.Np || w.S > OMP_MAX_S ||
+      d.Np % (32 * GSLICE))
     return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_gram_select, dim3((unsigned)w.B), dim3(256), 0, st, d, w);
+  hipLaunchKernelGGL(k_gram_select, dim3((unsigned)(w.B * GSLICE)), dim3(64), 0, st, d, w);
   return hipGetLastError();
 }
 
