@@ -149,8 +149,10 @@ typedef struct omp_opts {
                                    eps near the noise floor of y may stop a step apart from the
                                    residual-vector form). Same picks as the default form up to
                                    rounding. FP32 precision only (else OMP_EINVAL); the workspace
-                                   grows by B_pad * N_pad * 4 bytes (omp_workspace_size with the
-                                   same opts). 0 (default): residual vectors. */
+                                   grows by (1 + c) * B_pad * N_pad * 4 bytes, c = 0 or the K
+                                   chunks (2 to 8) of P's product when the tiles alone would leave
+                                   CUs idle (omp_workspace_size with the same opts gives the total).
+                                   0 (default): residual vectors. */
 } omp_opts_t;
 
 /* Phases reported through omp_opts_t.phase_ms. */
