@@ -17,6 +17,13 @@ Workload: A 1024 x 4096 Gaussian N(0, 1/M), a batch of 4096 signals, 64-sparse
 x with values +-(1 + |N(0,1)|), noise at 30 dB SNR per signal, S = 64 and no
 early stop (synthetic stand-in for the paper's unnamed application data).
 
+The same line also carries the measurements beside the benchmark step: plain
+FP32, the paper's ablations on these kernels (batching, Gram precomputation,
+progressive Cholesky), the Gram-domain form on the tall face-recognition shape,
+uneven batches, the learned proposal and the oracle on the host (CPU baseline);
+--no-* flags skip them. Two other modes print their own JSON line instead:
+--sweep (the paper's parameter sweep as a speed map) and --only-gram-domain.
+
 Prints ONE JSON line (rank 0, one GPU).
 """
 from __future__ import annotations

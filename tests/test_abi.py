@@ -153,6 +153,16 @@ def test_gram_domain_form(lib):
     s0 = lib.omp_workspace_size(2048, 1000, 300, 30, ctypes.byref(a))
     s1 = lib.omp_workspace_size(2048, 1000, 300, 30, ctypes.byref(g))
     assert s1 - s0 >= 512 * 1024 * 4
+    # The face-recognition shape (8064 x 1207, B = 1200): 10 x 10 tiles of 128 leave CUs
+    # idle, so P's product is split into 8 K chunks whose partials the workspace holds:
+    # P plus 8 partials of B_pad x N_pad = 1280 x 1280 floats (and 8 keys per signal).
+    f0 = lib.omp_workspace_size(8064, 1207, 1200, 30, ctypes.byref(a))
+    f1 = lib.omp_workspace_size(8064, 1207, 1200, 30, ctypes.byref(g))
+    assert 9 * 1280 * 1280 * 4 <= f1 - f0 < 9 * 1280 * 1280 * 4 + (1 << 20)
+    # The 1024 x 4096 shape at B = 4096 has 1024 tiles: no split, P alone.
+    b0 = lib.omp_workspace_size(1024, 4096, 4096, 64, ctypes.byref(a))
+    b1 = lib.omp_workspace_size(1024, 4096, 4096, 64, ctypes.byref(g))
+    assert 4096 * 4096 * 4 <= b1 - b0 < 4096 * 4096 * 4 + (1 << 20)
 
 
 def test_solve_beyond_limits_is_not_supported(lib):
