@@ -1100,11 +1100,11 @@ __global__ __launch_bounds__(64) void k_gram_select(DictView d, WorkView w) {
   const int64_t Np = d.Np, len = Np / GSLICE;
   const float *Pb = w.P + b * Np;
   const uint32_t *mk = w.mask + b * (Np / 32);
-  // NA atoms per lane at a time and four support rows per round, so that 4 NA
+  // NA atoms per lane at a time and JR support rows per round, so that JR NA
   // independent loads are in flight before their FMAs (c_n accumulates in
   // support order). Addresses past the slice are clamped to its last atom and
   // their results dropped.
-  constexpr int NA = 4;
+  constexpr int NA = 4, JR = 8;
   const int64_t end = (x + 1) * len;
   uint64_t kbest = 0;
   for (int64_t n0 = x * len + lane; n0 < end; n0 += 64 * NA) {
@@ -1117,19 +1117,16 @@ __global__ __launch_bounds__(64) void k_gram_select(DictView d, WorkView w) {
       c[a] = Pb[nn[a]];
     }
     int j = 0;
-    for (; j + 4 <= k; j += 4) {
-      const float *g0 = d.G + (int64_t)ss[j] * Np, *g1 = d.G + (int64_t)ss[j + 1] * Np;
-      const float *g2 = d.G + (int64_t)ss[j + 2] * Np, *g3 = d.G + (int64_t)ss[j + 3] * Np;
-      float v[4][NA];
+    for (; j + JR <= k; j += JR) {
+      float v[JR][NA];
 #pragma unroll
-      for (int a = 0; a < NA; ++a) {
-        v[0][a] = g0[nn[a]];
-        v[1][a] = g1[nn[a]];
-        v[2][a] = g2[nn[a]];
-        v[3][a] = g3[nn[a]];
+      for (int q = 0; q < JR; ++q) {
+        const float *g = d.G + (int64_t)ss[j + q] * Np;
+#pragma unroll
+        for (int a = 0; a < NA; ++a) v[q][a] = g[nn[a]];
       }
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
+      for (int q = 0; q < JR; ++q)
 #pragma unroll
         for (int a = 0; a < NA; ++a) c[a] = fmaf(-v[q][a], xs[j + q], c[a]);
     }
