@@ -22,7 +22,8 @@ FP32, the paper's ablations on these kernels (batching, Gram precomputation,
 progressive Cholesky), the Gram-domain form on the tall face-recognition shape,
 uneven batches, the learned proposal and the oracle on the host (CPU baseline);
 --no-* flags skip them. Two other modes print their own JSON line instead:
---sweep (the paper's parameter sweep as a speed map) and --only-gram-domain.
+--sweep (the paper's parameter sweep as a speed map), --apps (the shapes of its
+application table) and --only-gram-domain.
 
 Prints ONE JSON line (rank 0, one GPU).
 """
@@ -405,6 +406,53 @@ def run_gram_domain(steps=3, warmup=1):
     return line
 
 
+# The paper's realistic-application shapes (Section 4.2) and its v0 GPU figures
+# there (another GPU, precision unstated): context, not a ratio taken here.
+APPS = (("image_patches_256x1024", 256, 1024, 32, 5000, 183904.0),
+        ("face_8064x1207", 8064, 1207, 30, 1200, 25158.0),
+        ("audio_512x2048", 512, 2048, 64, 5000, 28336.0))
+
+
+def run_apps(steps=3, warmup=1):
+    """Signals/s of every form on the shapes of the paper's application table, synthetic
+    stand-ins for its data (image patches: the 256 x 1024 workload's first 5000 signals;
+    face: face_8064x1207; audio: a 512 x 2048 N(0,1/M) dictionary with 64-sparse
+    signals at 30 dB). Graph-replayed calls on prepared dictionaries."""
+    import torch
+    from paper_2407_06434_amd import omp, workloads
+    dev = torch.device("cuda:0")
+    out = []
+    for name, M, N, S, B, paper in APPS:
+        if name.startswith("image"):
+            w = workloads.batched_256x1024(B=B)
+        elif name.startswith("face"):
+            w = workloads.face_8064x1207(B=B)
+        else:
+            w = workloads.custom(M, N, B, S, seed=2048, k_true=S)
+        A = torch.from_numpy(w.A).to(dev)
+        Y = torch.from_numpy(w.Y).to(dev)
+        row = {"workload": name, "M": M, "N": N, "S": S, "B": B, "paper_v0_gpu": paper}
+        forms = [("bf16", "bf16", False), ("fp32", "fp32", False)]
+        if M >= N:
+            forms.append(("gram_domain_fp32", "fp32", True))
+        for fname, prec, gd in forms:
+            d = omp.Dictionary(A, prec)
+            r = None
+            for _ in range(warmup):
+                r = omp.solve(A, Y, S, precision=prec, dictionary=d, out=r, gram_domain=gd)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                r = omp.solve(A, Y, S, precision=prec, dictionary=d, out=r, gram_domain=gd)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            row[fname] = round(B / dt, 1)
+            del d
+        out.append(row)
+        log(f"apps: {row}")
+    return out
+
+
 SWEEP_N = (64, 128, 256, 512, 1024, 2048, 4096, 8192)
 SWEEP_B = (10, 50, 100, 500, 1000, 5000, 10000)
 SWEEP_S = (8, 32, 64)
@@ -483,6 +531,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal measurement")
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the benchmark step, run the paper's parameter sweep and print its speed map")
+    ap.add_argument("--apps", action="store_true",
+                    help="instead of the benchmark step, time every form on the paper's application shapes")
     ap.add_argument("--only-gram-domain", action="store_true",
                     help="run only the Gram-domain measurement on the face-recognition shape and print it")
     ap.add_argument("--no-gram-domain", action="store_true",
@@ -499,6 +549,10 @@ def main():
               f"(the batch would shard by signals with no in-loop communication).", file=sys.stderr)
         sys.exit(2)
 
+    if args.apps:
+        print(json.dumps({"metric": "application_shapes", "unit": "signals/s", "data": "synthetic",
+                          "steps": 3, "rows": run_apps()}), flush=True)
+        return
     if args.only_gram_domain:
         print(json.dumps(dict(metric="gram_domain", data="synthetic", **run_gram_domain())), flush=True)
         return
