@@ -152,7 +152,9 @@ typedef struct omp_opts {
                                    grows by (1 + c) * B_pad * N_pad * 4 bytes, c = 0 or the K
                                    chunks (2 to 8) of P's product when the tiles alone would leave
                                    CUs idle (omp_workspace_size with the same opts gives the total).
-                                   0 (default): residual vectors. */
+                                   2 = automatic: the Gram-domain form for FP32 solves with M >= N,
+                                   the residual-vector form otherwise (the scikit-learn choice).
+                                   0 (default): residual vectors. Other values: OMP_EINVAL. */
 } omp_opts_t;
 
 /* Phases reported through omp_opts_t.phase_ms. */

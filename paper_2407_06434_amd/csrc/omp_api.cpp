@@ -347,13 +347,19 @@ int omp_dict_init(omp_dict_t *dict, const float *A, int64_t M, int64_t N, int64_
   return OMP_OK;
 }
 
+// Whether a solve runs in the Gram-domain form: on request (1), or automatically
+// (2) for FP32 solves of tall dictionaries (M >= N).
+static bool gram_domain_form(int32_t mode, int prec, int64_t M, int64_t N) {
+  return mode == 1 || (mode == 2 && prec == OMP_PREC_FP32 && M >= N);
+}
+
 size_t omp_workspace_size(int64_t M, int64_t N, int64_t B, int32_t S, const omp_opts_t *opts) {
   const int prec = opts ? opts->precision : OMP_PREC_FP32;
   if (!dims_ok(M, N) || B < 0 || B > ((int64_t)1 << 26) || S < 1 || S > OMP_MAX_S) return 0;
   if (prec != OMP_PREC_FP32 && prec != OMP_PREC_BF16) return 0;
   const int cfg = opts ? opts->tile_config : 0;
   if (cfg < 0 || cfg > MAX_TILE_CFG) return 0;
-  size_t total = work_bytes(M, N, B, S, prec, cfg, opts && opts->gram_domain == 1);
+  size_t total = work_bytes(M, N, B, S, prec, cfg, opts && gram_domain_form(opts->gram_domain, prec, M, N));
   if (!opts || !opts->dict) total += dict_bytes(M, N, prec);
   return total;
 }
@@ -369,9 +375,9 @@ int omp_solve(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y,
   if (cfg < 0 || cfg > MAX_TILE_CFG) return OMP_EINVAL;
   if (opts->gram_on_the_fly != 0 && opts->gram_on_the_fly != 1) return OMP_EINVAL;
   if (opts->refactor != 0 && opts->refactor != 1) return OMP_EINVAL;
-  if (opts->gram_domain != 0 && opts->gram_domain != 1) return OMP_EINVAL;
-  if (opts->gram_domain && prec != OMP_PREC_FP32) return OMP_EINVAL;
-  const bool gdom = opts->gram_domain == 1;
+  if (opts->gram_domain < 0 || opts->gram_domain > 2) return OMP_EINVAL;
+  if (opts->gram_domain == 1 && prec != OMP_PREC_FP32) return OMP_EINVAL;
+  const bool gdom = gram_domain_form(opts->gram_domain, prec, M, N);
   if (!dims_ok(M, N) || B < 0 || B > ((int64_t)1 << 26)) return OMP_EINVAL;
   if (S < 1 || S > M || S > N) return OMP_EINVAL;
   if (S > OMP_MAX_S) return OMP_ENOTSUPP;
@@ -469,7 +475,7 @@ int omp_solve(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y,
     key.cfg = cfg;
     key.gram_fly = opts->gram_on_the_fly;
     key.refactor = opts->refactor;
-    key.gram_dom = opts->gram_domain;
+    key.gram_dom = gdom ? 1 : 0;
     std::memcpy(&key.eps_bits, &eps, sizeof(float));
     {
       const DictView dp = opts->dict ? dict_view(opts->dict->mem, M, N, prec)

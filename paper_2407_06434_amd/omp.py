@@ -210,7 +210,7 @@ def solve(A: torch.Tensor, Y: torch.Tensor, S: int, eps: float = 0.0, *, precisi
           eps_per_signal: Optional[torch.Tensor] = None, dense: bool = True,
           workspace: Optional[torch.Tensor] = None, out: Optional[Result] = None, stream=None,
           timing: Optional[dict] = None, tile_config: int = 0, graph: bool = True,
-          gram_on_the_fly: bool = False, refactor: bool = False, gram_domain: bool = False) -> Result:
+          gram_on_the_fly: bool = False, refactor: bool = False, gram_domain=False) -> Result:
     """Batched OMP (Algorithm 1) on the GPU.
 
     A: (N, M) float32 atom-major dictionary; Y: (B, M) float32 signals.
@@ -226,7 +226,7 @@ def solve(A: torch.Tensor, Y: torch.Tensor, S: int, eps: float = 0.0, *, precisi
     the Cholesky factor of the support's Gram block at every step instead of
     appending one row to it. `gram_domain` (FP32 only; for tall dictionaries, M >= N)
     takes each step's correlations from P = A^T y and the Gram matrix instead of from
-    residual vectors.
+    residual vectors; gram_domain="auto" picks that form for FP32 solves with M >= N.
     """
     _check_matrix(A, "A")
     N, M = A.shape
@@ -241,7 +241,7 @@ def solve(A: torch.Tensor, Y: torch.Tensor, S: int, eps: float = 0.0, *, precisi
     o.use_graph = 1 if graph else 0
     o.gram_on_the_fly = 1 if gram_on_the_fly else 0
     o.refactor = 1 if refactor else 0
-    o.gram_domain = 1 if gram_domain else 0
+    o.gram_domain = 2 if gram_domain == "auto" else (1 if gram_domain else 0)
     if dictionary is not None:
         if dictionary.A is not A or dictionary.precision != precision:
             raise ValueError("dictionary was prepared for another A or precision")

@@ -159,6 +159,19 @@ def test_gram_domain_form(lib):
     f0 = lib.omp_workspace_size(8064, 1207, 1200, 30, ctypes.byref(a))
     f1 = lib.omp_workspace_size(8064, 1207, 1200, 30, ctypes.byref(g))
     assert 9 * 1280 * 1280 * 4 <= f1 - f0 < 9 * 1280 * 1280 * 4 + (1 << 20)
+    # Automatic choice (2): the Gram-domain form for FP32 and M >= N only.
+    au = omp.OmpOptsStruct()
+    lib.omp_opts_default(ctypes.byref(au))
+    au.gram_domain = 2
+    assert lib.omp_workspace_size(8064, 1207, 1200, 30, ctypes.byref(au)) == f1
+    assert lib.omp_workspace_size(1024, 4096, 4096, 64, ctypes.byref(au)) == \
+        lib.omp_workspace_size(1024, 4096, 4096, 64, ctypes.byref(a))
+    au.precision = omp.PREC["bf16"]
+    ab = omp.OmpOptsStruct()
+    lib.omp_opts_default(ctypes.byref(ab))
+    ab.precision = omp.PREC["bf16"]
+    assert lib.omp_workspace_size(8064, 1207, 1200, 30, ctypes.byref(au)) == \
+        lib.omp_workspace_size(8064, 1207, 1200, 30, ctypes.byref(ab))
     # The 1024 x 4096 shape at B = 4096 has 1024 tiles: no split, P alone.
     b0 = lib.omp_workspace_size(1024, 4096, 4096, 64, ctypes.byref(a))
     b1 = lib.omp_workspace_size(1024, 4096, 4096, 64, ctypes.byref(g))

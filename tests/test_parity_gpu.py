@@ -468,3 +468,21 @@ def test_gram_domain_face_shape_sampled(orc):
     rep = parity.check(w, out, orc, idx=idx)
     print(rep)
 
+
+@pytest.mark.parametrize("M,N", [(512, 128), (128, 512)])
+def test_gram_domain_automatic_choice(M, N):
+    """gram_domain="auto" gives the Gram-domain form's results bit for bit on a tall
+    dictionary and the residual-vector form's on a wide one."""
+    torch = _torch()
+    from paper_2407_06434_amd import omp, workloads
+    w = workloads.custom(M, N, 60, 16, seed=M + 2 * N, k_true=16, column_norm="unit")
+    dev = torch.device("cuda:0")
+    A = torch.from_numpy(w.A).to(dev)
+    Y = torch.from_numpy(w.Y).to(dev)
+    print(f"case automatic form M={M} N={N}", flush=True)
+    auto = omp.solve(A, Y, w.S, precision="fp32", gram_domain="auto")
+    want = omp.solve(A, Y, w.S, precision="fp32", gram_domain=M >= N)
+    torch.cuda.synchronize()
+    for k in ("support", "coef", "status", "rnorm"):
+        assert torch.equal(getattr(auto, k), getattr(want, k)), k
+
