@@ -52,7 +52,7 @@ extern "C" {
 #define OMP_EINVAL (-1)     /* invalid argument (sizes, null pointers, alignment, NaN eps) */
 #define OMP_EWORKSPACE (-2) /* workspace or dictionary memory missing / too small / misaligned */
 #define OMP_EDEVICE (-3)    /* a HIP runtime call failed, or the device is not gfx950 */
-#define OMP_ENOTSUPP (-4)   /* valid request beyond this build's limits (e.g. S > OMP_MAX_S) */
+#define OMP_ENOTSUPP (-4)   /* valid request beyond the library's limits (e.g. S > OMP_MAX_S) */
 
 /* ---- limits ------------------------------------------------------------ */
 #define OMP_MAX_S 256 /* largest sparsity level S (the Cholesky factor lives in LDS) */

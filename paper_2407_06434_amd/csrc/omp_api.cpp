@@ -302,7 +302,7 @@ const char *omp_status_string(int status) {
     case OMP_EINVAL: return "invalid argument";
     case OMP_EWORKSPACE: return "workspace or dictionary memory missing, too small or misaligned";
     case OMP_EDEVICE: return "HIP runtime error or unsupported device (needs gfx950)";
-    case OMP_ENOTSUPP: return "request exceeds this build's limits";
+    case OMP_ENOTSUPP: return "request exceeds the library's limits";
     default: return "unknown status";
   }
 }

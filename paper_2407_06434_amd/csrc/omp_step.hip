@@ -727,11 +727,11 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
   float *Vs = smem + (size_t)wv * (VS + solve_list_len(w));
   int *clist = reinterpret_cast<int *>(Vs + VS);  // BF16 pick: candidate list (one entry per key at most)
 
-  // ---- round 1: state, residual norms, keys, support, u (none of these
+  // ---- memory round 1: state, residual norms, keys, support, u (none of these
   // addresses depends on another load)
   int fl = w.flags[b];
   const int k = __builtin_amdgcn_readfirstlane(w.k[b]);  // wave-uniform: scalar loop bounds
-  const float eps_b = w.epsb[b];  // read here, with the rest of round 1
+  const float eps_b = w.epsb[b];  // read here, with the rest of memory round 1
   const int S_b = w.Sb[b];
   const double pn = lane < NSLICE_MAX ? w.pnorm[b * NSLICE_MAX + lane] : 0.0;
   const double pd = (BF16 && lane < NSLICE_MAX) ? w.pdelta[b * NSLICE_MAX + lane] : 0.0;
@@ -817,7 +817,7 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
   for (int p = 0; p < RPL; ++p)
     if (lane + 64 * p >= k) uo[p] = xo[p] = 0.f;
 
-  // ---- round 2: the packed factor straight into LDS (asynchronous
+  // ---- memory round 2: the packed factor straight into LDS (asynchronous
   // global-to-LDS loads: no registers, no wait until it is read) ...
   if (w.refactor) {
     // ablation A3: the Gram block G[S, S] (packed lower triangle) instead of the
