@@ -193,12 +193,13 @@ Result = namedtuple("Result", "X support coef status rnorm")
 
 
 def workspace_bytes(M: int, N: int, B: int, S: int, precision: str = "fp32", with_dict: bool = False,
-                    tile_config: int = 0) -> int:
+                    tile_config: int = 0, gram_domain=False) -> int:
     lib = load()
     o = OmpOptsStruct()
     lib.omp_opts_default(ctypes.byref(o))
     o.precision = PREC[precision]
     o.tile_config = int(tile_config)
+    o.gram_domain = 2 if gram_domain == "auto" else (1 if gram_domain else 0)
     d = OmpDictStruct()
     if with_dict:
         o.dict = ctypes.pointer(d)

@@ -202,28 +202,32 @@ def test_batch_composition_independence(prec):
         assert np.array_equal(full[key][130:137], part[key]), key
 
 
-@pytest.mark.parametrize("prec", PRECS)
-def test_graph_replays_match_direct_launches(prec):
+@pytest.mark.parametrize("form", FORMS)
+def test_graph_replays_match_direct_launches(form):
     """The graph-replayed solve (cached per argument set) equals the directly launched one
     on every replay, with other eager GPU work and synchronisations between replays; a
-    timed call (which launches directly) between replays gives the same result."""
+    timed call (which launches directly) between replays gives the same result. The
+    Gram-domain form runs on a tall dictionary whose projection is split along K."""
+    prec, gd = _form(form)
     torch = _torch()
     from paper_2407_06434_amd import omp, workloads
-    w = workloads.batched_256x1024(B=300)
+    w = workloads.custom(2048, 300, 200, 24, seed=9, k_true=24) if gd else workloads.batched_256x1024(B=300)
     dev = torch.device("cuda:0")
     A = torch.from_numpy(w.A).to(dev)
     Y = torch.from_numpy(w.Y).to(dev)
     d = omp.Dictionary(A, prec)
-    print(f"case graph replays {prec}", flush=True)
-    ref = omp.solve(A, Y, w.S, precision=prec, dictionary=d, graph=False)
+    print(f"case graph replays {form}", flush=True)
+    ref = omp.solve(A, Y, w.S, precision=prec, dictionary=d, graph=False, gram_domain=gd)
     torch.cuda.synchronize()
     ref = {k: v.cpu().numpy() for k, v in ref._asdict().items() if v is not None}
-    ws = torch.empty(omp.workspace_bytes(w.M, w.N, w.B, w.S, prec, with_dict=True), dtype=torch.uint8, device=dev)
+    ws = torch.empty(omp.workspace_bytes(w.M, w.N, w.B, w.S, prec, with_dict=True, gram_domain=gd),
+                     dtype=torch.uint8, device=dev)
     out = None
     other = workloads.custom(64, 256, 50, 8, seed=4)
     for rep in range(5):
         timing = {} if rep == 2 else None
-        out = omp.solve(A, Y, w.S, precision=prec, dictionary=d, workspace=ws, out=out, graph=True, timing=timing)
+        out = omp.solve(A, Y, w.S, precision=prec, dictionary=d, workspace=ws, out=out, graph=True, timing=timing,
+                        gram_domain=gd)
         torch.cuda.synchronize()
         got = {k: v.cpu().numpy() for k, v in out._asdict().items() if v is not None}
         for k in ref:
@@ -236,8 +240,9 @@ def test_graph_replays_match_direct_launches(prec):
         torch.cuda.synchronize()
         if timing is not None:
             print("graph timing", timing)
-            assert timing["corr"][1] == w.S and timing["update"][1] == w.S and timing["residual"][1] == w.S
-            assert timing["init"][1] == 1 and timing["output"][1] == 1
+            assert timing["corr"][1] == w.S and timing["update"][1] == w.S
+            assert timing["residual"][1] == (0 if gd else w.S)  # the Gram-domain form keeps no residuals
+            assert timing["init"][1] == (2 if gd else 1) and timing["output"][1] == 1
             assert all(v[0] > 0 for k, v in timing.items() if v[1] > 0)
 
 
