@@ -22,8 +22,9 @@ FP32, the paper's ablations on these kernels (batching, Gram precomputation,
 progressive Cholesky), the Gram-domain form on the tall face-recognition shape,
 uneven batches, the learned proposal and the oracle on the host (CPU baseline);
 --no-* flags skip them. Two other modes print their own JSON line instead:
---sweep (the paper's parameter sweep as a speed map), --apps (the shapes of its
-application table) and --only-gram-domain.
+--sweep (the paper's parameter sweep as a speed map), --sweep-tall (every form on
+square and tall dictionaries), --apps (the shapes of its application table) and
+--only-gram-domain.
 
 Prints ONE JSON line (rank 0, one GPU).
 """
@@ -495,6 +496,45 @@ def run_sweep(precision, steps=3, warmup=1):
     return cells
 
 
+TALL_M = (512, 2048, 8192)
+TALL_N = (256, 1024, 2048)
+
+
+def run_sweep_tall(B=2000, S=32, steps=3, warmup=1):
+    """Where the Gram-domain form pays: every form on square and tall dictionaries
+    (M >= N from the grid TALL_M x TALL_N), B signals, S = 32, unit-norm N(0,1/M) atoms,
+    S-sparse signals at 30 dB. Signals/s over graph-replayed calls on prepared
+    dictionaries."""
+    import torch
+    from paper_2407_06434_amd import omp, workloads
+    dev = torch.device("cuda:0")
+    rows = []
+    for M in TALL_M:
+        for N in TALL_N:
+            if N > M:
+                continue
+            w = workloads.custom(M, N, B, S, seed=M + N, k_true=S, column_norm="unit")
+            A = torch.from_numpy(w.A).to(dev)
+            Y = torch.from_numpy(w.Y).to(dev)
+            row = {"M": M, "N": N, "B": B, "S": S}
+            for fname, prec, gd in (("bf16", "bf16", False), ("fp32", "fp32", False),
+                                    ("gram_domain_fp32", "fp32", True)):
+                d = omp.Dictionary(A, prec)
+                r = None
+                for _ in range(warmup):
+                    r = omp.solve(A, Y, S, precision=prec, dictionary=d, out=r, gram_domain=gd)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(steps):
+                    r = omp.solve(A, Y, S, precision=prec, dictionary=d, out=r, gram_domain=gd)
+                torch.cuda.synchronize()
+                row[fname] = round(B * steps / (time.perf_counter() - t0), 1)
+                del d
+            rows.append(row)
+            log(f"tall sweep: {row}")
+    return rows
+
+
 def cpu_baseline(w, target_s):
     """The oracle, as it stands, on the first n signals of the same workload."""
     import oracle
@@ -531,6 +571,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal measurement")
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the benchmark step, run the paper's parameter sweep and print its speed map")
+    ap.add_argument("--sweep-tall", action="store_true",
+                    help="instead of the benchmark step, time every form on square and tall dictionaries")
     ap.add_argument("--apps", action="store_true",
                     help="instead of the benchmark step, time every form on the paper's application shapes")
     ap.add_argument("--only-gram-domain", action="store_true",
@@ -549,6 +591,10 @@ def main():
               f"(the batch would shard by signals with no in-loop communication).", file=sys.stderr)
         sys.exit(2)
 
+    if args.sweep_tall:
+        print(json.dumps({"metric": "tall_sweep", "unit": "signals/s", "data": "synthetic", "steps": 3,
+                          "rows": run_sweep_tall()}), flush=True)
+        return
     if args.apps:
         print(json.dumps({"metric": "application_shapes", "unit": "signals/s", "data": "synthetic",
                           "steps": 3, "rows": run_apps()}), flush=True)
