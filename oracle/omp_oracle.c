@@ -247,7 +247,9 @@ done:
  * A batch of B independent signals, split over nthreads host threads (one
  * signal per task; the arithmetic per signal is exactly oracle_omp_signal).
  * Per-signal arrays are row-major with row length S (S+1 for rnorm_hist).
- *   S_arr, eps_arr    optional per-signal sparsity / tolerance (NULL: use S, eps)
+ *   S_arr, eps_arr    optional per-signal sparsity / tolerance (NULL: use S, eps);
+ *                     S_b is clamped to 0..S (a cap outside that range means no pick
+ *                     or the batch's cap)
  *   prefix, nprefix   optional per-signal forced prefixes, prefix row length S
  * Returns the first non-zero per-signal return code, else ORC_OK.
  */
@@ -262,6 +264,7 @@ int oracle_omp_batch(int M, int N, const float *A, int64_t lda, int B, const flo
   for (int b = 0; b < B; ++b) {
     int Sb = S_arr ? S_arr[b] : S;
     if (Sb > S) Sb = S;
+    if (Sb < 0) Sb = 0;
     double eb = eps_arr ? (double)eps_arr[b] : eps;
     size_t o = (size_t)b * (size_t)S;
     /* per-signal outputs live in rows of length S; the signal uses the first Sb */

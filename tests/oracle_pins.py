@@ -251,6 +251,52 @@ def pin_stop_rules(orc, lib):
     assert o["k"][0] == 1 and o["status"][0] == orc.SIG_DEPENDENT
 
 
+def pin_per_signal_caps_and_tolerances(orc, lib):
+    """Per-signal S_b and eps_b of a batch (Algorithm 1 runs independently per signal):
+    a cap S_b keeps exactly the first S_b picks of the uncapped run (greedy picks do not
+    depend on the cap); eps_b between two residual norms, computed here by numpy least
+    squares on the uncapped run's prefixes, stops exactly between them; eps_b >= ||y_b||
+    and S_b = 0 give k_b = 0; every signal equals a one-signal call with scalar S_b, eps_b."""
+    g = np.random.default_rng(15)
+    M, N, S, B = 24, 80, 8, 12
+    A = _dict(M, N, 16, norms=(0.5, 2.0))
+    Y = g.standard_normal((B, M)).astype(np.float32)
+    full = orc.omp(A, Y, S, lib=lib)
+    Sb = np.array([0, 1, 3, 8, 5, 8, 2, 8, 7, 4, 8, 6], np.int32)
+    stop_at = np.array([-1, -1, -1, 2, -1, 5, -1, 0, 3, -1, 6, -1])  # eps_b between ||r_j|| and ||r_j+1||
+    eps = np.zeros(B, np.float32)
+    want_k = np.minimum(Sb, S).astype(int)
+    for b in range(B):
+        sup = full["support"][b]
+        yb = Y[b].astype(np.float64)
+        rn = [np.linalg.norm(yb)] + [np.linalg.norm(_lstsq(A, Y[b], sup[:j])[1]) for j in range(1, S + 1)]
+        j = int(stop_at[b])
+        if j >= 0:
+            eps[b] = np.float32(0.5 * (rn[j] + rn[j + 1]))
+            assert rn[j + 1] < eps[b] < rn[j]
+            want_k[b] = min(want_k[b], j + 1)
+    eps[4] = np.float32(np.linalg.norm(Y[4].astype(np.float64)) * 1.0001)  # eps >= ||y||
+    want_k[4] = 0
+    for kw in (dict(S_per_signal=Sb, eps_per_signal=eps), dict(S_per_signal=Sb), dict(eps_per_signal=eps)):
+        o = orc.omp(A, Y, S, **kw, lib=lib)
+        for b in range(B):
+            kb = min(int(Sb[b]), S) if "S_per_signal" in kw else S
+            if "eps_per_signal" in kw:
+                kb = min(kb, int(want_k[b]) if stop_at[b] >= 0 or b == 4 else kb)
+            assert o["k"][b] == kb, (kw.keys(), b, o["k"][b], kb)
+            assert o["support"][b, :kb].tolist() == full["support"][b, :kb].tolist(), (b,)
+            assert np.all(o["support"][b, kb:] == -1) and np.all(o["coef"][b, kb:] == 0.0)
+            if kb > 0:
+                x, _ = _lstsq(A, Y[b], full["support"][b, :kb])
+                np.testing.assert_allclose(o["coef"][b, :kb], x, rtol=1e-10, atol=1e-12)
+            eb = float(eps[b]) if "eps_per_signal" in kw else 0.0
+            stopped_on_eps = eb > 0 and o["rnorm_hist"][b, kb] <= eb
+            assert bool(o["status"][b] & orc.SIG_EPS) == stopped_on_eps, (b, o["status"][b])
+            assert bool(o["status"][b] & orc.SIG_SMAX) == (kb >= (min(int(Sb[b]), S) if "S_per_signal" in kw else S))
+            one = orc.omp(A, Y[b:b + 1], kb if kb < S else S, eb, lib=lib)
+            assert one["support"][0, :kb].tolist() == o["support"][b, :kb].tolist()
+
+
 def pin_sklearn_crosscheck(orc, lib):
     """scikit-learn's orthogonal_mp (unit-norm atoms) agrees on the plain 64x256 workload."""
     from sklearn.linear_model import orthogonal_mp
@@ -265,4 +311,4 @@ def pin_sklearn_crosscheck(orc, lib):
 
 PINS = [pin_s1_matched_filter, pin_bruteforce_tiny, pin_greedy_choice, pin_exact_recovery_erc,
         pin_orthonormal_thresholding, pin_invariants, pin_metamorphic, pin_tie_break_lowest,
-        pin_stop_rules, pin_sklearn_crosscheck]
+        pin_stop_rules, pin_per_signal_caps_and_tolerances, pin_sklearn_crosscheck]

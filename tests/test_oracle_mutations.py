@@ -34,6 +34,11 @@ MUTATIONS = {
     "reflector_not_applied_to_b": ("for (int i = j; i < M; ++i) b[i] -= t * wj[i];", "(void)t;"),
     "stop_on_ge": ("while (k < S && rn > eps_eff)", "while (k < S && rn >= eps_eff)"),
     "householder_beta_wrong": ("double beta = (vtv > 0.0) ? 2.0 / vtv : 0.0;", "double beta = (vtv > 0.0) ? 1.0 / vtv : 0.0;"),
+    "per_signal_eps_ignored": ("double eb = eps_arr ? (double)eps_arr[b] : eps;", "double eb = eps;"),
+    "per_signal_S_ignored": ("int Sb = S_arr ? S_arr[b] : S;", "int Sb = S;"),
+    "per_signal_eps_wrong_row": ("double eb = eps_arr ? (double)eps_arr[b] : eps;",
+                                 "double eb = eps_arr ? (double)eps_arr[0] : eps;"),
+    "per_signal_S_wrong_row": ("int Sb = S_arr ? S_arr[b] : S;", "int Sb = S_arr ? S_arr[b > 0 ? b - 1 : 0] : S;"),
 }
 
 
