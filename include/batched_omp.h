@@ -69,6 +69,8 @@ extern "C" {
 #define OMP_SIG_DEPENDENT 4  /* the picked atom was (numerically) in the span of the support:
                                 Cholesky pivot d^2 <= 1e-6 ||a_n*||^2; it was not added */
 #define OMP_SIG_NONFINITE 8  /* y_b held a NaN or Inf; nothing was selected, x_b = 0 */
+#define OMP_SIG_NEARTIE 16   /* with opts.flag_near_ties: at some step the second best atom
+                                scored within 1e-5 (relative) of the picked one */
 #define OMP_SIG_EXHAUSTED 32 /* no selectable atom was left (all selected or zero norm) */
 #define OMP_SIG_WIDENED 64   /* BF16 form: the FP32 re-score needed the widened candidate set */
 #define OMP_SIG_LEARNED 128  /* omp_learned_solve: the network's proposal was accepted (no OMP run) */
@@ -155,6 +157,18 @@ typedef struct omp_opts {
                                    2 = automatic: the Gram-domain form for FP32 solves with M >= N,
                                    the residual-vector form otherwise (the scikit-learn choice).
                                    0 (default): residual vectors. Other values: OMP_EINVAL. */
+  int32_t flag_near_ties;       /* 1 = record near-ties: status bit OMP_SIG_NEARTIE is set for a
+                                   signal when, at any of its steps, the runner-up atom scored
+                                   s_2 >= (1 - 1e-5) s_1 (s_1 the picked atom's score; scores as
+                                   the form computes them: the FP32 product and the Gram-domain
+                                   correlations in FP32, the BF16 form's exact re-score in FP64
+                                   sums, which then also re-scores every atom that could come
+                                   within 1e-5 of the pick). Two near-tied atoms are ordered by
+                                   rounding, so at such a step another implementation may
+                                   legitimately pick the other one. Costs a second key per tile
+                                   (workspace: omp_workspace_size with the same opts) and wider
+                                   re-scoring; for debugging and parity runs. 0 (default): off.
+                                   Other values: OMP_EINVAL. */
 } omp_opts_t;
 
 /* Phases reported through omp_opts_t.phase_ms. */
@@ -201,7 +215,7 @@ int omp_solve(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y,
 
 /* ---- uneven batches: several problems, slot scheduling ------------------
  * Batches whose signals stop at very different iterations (per-signal S_b and
- * eps_b, Section 3.3 of the paper: finished signals either stay in the batch or
+ * eps_b, Section 3.5 of the paper: finished signals either stay in the batch or
  * are compacted out) and batches over several dictionaries. Each problem owns
  * `slots` columns of the correlation product. A signal occupies a slot from
  * its admission until it stops; the solve kernel then writes its outputs and

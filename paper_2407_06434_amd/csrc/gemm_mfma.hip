@@ -99,7 +99,8 @@ __device__ inline void xcd_tile(int b, int nta, int ntb, int *tn, int *tb) {
 // whose unsigned maximum is the largest score with ties going to the lowest
 // index (bits(s) is monotone for s >= 0); key 0 means "no candidate".
 //
-// TOP2 = false (FP32 form): one key per (signal, tile), the tile's winner.
+// TOP2 = false (FP32 form): one key per (signal, tile), the tile's winner; with
+//   SECOND (near-tie flagging) two keys, the tile's best and second best.
 // TOP2 = true  (BF16 form): each lane keeps, for each "subgroup" of the atoms
 //   it holds for its signal (16 atoms per fragment, SUBF fragments), the three
 //   best scores and writes them as three keys. A key is 32 bits: bits(s) with
@@ -111,7 +112,7 @@ __device__ inline void xcd_tile(int b, int nta, int ntb, int *tn, int *tb) {
 //   atoms marked invalid (bit 31 set; s >= 0 leaves that bit free), so the third
 //   key still bounds every atom of the subgroup that is not listed.
 // ---------------------------------------------------------------------------
-template <class Op, class T, bool TOP2>
+template <class Op, class T, bool TOP2, bool SECOND = false>
 __global__ __launch_bounds__(T::NTHR) void k_corr_select(
     const typename Op::elem *__restrict__ Aop, const typename Op::elem *__restrict__ Rop, int64_t Mp,
     int64_t Np, const float *__restrict__ inv_nu, const uint32_t *__restrict__ mask,
@@ -228,12 +229,12 @@ __global__ __launch_bounds__(T::NTHR) void k_corr_select(
     return;
   }
 
-  uint64_t *red = reinterpret_cast<uint64_t *>(lds);  // [WN][TB], LDS is free after the main loop
+  uint64_t *red = reinterpret_cast<uint64_t *>(lds);  // [WN][TB] (x2 with SECOND), LDS is free after the main loop
 #pragma unroll
   for (int j = 0; j < T::FB; ++j) {
     const int jt = wb * T::FB * 32 + j * 32 + (lane & 31);  // signal within the tile
     const int64_t b = b0 + jt;
-    uint64_t best = 0;
+    uint64_t best = 0, sec = 0;  // sec: second best (SECOND only)
 #pragma unroll
     for (int i = 0; i < T::FN; ++i) {
       const int64_t nf = nw0 + i * 32;  // first atom of the fragment
@@ -250,20 +251,34 @@ __global__ __launch_bounds__(T::NTHR) void k_corr_select(
           const uint64_t key = cand ? ((uint64_t)__float_as_uint(s) << 32) |
                                           (uint64_t)(0xFFFFFFFFu - (uint32_t)(nf + row))
                                     : 0ull;
+          if (SECOND) sec = max(sec, min(best, key));
           best = key > best ? key : best;
         }
       }
     }
     const uint64_t other = __shfl_xor(best, 32);
+    if (SECOND) sec = max(max(sec, __shfl_xor(sec, 32)), min(best, other));
     best = other > best ? other : best;
-    if (lane < 32) red[wn * T::TB + jt] = best;
+    if (lane < 32) {
+      red[wn * T::TB + jt] = best;
+      if (SECOND) red[(T::WN + wn) * T::TB + jt] = sec;
+    }
   }
   __syncthreads();
   for (int t = threadIdx.x; t < T::TB; t += T::NTHR) {
-    uint64_t best = 0;
+    uint64_t best = 0, sec = 0;
 #pragma unroll
-    for (int w = 0; w < T::WN; ++w) best = red[w * T::TB + t] > best ? red[w * T::TB + t] : best;
-    part[(b0 + t) * ntile + tn] = best;
+    for (int w = 0; w < T::WN; ++w) {
+      const uint64_t v = red[w * T::TB + t];
+      if (SECOND) sec = max(max(sec, red[(T::WN + w) * T::TB + t]), min(best, v));
+      best = v > best ? v : best;
+    }
+    if (SECOND) {
+      part[(b0 + t) * ntile * 2 + 2 * tn] = best;
+      part[(b0 + t) * ntile * 2 + 2 * tn + 1] = sec;
+    } else {
+      part[(b0 + t) * ntile + tn] = best;
+    }
   }
 }
 
@@ -287,10 +302,10 @@ hipError_t set_lds(K kernel, size_t bytes) {
   return e;
 }
 
-template <class Op, class T, bool TOP2>
+template <class Op, class T, bool TOP2, bool SECOND = false>
 hipError_t launch_corr_t(const typename Op::elem *Aop, const typename Op::elem *Rop, const DictView &d,
                          const WorkView &w, hipStream_t st) {
-  auto kern = k_corr_select<Op, T, TOP2>;
+  auto kern = k_corr_select<Op, T, TOP2, SECOND>;
   hipError_t e = set_lds(kern, T::LDS_BYTES);
   if (e != hipSuccess) return e;
   const int ntile = (int)(d.Np / T::TN);
@@ -300,13 +315,13 @@ hipError_t launch_corr_t(const typename Op::elem *Aop, const typename Op::elem *
 }
 
 template <class T>
-CorrGeom geom(int precision, int cfg) {
+CorrGeom geom(int precision, int cfg, bool ties) {
   CorrGeom g;
   constexpr int SUBF = T::FN >= 2 ? 2 : 1;
   g.cfg = cfg;
   g.tile_atoms = T::TN;
   g.tile_signals = T::TB;
-  g.keys_per_tile = precision == 1 ? T::WN * (T::FN / SUBF) * 2 * NKEEP : 1;
+  g.keys_per_tile = precision == 1 ? T::WN * (T::FN / SUBF) * 2 * NKEEP : (ties ? 2 : 1);
   g.wave_atoms = T::FN * 32;
   g.sub_frags = SUBF;
   g.subs_per_half = T::FN / SUBF;
@@ -315,13 +330,13 @@ CorrGeom geom(int precision, int cfg) {
 
 }  // namespace
 
-CorrGeom corr_geometry(int precision, int64_t Np, int64_t Bp, int cfg) {
+CorrGeom corr_geometry(int precision, int64_t Np, int64_t Bp, int cfg, bool ties) {
   if (cfg == 0) cfg = (Np / 256) * (Bp / 256) >= 192 ? 3 : 1;
   switch (cfg) {
-    case 2: return geom<Cfg2>(precision, 2);
-    case 3: return geom<Cfg3>(precision, 3);
-    case 4: return geom<Cfg4>(precision, 4);
-    default: return geom<Cfg1>(precision, 1);
+    case 2: return geom<Cfg2>(precision, 2, ties);
+    case 3: return geom<Cfg3>(precision, 3, ties);
+    case 4: return geom<Cfg4>(precision, 4, ties);
+    default: return geom<Cfg1>(precision, 1, ties);
   }
 }
 
@@ -376,22 +391,25 @@ hipError_t launch_project(const DictView &d, const WorkView &w, hipStream_t st) 
 template <class T>
 hipError_t launch_corr_cfg(const DictView &d, const WorkView &w, int precision, hipStream_t st) {
   if (precision == 1) return launch_corr_t<OpBF16, T, true>(d.A16, w.R16, d, w, st);
+  if (w.ncand == 2) return launch_corr_t<OpF32, T, false, true>(d.A32, w.R32, d, w, st);
   return launch_corr_t<OpF32, T, false>(d.A32, w.R32, d, w, st);
 }
 
 template <class T>
-hipError_t prepare_corr_cfg(int precision) {
+hipError_t prepare_corr_cfg(int precision, bool second) {
   if (precision == 1) return set_lds(k_corr_select<OpBF16, T, true>, T::LDS_BYTES);
+  if (second) return set_lds(k_corr_select<OpF32, T, false, true>, T::LDS_BYTES);
   return set_lds(k_corr_select<OpF32, T, false>, T::LDS_BYTES);
 }
 
 hipError_t prepare_corr(const DictView &d, const WorkView &w, int precision) {
   (void)d;
+  const bool second = w.ncand == 2 && precision != 1;
   switch (w.tile_cfg) {
-    case 2: return prepare_corr_cfg<Cfg2>(precision);
-    case 3: return prepare_corr_cfg<Cfg3>(precision);
-    case 4: return prepare_corr_cfg<Cfg4>(precision);
-    default: return prepare_corr_cfg<Cfg1>(precision);
+    case 2: return prepare_corr_cfg<Cfg2>(precision, second);
+    case 3: return prepare_corr_cfg<Cfg3>(precision, second);
+    case 4: return prepare_corr_cfg<Cfg4>(precision, second);
+    default: return prepare_corr_cfg<Cfg1>(precision, second);
   }
 }
 

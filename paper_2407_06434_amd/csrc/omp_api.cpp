@@ -66,12 +66,13 @@ struct WorkLayout {
   int pchunks;
 };
 
-WorkLayout work_layout(int64_t M, int64_t N, int64_t B, int S, int precision, int cfg, bool gram_dom = false) {
+WorkLayout work_layout(int64_t M, int64_t N, int64_t B, int S, int precision, int cfg, bool gram_dom = false,
+                       bool ties = false) {
   WorkLayout L;
   L.Mp = round_up(M, KPAD);
   L.Np = round_up(N, NPAD);
   L.Bp = round_up(B > 0 ? B : 1, BPAD);
-  L.g = corr_geometry(precision, L.Np, L.Bp, cfg);
+  L.g = corr_geometry(precision, L.Np, L.Bp, cfg, ties);
   L.ntile = (int)(L.Np / L.g.tile_atoms);
   // Slice the residual over the XCDs when the FP32 dictionary outgrows one L2.
   L.nslice = (L.Np * L.Mp * 4 > (int64_t)2 << 20) ? NSLICE_MAX : 1;
@@ -81,9 +82,9 @@ WorkLayout work_layout(int64_t M, int64_t N, int64_t B, int S, int precision, in
   L.Yp = c.take<float>(Bp * L.Mp);
   L.R32 = c.take<float>(Bp * L.Mp);
   L.R16 = precision == OMP_PREC_BF16 ? c.take<uint16_t>(Bp * L.Mp) : 0;
-  // (the Gram-domain select writes GSLICE keys per signal)
+  // (the Gram-domain select writes GSLICE keys per signal, twice that with near-tie flagging)
   L.part = c.take<uint64_t>(Bp * (size_t)std::max<int64_t>((int64_t)L.ntile * L.g.keys_per_tile,
-                                                            gram_dom ? GSLICE : 1));
+                                                            gram_dom ? GSLICE * (ties ? 2 : 1) : 1));
   L.mask = c.take<uint32_t>(Bp * (L.Np / 32));
   L.k = c.take<int32_t>(Bp);
   L.flags = c.take<int32_t>(Bp);
@@ -236,8 +237,8 @@ DictView dict_view(void *mem, int64_t M, int64_t N, int precision) {
   return d;
 }
 
-size_t work_bytes(int64_t M, int64_t N, int64_t B, int S, int precision, int cfg, bool gram_dom) {
-  return work_layout(M, N, B, S, precision, cfg, gram_dom).total;
+size_t work_bytes(int64_t M, int64_t N, int64_t B, int S, int precision, int cfg, bool gram_dom, bool ties) {
+  return work_layout(M, N, B, S, precision, cfg, gram_dom, ties).total;
 }
 
 bool solve_fits(int64_t M, int64_t N, int64_t B, int S, int precision, int cfg) {
@@ -245,8 +246,9 @@ bool solve_fits(int64_t M, int64_t N, int64_t B, int S, int precision, int cfg) 
   return solve_waves_for(L.vstride, L.ntile * L.g.keys_per_tile, precision == OMP_PREC_BF16) > 0;
 }
 
-WorkView work_view(void *mem, int64_t M, int64_t N, int64_t B, int S, int precision, int cfg, bool gram_dom) {
-  const WorkLayout L = work_layout(M, N, B, S, precision, cfg, gram_dom);
+WorkView work_view(void *mem, int64_t M, int64_t N, int64_t B, int S, int precision, int cfg, bool gram_dom,
+                   bool ties) {
+  const WorkLayout L = work_layout(M, N, B, S, precision, cfg, gram_dom, ties);
   WorkView w;
   w.B = B;
   w.Bp = L.Bp;
@@ -284,7 +286,11 @@ WorkView work_view(void *mem, int64_t M, int64_t N, int64_t B, int S, int precis
   w.P = gram_dom ? at<float>(mem, L.P) : nullptr;
   w.pchunks = L.pchunks;
   w.Pk = L.pchunks > 1 ? at<float>(mem, L.Pk) : nullptr;
-  if (gram_dom) w.ntile = GSLICE;  // one key per (signal, atom slice) from the Gram-domain select
+  w.flag_ties = ties ? 1 : 0;
+  if (gram_dom) {  // one key (two with near-tie flagging) per (signal, atom slice) from the Gram-domain select
+    w.ntile = GSLICE;
+    w.ncand = ties ? 2 : 1;
+  }
   return w;
 }
 
@@ -354,19 +360,28 @@ static bool gram_domain_form(int32_t mode, int prec, int64_t M, int64_t N) {
 }
 
 size_t omp_workspace_size(int64_t M, int64_t N, int64_t B, int32_t S, const omp_opts_t *opts) {
+  return solve_bytes(M, N, B, S, opts);
+}
+
+}  // extern "C"
+
+size_t bomp::solve_bytes(int64_t M, int64_t N, int64_t B, int32_t S, const omp_opts_t *opts) {
   const int prec = opts ? opts->precision : OMP_PREC_FP32;
   if (!dims_ok(M, N) || B < 0 || B > ((int64_t)1 << 26) || S < 1 || S > OMP_MAX_S) return 0;
   if (prec != OMP_PREC_FP32 && prec != OMP_PREC_BF16) return 0;
   const int cfg = opts ? opts->tile_config : 0;
   if (cfg < 0 || cfg > MAX_TILE_CFG) return 0;
-  size_t total = work_bytes(M, N, B, S, prec, cfg, opts && gram_domain_form(opts->gram_domain, prec, M, N));
+  size_t total = work_bytes(M, N, B, S, prec, cfg, opts && gram_domain_form(opts->gram_domain, prec, M, N),
+                            opts && opts->flag_near_ties == 1);
   if (!opts || !opts->dict) total += dict_bytes(M, N, prec);
   return total;
 }
 
-int omp_solve(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y, int64_t B, int64_t ldy,
-              int32_t S, float eps, float *X_out, int32_t *support_out, const omp_opts_t *opts,
-              void *stream) {
+namespace bomp {
+
+int solve_impl(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y, int64_t B, int64_t ldy,
+               int32_t S, float eps, float *X_out, int32_t *support_out, const omp_opts_t *opts, void *stream,
+               void *workspace, size_t workspace_bytes, bool direct) {
   // ---- validation (host only) ----
   if (!opts) return OMP_EINVAL;
   const int prec = opts->precision;
@@ -377,7 +392,9 @@ int omp_solve(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y,
   if (opts->refactor != 0 && opts->refactor != 1) return OMP_EINVAL;
   if (opts->gram_domain < 0 || opts->gram_domain > 2) return OMP_EINVAL;
   if (opts->gram_domain == 1 && prec != OMP_PREC_FP32) return OMP_EINVAL;
+  if (opts->flag_near_ties != 0 && opts->flag_near_ties != 1) return OMP_EINVAL;
   const bool gdom = gram_domain_form(opts->gram_domain, prec, M, N);
+  const bool ties = opts->flag_near_ties == 1;
   if (!dims_ok(M, N) || B < 0 || B > ((int64_t)1 << 26)) return OMP_EINVAL;
   if (S < 1 || S > M || S > N) return OMP_EINVAL;
   if (S > OMP_MAX_S) return OMP_ENOTSUPP;
@@ -391,10 +408,9 @@ int omp_solve(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y,
         !dd->mem)
       return OMP_EINVAL;
   }
-  const size_t wneed = work_bytes(M, N, B, S, prec, cfg, gdom);
+  const size_t wneed = work_bytes(M, N, B, S, prec, cfg, gdom, ties);
   const size_t need = wneed + (opts->dict ? 0 : dict_bytes(M, N, prec));
-  if (!opts->workspace || opts->workspace_bytes < need || !aligned(opts->workspace, ALIGN))
-    return OMP_EWORKSPACE;
+  if (!workspace || workspace_bytes < need || !aligned(workspace, ALIGN)) return OMP_EWORKSPACE;
   if (B == 0) return OMP_OK;
   int rc = check_device();
   if (rc != OMP_OK) return rc;
@@ -409,13 +425,13 @@ int omp_solve(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y,
     if (opts->dict) {
       d = dict_view(opts->dict->mem, M, N, prec);
     } else {
-      void *dmem = static_cast<char *>(opts->workspace) + wneed;
+      void *dmem = static_cast<char *>(workspace) + wneed;
       d = dict_view(dmem, M, N, prec);
       e = timer.run(OMP_PHASE_DICT, [&] { return launch_dict_prep(A, lda, d, cs); });
       if (e == hipSuccess) e = timer.run(OMP_PHASE_DICT, [&] { return launch_gram(d, cs); });
       if (e != hipSuccess) return e;
     }
-    WorkView w = work_view(opts->workspace, M, N, B, S, prec, cfg, gdom);
+    WorkView w = work_view(workspace, M, N, B, S, prec, cfg, gdom, ties);
     w.gram_fly = opts->gram_on_the_fly;
     w.refactor = opts->refactor;
     e = timer.run(OMP_PHASE_INIT, [&] {
@@ -442,15 +458,15 @@ int omp_solve(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y,
 
   hipError_t e = hipSuccess;
   bool done = false;
-  if (opts->use_graph && !timer.on()) {
+  if (!direct && opts->use_graph && !timer.on()) {
     // The whole solve replayed from a hipGraph cached under every argument. On
     // the first use the launches are captured. (A timed call launches directly:
     // events recorded by graph nodes cannot be read back with elapsed times.)
     struct Key {
       const void *A, *Y, *X, *sup, *Sp, *Ep, *st_out, *rn_out, *coef, *dmem, *ws, *pool;
       int64_t M, N, lda, B, ldy;
-      int32_t S, prec, cfg, gram_fly, refactor, gram_dom;
-      uint32_t eps_bits, pad;
+      int32_t S, prec, cfg, gram_fly, refactor, gram_dom, ties;
+      uint32_t eps_bits;
     } key;
     std::memset(&key, 0, sizeof(key));
     key.A = A;
@@ -463,7 +479,7 @@ int omp_solve(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y,
     key.rn_out = opts->rnorm_out;
     key.coef = opts->coef_out;
     key.dmem = opts->dict ? opts->dict->mem : nullptr;
-    key.ws = opts->workspace;
+    key.ws = workspace;
     key.pool = nullptr;
     key.M = M;
     key.N = N;
@@ -476,11 +492,12 @@ int omp_solve(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y,
     key.gram_fly = opts->gram_on_the_fly;
     key.refactor = opts->refactor;
     key.gram_dom = gdom ? 1 : 0;
+    key.ties = ties ? 1 : 0;
     std::memcpy(&key.eps_bits, &eps, sizeof(float));
     {
       const DictView dp = opts->dict ? dict_view(opts->dict->mem, M, N, prec)
-                                     : dict_view(static_cast<char *>(opts->workspace) + wneed, M, N, prec);
-      e = prepare_kernels(dp, work_view(opts->workspace, M, N, B, S, prec, cfg), prec, 0);
+                                     : dict_view(static_cast<char *>(workspace) + wneed, M, N, prec);
+      e = prepare_kernels(dp, work_view(workspace, M, N, B, S, prec, cfg, gdom, ties), prec, 0);
     }
     if (e == hipSuccess)
       e = graph_launch_cached(std::string(reinterpret_cast<const char *>(&key), sizeof(key)),
@@ -499,6 +516,18 @@ int omp_solve(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y,
   if (e == hipSuccess) e = timer.finish();
   if (e != hipSuccess) return device_error(e);
   return OMP_OK;
+}
+
+}  // namespace bomp
+
+extern "C" {
+
+int omp_solve(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y, int64_t B, int64_t ldy,
+              int32_t S, float eps, float *X_out, int32_t *support_out, const omp_opts_t *opts,
+              void *stream) {
+  if (!opts) return OMP_EINVAL;
+  return solve_impl(A, M, N, lda, Y, B, ldy, S, eps, X_out, support_out, opts, stream, opts->workspace,
+                    opts->workspace_bytes, false);
 }
 
 }  // extern "C"

@@ -20,6 +20,10 @@ constexpr int KPAD = 64;
 constexpr int NPAD = 256;
 constexpr int BPAD = 256;
 
+// Near-tie flagging: a step is flagged when the second best atom's score is
+// within this fraction of the best one's.
+constexpr double TIE_REL = 1e-5;
+
 // Squared dependency threshold on the Cholesky pivot: an atom whose distance to
 // the span of the support is at most 1e-3 of its norm is not appended.
 constexpr double DEP_TOL2 = 1e-6;
@@ -89,6 +93,7 @@ struct WorkView {
   float *P;       // [Bp][Np] Gram-domain form: P = Y A^T, the correlations of y (else nullptr)
   float *Pk;      // [pchunks][Bp][Np] split-K partial products of P (pchunks > 1), else nullptr
   int pchunks;    // K chunks of the P product (1: no split)
+  int flag_ties;  // 1: near-tie flagging (the select stages keep the second best atom too)
 };
 
 // Gram-domain select: the atoms are split into this many contiguous slices, one
@@ -105,10 +110,12 @@ inline int project_chunks(int64_t Bp, int64_t Np, int64_t Mp) {
   return ks;
 }
 
-// `gram_dom` adds the Gram-domain form's P buffer to the layout.
-size_t work_bytes(int64_t M, int64_t N, int64_t B, int S, int precision, int cfg, bool gram_dom = false);
+// `gram_dom` adds the Gram-domain form's P buffer to the layout; `ties` (near-tie
+// flagging) doubles the FP32 and Gram-domain select keys (best and second best).
+size_t work_bytes(int64_t M, int64_t N, int64_t B, int S, int precision, int cfg, bool gram_dom = false,
+                  bool ties = false);
 WorkView work_view(void *mem, int64_t M, int64_t N, int64_t B, int S, int precision, int cfg,
-                   bool gram_dom = false);
+                   bool gram_dom = false, bool ties = false);
 
 // ---- the solve kernel's LDS (shared by its launcher and the entry points'
 // validation) ---------------------------------------------------------------
@@ -162,6 +169,13 @@ struct SlotView {
 };
 
 // ---- host helpers shared by the entry points --------------------------------
+// omp_solve with the workspace given explicitly (omp_solve passes opts'
+// workspace, the allocation-free entry point its static scratch). `direct`
+// launches the kernels one by one (no graph capture or instantiation).
+int solve_impl(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y, int64_t B, int64_t ldy,
+               int32_t S, float eps, float *X_out, int32_t *support_out, const struct omp_opts *opts,
+               void *stream, void *workspace, size_t workspace_bytes, bool direct);
+size_t solve_bytes(int64_t M, int64_t N, int64_t B, int32_t S, const struct omp_opts *opts);
 bool aligned(const void *p, size_t a);
 bool dims_ok(int64_t M, int64_t N);          // sizes the padded buffers can hold
 int device_error(hipError_t e);              // records e for omp_last_hip_error, returns OMP_EDEVICE
@@ -235,6 +249,7 @@ struct CorrGeom {
   int subs_per_half;
 };
 // cfg 0 picks by shape: 256 x 256 tiles when that still gives about one tile per CU.
-CorrGeom corr_geometry(int precision, int64_t Np, int64_t Bp, int cfg);
+// `ties`: the FP32 epilogue writes two keys per (signal, tile), best and second best.
+CorrGeom corr_geometry(int precision, int64_t Np, int64_t Bp, int cfg, bool ties = false);
 
 }  // namespace bomp

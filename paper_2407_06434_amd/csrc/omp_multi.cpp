@@ -5,7 +5,7 @@
 // Each problem owns `slots` workspace columns. The solve kernel retires a
 // signal as soon as it stops (writing its outputs) and admits the next waiting
 // signal into the freed slot, so finished signals stop costing correlation
-// work (the compaction alternative to keeping them in the batch, Section 3.3).
+// work (the compaction alternative to keeping them in the batch, Section 3.5).
 // One iteration is correlation -> solve -> residual per problem; a chunk of
 // iterations for all problems, each problem on its own branch, is captured
 // once into a hipGraph and replayed until every signal is out. Between chunks
@@ -99,13 +99,23 @@ size_t total_bytes(const omp_problem_t *probs, int nprob, int precision) {
   return off;
 }
 
+// A cached executable graph. `done` is recorded on the launch stream after
+// every launch of `exec`, so that an evicted graph is destroyed only once its
+// last launch has finished (an asynchronous omp_solve may still have it queued).
+struct GraphEntry {
+  std::string key;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t done = nullptr;
+};
+
 // Per-device runtime state: internal streams (default priority), events, one
-// pinned host buffer for the counters and the graph cache.
+// pinned host buffer for the counters and the graph cache (most recently used
+// first).
 struct DevState {
   hipStream_t streams[OMP_MAX_PROBLEMS] = {};
   hipEvent_t fork = nullptr, join[OMP_MAX_PROBLEMS] = {}, ready[2] = {};
   int32_t *pinned = nullptr;  // [2][OMP_MAX_PROBLEMS * CTRL_WORDS]
-  std::list<std::pair<std::string, hipGraphExec_t>> cache;
+  std::list<GraphEntry> cache;
 };
 
 std::mutex g_mu;  // serializes omp_solve_multi / omp_tune across host threads
@@ -165,20 +175,54 @@ hipError_t capture_chunk(DevState *ds, const std::vector<Plan> &plans, int preci
   return e;
 }
 
-hipError_t cached_graph(DevState *ds, const std::vector<Plan> &plans, int precision, int chunk,
-                        hipGraphExec_t *exec);
+// Moves the entry under `key` to the front and returns it (nullptr: not cached).
+GraphEntry *cache_find(DevState *ds, const std::string &key) {
+  for (auto it = ds->cache.begin(); it != ds->cache.end(); ++it) {
+    if (it->key == key) {
+      ds->cache.splice(ds->cache.begin(), ds->cache, it);
+      return &ds->cache.front();
+    }
+  }
+  return nullptr;
+}
+
+// Caches a newly instantiated graph under `key`, evicting the least recently
+// used entries beyond GRAPH_CACHE: each evicted graph's last launch is waited
+// for before the graph is destroyed.
+hipError_t cache_insert(DevState *ds, std::string key, hipGraphExec_t g, GraphEntry **out) {
+  GraphEntry ent;
+  ent.key = std::move(key);
+  ent.exec = g;
+  hipError_t e = hipEventCreateWithFlags(&ent.done, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    (void)hipGraphExecDestroy(g);
+    return e;
+  }
+  ds->cache.push_front(std::move(ent));
+  while (ds->cache.size() > GRAPH_CACHE) {
+    GraphEntry &old = ds->cache.back();
+    e = hipEventSynchronize(old.done);  // an event never recorded completes at once
+    if (e != hipSuccess) return e;      // kept: it may still be in flight
+    (void)hipGraphExecDestroy(old.exec);
+    (void)hipEventDestroy(old.done);
+    ds->cache.pop_back();
+  }
+  *out = &ds->cache.front();
+  return hipSuccess;
+}
+
+// Launches a cached graph on `st` and marks its completion on that stream.
+hipError_t cache_launch(GraphEntry *ent, hipStream_t st) {
+  hipError_t e = hipGraphLaunch(ent->exec, st);
+  if (e == hipSuccess) e = hipEventRecord(ent->done, st);
+  return e;
+}
 
 // Looks `key` up in the device's graph cache; on a miss, runs `body` under
 // stream capture on internal stream 0 and caches the instantiated graph.
 hipError_t cached_graph_body(DevState *ds, const std::string &key,
-                             const std::function<hipError_t(hipStream_t)> &body, hipGraphExec_t *exec) {
-  for (auto it = ds->cache.begin(); it != ds->cache.end(); ++it) {
-    if (it->first == key) {
-      ds->cache.splice(ds->cache.begin(), ds->cache, it);
-      *exec = it->second;
-      return hipSuccess;
-    }
-  }
+                             const std::function<hipError_t(hipStream_t)> &body, GraphEntry **out) {
+  if ((*out = cache_find(ds, key)) != nullptr) return hipSuccess;
   hipStream_t s0 = ds->streams[0];
   hipError_t e = hipStreamBeginCapture(s0, hipStreamCaptureModeRelaxed);
   if (e != hipSuccess) return e;
@@ -190,39 +234,20 @@ hipError_t cached_graph_body(DevState *ds, const std::string &key,
   if (e == hipSuccess) e = hipGraphInstantiate(&g, graph, nullptr, nullptr, 0);
   if (graph) (void)hipGraphDestroy(graph);
   if (e != hipSuccess) return e;
-  ds->cache.emplace_front(key, g);
-  while (ds->cache.size() > GRAPH_CACHE) {
-    (void)hipGraphExecDestroy(ds->cache.back().second);
-    ds->cache.pop_back();
-  }
-  *exec = g;
-  return hipSuccess;
+  return cache_insert(ds, key, g, out);
 }
 
-hipError_t cached_graph(DevState *ds, const std::vector<Plan> &plans, int precision, int chunk,
-                        hipGraphExec_t *exec) {
+hipError_t cached_graph(DevState *ds, const std::vector<Plan> &plans, int precision, int chunk, GraphEntry **out) {
   std::string key("M");
   key.append(reinterpret_cast<const char *>(plans.data()), plans.size() * sizeof(Plan));
   key.append(reinterpret_cast<const char *>(&precision), sizeof(precision));
   key.append(reinterpret_cast<const char *>(&chunk), sizeof(chunk));
   // the chunk is captured by capture_chunk (its own fork/join over the problem streams)
-  for (auto it = ds->cache.begin(); it != ds->cache.end(); ++it) {
-    if (it->first == key) {
-      ds->cache.splice(ds->cache.begin(), ds->cache, it);
-      *exec = it->second;
-      return hipSuccess;
-    }
-  }
+  if ((*out = cache_find(ds, key)) != nullptr) return hipSuccess;
   hipGraphExec_t g = nullptr;
   hipError_t e = capture_chunk(ds, plans, precision, chunk, &g);
   if (e != hipSuccess) return e;
-  ds->cache.emplace_front(std::move(key), g);
-  while (ds->cache.size() > GRAPH_CACHE) {
-    (void)hipGraphExecDestroy(ds->cache.back().second);
-    ds->cache.pop_back();
-  }
-  *exec = g;
-  return hipSuccess;
+  return cache_insert(ds, std::move(key), g, out);
 }
 
 int solve_multi_locked(const omp_problem_t *probs, int nprob, const omp_multi_opts_t *opts, void *stream) {
@@ -282,8 +307,8 @@ int solve_multi_locked(const omp_problem_t *probs, int nprob, const omp_multi_op
     e = prepare_kernels(q.d, q.w, prec, q.lanes);
     if (e != hipSuccess) return device_error(e);
   }
-  hipGraphExec_t exec = nullptr;
-  e = cached_graph(ds, plans, prec, chunk, &exec);
+  GraphEntry *graph = nullptr;
+  e = cached_graph(ds, plans, prec, chunk, &graph);
   if (e != hipSuccess) return device_error(e);
 
   hipEvent_t t0 = nullptr, t1 = nullptr;
@@ -299,7 +324,7 @@ int solve_multi_locked(const omp_problem_t *probs, int nprob, const omp_multi_op
   int64_t c = 0;
   bool done = false;
   while (e == hipSuccess && !done) {
-    e = hipGraphLaunch(exec, st);
+    e = cache_launch(graph, st);
     int32_t *buf = ds->pinned + (size_t)(c & 1) * OMP_MAX_PROBLEMS * CTRL_WORDS;
     if (e == hipSuccess) e = hipMemcpyAsync(buf, ctrl, nctrl * sizeof(int32_t), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipEventRecord(ds->ready[c & 1], st);
@@ -351,10 +376,10 @@ hipError_t graph_launch_cached(const std::string &key, const std::function<hipEr
   DevState *ds = nullptr;
   hipError_t e = dev_state(&ds);
   if (e != hipSuccess) return e;
-  hipGraphExec_t exec = nullptr;
-  e = cached_graph_body(ds, "S" + key, body, &exec);
+  GraphEntry *graph = nullptr;
+  e = cached_graph_body(ds, "S" + key, body, &graph);
   if (e != hipSuccess) return e;
-  return hipGraphLaunch(exec, st);
+  return cache_launch(graph, st);
 }
 
 }  // namespace bomp

@@ -113,6 +113,14 @@ __device__ inline float pick(const float (&a)[R], int p) {
   return v;
 }
 
+template <int R>
+__device__ inline int pick_i(const int (&a)[R], int p) {
+  int v = a[0];
+#pragma unroll
+  for (int i = 1; i < R; ++i) v = (p == i) ? a[i] : v;
+  return v;
+}
+
 __device__ inline float readlane(float v, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
@@ -224,6 +232,7 @@ template <int RPL>
 struct RescoreQueue {
   int n0 = -1, n1 = -1;
   double bs = -1.0;
+  double bs2 = -1.0;  // best exact score of any other atom (near-tie flagging)
   double bar = 0.0, bnu2 = 0.0;
   int bn = 0x7fffffff;
   float bg[RPL];
@@ -247,12 +256,15 @@ struct RescoreQueue {
       if (n[i] < 0) continue;
       const double sc = fabs(ar[i]) / sqrt(nu2[i]);
       if (better(sc, n[i], bs, bn)) {
+        if (n[i] != bn) bs2 = bs;  // (an atom may be re-scored twice: it is not its own runner-up)
         bs = sc;
         bn = n[i];
         bar = ar[i];
         bnu2 = nu2[i];
 #pragma unroll
         for (int p = 0; p < RPL; ++p) bg[p] = gc[i][p];
+      } else if (n[i] != bn && sc > bs2) {
+        bs2 = sc;
       }
     }
   }
@@ -422,13 +434,16 @@ __device__ void gram_row_from_atoms(const DictView &d, int nstar, const int (&si
 template <int RPL>
 __device__ int select_bf16(const DictView &d, const WorkView &w, int64_t b, float smax, double tau,
                            const int (&si)[RPL], int k, int lane, int *widened, double *cdot, double *nu2,
-                           float (&g)[RPL], int *clist, const uint32_t (&kv)[KREG], bool kreg) {
+                           float (&g)[RPL], int *clist, const uint32_t (&kv)[KREG], bool kreg, int *neartie) {
   const int nkeys = w.ntile * w.ncand;
   const uint32_t *keys = reinterpret_cast<const uint32_t *>(w.part) + b * nkeys;
   const float4 *r4 = reinterpret_cast<const float4 *>(w.R32) + b * (d.Mp / 4);
   const double et = 1.0 / 262144.0;  // 2^-18: the epilogue's rounding of listed scores
-  const double thr = (double)smax - 2.0 * tau - et * (double)smax;
-  const double mthr = (double)smax - 2.0 * tau;
+  // Near-tie flagging widens both windows by TIE_REL s_max, so that every atom
+  // whose exact score can reach (1 - TIE_REL) s_w is re-scored too.
+  const double tw = w.flag_ties ? TIE_REL * (double)smax : 0.0;
+  const double thr = (double)smax - 2.0 * tau - et * (double)smax - tw;
+  const double mthr = (double)smax - 2.0 * tau - tw;
   // the same tests on score bits: s >= thr, and s (1 + et) >= mthr taken as
   // s >= mthr / (1 + et) lowered by 1e-12 relative (a superset of the list)
   const uint32_t thr_bits = float_bits_floor(thr);
@@ -469,7 +484,7 @@ __device__ int select_bf16(const DictView &d, const WorkView &w, int64_t b, floa
   for (int i = 0; i < npass; ++i) {
     const int slot = movf ? i * NKEEP + NKEEP - 1 : __builtin_amdgcn_readfirstlane(mlist[i]);
     const double theta = key_score(keys[slot]);
-    if (!(theta * (1.0 + et) + tau >= q.bs)) continue;
+    if (!(theta * (1.0 + et) + tau >= (w.flag_ties ? (1.0 - TIE_REL) * q.bs : q.bs))) continue;
     const int tile = slot / w.ncand;
     const int sgl = (slot % w.ncand) / NKEEP;  // ((wn * subs_per_half + ig) * 2 + h)
     const int hh = sgl & 1;
@@ -487,6 +502,7 @@ __device__ int select_bf16(const DictView &d, const WorkView &w, int64_t b, floa
   }
   *cdot = q.bar;
   *nu2 = q.bnu2;
+  *neartie = (w.flag_ties && q.bs2 >= (1.0 - TIE_REL) * q.bs) ? 1 : 0;
 #pragma unroll
   for (int p = 0; p < RPL; ++p) g[p] = q.bg[p];
   return q.bn == 0x7fffffff ? -1 : q.bn;
@@ -609,7 +625,8 @@ __device__ void init_column(const WorkView &w, int64_t b, const float *__restric
   const bool all_finite = __all(finite);
   if (lane < NSLICE_MAX) {
     w.pnorm[b * NSLICE_MAX + lane] = (lane == 0 && all_finite) ? s : 0.0;
-    w.pdelta[b * NSLICE_MAX + lane] = (lane == 0 && all_finite) ? dl : 0.0;
+    // (the Gram-domain form keeps ||y||^2 there: the rounding scale of its running ||r||^2)
+    w.pdelta[b * NSLICE_MAX + lane] = (lane == 0 && all_finite) ? (w.gram_dom ? s : dl) : 0.0;
   }
   if (lane == 0) {
     eb = fmaxf(eb, 0.f);  // also maps NaN to 0
@@ -671,7 +688,7 @@ __device__ void retire_and_admit(const WorkView &w, const SlotView &sv, int64_t 
       if (rn <= (double)w.epsb[b]) st |= OMP_SIG_EPS;
       if (k >= w.Sb[b]) st |= OMP_SIG_SMAX;
     }
-    st |= fl & OMP_SIG_WIDENED;
+    st |= fl & (OMP_SIG_WIDENED | OMP_SIG_NEARTIE);
     if (sv.status_out) sv.status_out[sg] = (k << 8) | st;
     if (sv.rnorm_out) sv.rnorm_out[sg] = (float)rn;
     nxt = atomicAdd(sv.ctrl, 1);
@@ -735,6 +752,7 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
   const int S_b = w.Sb[b];
   const double pn = lane < NSLICE_MAX ? w.pnorm[b * NSLICE_MAX + lane] : 0.0;
   const double pd = (BF16 && lane < NSLICE_MAX) ? w.pdelta[b * NSLICE_MAX + lane] : 0.0;
+  const double y2 = w.gram_dom ? w.pdelta[b * NSLICE_MAX] : 0.0;  // Gram-domain form: ||y||^2
   // Every stop found below leaves through the `stop` label with these set, so
   // that the stop's code (slot scheduler: the retire and admit) exists once.
   int stopfl = 0;
@@ -813,6 +831,21 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
     stopfl = fl | FLAG_DONE | OMP_SIG_EXHAUSTED;
     goto stop;
   }
+  if (!BF16 && w.flag_ties) {
+    // Near-tie flagging (FP32 and Gram-domain forms): the keys hold every tile's
+    // best and second best atom, so the largest key below kmax is the second
+    // best atom overall; flag the step when its score is within 1e-5 of the best.
+    const uint64_t *keys = w.part + b * nkeys;
+    uint64_t k2 = 0;
+    for (int t = lane; t < nkeys; t += 64) {
+      const uint64_t v = keys[t];
+      k2 = ((v & 0xFFFFFFFFull) && v < kmax && v > k2) ? v : k2;
+    }
+    k2 = wave_max(k2);
+    const double s1 = (double)__uint_as_float((uint32_t)(kmax >> 32));
+    const double s2 = (double)__uint_as_float((uint32_t)(k2 >> 32));
+    if (k2 != 0ull && s2 >= (1.0 - TIE_REL) * s1) fl |= OMP_SIG_NEARTIE;
+  }
 #pragma unroll
   for (int p = 0; p < RPL; ++p)
     if (lane + 64 * p >= k) uo[p] = xo[p] = 0.f;
@@ -850,12 +883,14 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
   const float4 *r4 = reinterpret_cast<const float4 *>(w.R32) + b * (d.Mp / 4);
   if (BF16) {
     const double tau = bf16_tau(rn, sqrt(wave_sum(pd)), (double)d.aerr_max[0], d.Mp);
+    int neartie = 0;
     nstar = select_bf16<RPL>(d, w, b, __uint_as_float((uint32_t)(kmax >> 32)), tau, si, k, lane, &widened, &cdot,
-                             &nu2, g, clist, kv, kreg);
+                             &nu2, g, clist, kv, kreg, &neartie);
     if (nstar < 0) {
       stopfl = fl | FLAG_DONE | OMP_SIG_EXHAUSTED;
       goto stop;
     }
+    if (neartie) fl |= OMP_SIG_NEARTIE;
   } else {
     nstar = (int)(0xFFFFFFFFu - (uint32_t)(kmax & 0xFFFFFFFFull));
     nu2 = d.nu2[nstar];
@@ -964,13 +999,6 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
   for (int p = 0; p < RPL; ++p) zu += (double)z[p] * (double)uo[p];
   zu = wave_sum(zu);
   const float uk = (float)((beta - zu) / (double)dk);
-  if (w.gram_dom && lane == 0) {
-    // Gram-domain form: ||r_k||^2 = ||r_{k-1}||^2 - u_k^2 (u_k is y's component
-    // along the new orthonormal direction), kept in FP64 where the residual
-    // kernel would have left the slice norms
-    const double ud = (beta - zu) / (double)dk;
-    w.pnorm[b * NSLICE_MAX] = fmax(rn * rn - ud * ud, 0.0);
-  }
 
   // 7. Append row k of V, u_k and n* (LDS and memory).
   const int64_t rk = (int64_t)k * (k + 1) / 2;
@@ -1060,6 +1088,35 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
     if (i < K) w.xh[b * S + i] = x[p];
   }
 
+  if (w.gram_dom) {
+    // Gram-domain form (no residual vectors): ||r_K||^2 = ||r_k||^2 - u_K^2, u_K
+    // being y's component along the new orthonormal direction, kept in FP64
+    // where the residual kernel would have left the slice norms. That running
+    // value carries the rounding of the FP32 quantities it is built from, about
+    // K u ||y||^2; once it falls to that level, or to within it of eps_b^2 (where
+    // it would decide the stop), ||y - A_S x||^2 is formed explicitly instead:
+    // exact FP64 products of the FP32 atoms and coefficients, FP64 sums.
+    const double ud = (beta - zu) / (double)dk;
+    double r2 = rn * rn - ud * ud;
+    const double floor2 = 64.0 * (double)(K + 1) * (1.0 / 16777216.0) * y2;
+    const double e2 = (double)eps_b * (double)eps_b;
+    if (!(r2 > floor2) || fabs(r2 - e2) <= floor2) {
+      const float *yb = w.Yp + b * w.Mp;
+      double acc = 0.0;
+      for (int64_t m = lane; m < d.M; m += 64) {
+        double rm = (double)yb[m];
+        for (int j = 0; j < K; ++j) {
+          const int sj = j < k ? __builtin_amdgcn_readlane(pick_i(si, j >> 6), j & 63) : nstar;
+          const float xj = readlane(pick(x, j >> 6), j & 63);
+          rm -= (double)xj * (double)d.A32[(int64_t)sj * d.Mp + m];
+        }
+        acc += rm * rm;
+      }
+      r2 = wave_sum(acc);
+    }
+    if (lane == 0) w.pnorm[b * NSLICE_MAX] = r2;
+  }
+
   // 9. New state; the residual kernel picks the signal up through FLAG_NEWX.
   if (lane == 0) {
     fl |= FLAG_NEWX;
@@ -1106,7 +1163,8 @@ __global__ __launch_bounds__(64) void k_gram_select(DictView d, WorkView w) {
   // their results dropped.
   constexpr int NA = 4, JR = 8;
   const int64_t end = (x + 1) * len;
-  uint64_t kbest = 0;
+  const bool ties = w.ncand == 2;  // near-tie flagging: the slice's second best key too
+  uint64_t kbest = 0, ksec = 0;
   for (int64_t n0 = x * len + lane; n0 < end; n0 += 64 * NA) {
     int64_t nn[NA];
     float c[NA];
@@ -1143,9 +1201,20 @@ __global__ __launch_bounds__(64) void k_gram_select(DictView d, WorkView w) {
       const bool taken = (mk[n >> 5] >> (n & 31)) & 1u;
       if (iv > 0.f && !taken) {
         const uint64_t key = ((uint64_t)__float_as_uint(fabsf(c[a]) * iv) << 32) | (0xFFFFFFFFull - (uint64_t)n);
+        ksec = max(ksec, min(kbest, key));
         kbest = key > kbest ? key : kbest;
       }
     }
+  }
+  if (ties) {
+    // the slice's second best: the best key below the slice's best (keys are distinct)
+    const uint64_t top = wave_max(kbest);
+    ksec = wave_max(kbest == top ? ksec : kbest);
+    if (lane == 0) {
+      w.part[(b * GSLICE + x) * 2] = top;
+      w.part[(b * GSLICE + x) * 2 + 1] = ksec;
+    }
+    return;
   }
   kbest = wave_max(kbest);
   if (lane == 0) w.part[b * GSLICE + x] = kbest;  // ntile = GSLICE keys per signal in this form
@@ -1290,7 +1359,7 @@ __global__ __launch_bounds__(256) void k_finalize(WorkView w, int64_t N, float *
       if (rn <= (double)w.epsb[b]) st |= OMP_SIG_EPS;
       if (k >= w.Sb[b]) st |= OMP_SIG_SMAX;
     }
-    st |= fl & OMP_SIG_WIDENED;
+    st |= fl & (OMP_SIG_WIDENED | OMP_SIG_NEARTIE);
     if (status_out) status_out[b] = (k << 8) | st;
     if (rnorm_out) rnorm_out[b] = (float)rn;
   }
@@ -1413,7 +1482,8 @@ hipError_t launch_residual_lp(const DictView &d, const WorkView &w, int precisio
 }
 
 hipError_t launch_gram_select(const DictView &d, const WorkView &w, hipStream_t st) {
-  if (!w.gram_dom || !w.P || w.ntile != GSLICE || w.ncand != 1 || w.R16 || w.Np != d.Np || w.S > OMP_MAX_S ||
+  if (!w.gram_dom || !w.P || w.ntile != GSLICE || (w.ncand != 1 && w.ncand != 2) || w.R16 || w.Np != d.Np ||
+      w.S > OMP_MAX_S ||
       d.Np % (32 * GSLICE))
     return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_gram_select, dim3((unsigned)(w.B * GSLICE)), dim3(64), 0, st, d, w);

@@ -24,6 +24,7 @@ PREC = {"fp32": 0, "bf16": 1}
 NPHASE = 6
 PHASES = ("dict", "init", "corr", "update", "output", "residual")
 SIG_EPS, SIG_SMAX, SIG_DEPENDENT, SIG_NONFINITE, SIG_EXHAUSTED, SIG_WIDENED = 1, 2, 4, 8, 32, 64
+SIG_NEARTIE = 16
 
 EXPORTED = ("omp_dict_size", "omp_dict_init", "omp_opts_default", "omp_workspace_size", "omp_solve",
             "omp_status_string", "omp_last_hip_error", "omp_version", "omp_multi_workspace_size",
@@ -59,7 +60,7 @@ class OmpOptsStruct(ctypes.Structure):
                 ("phase_ms", ctypes.POINTER(ctypes.c_float)),
                 ("phase_launches", ctypes.POINTER(ctypes.c_int32)), ("use_graph", ctypes.c_int32),
                 ("gram_on_the_fly", ctypes.c_int32), ("refactor", ctypes.c_int32),
-                ("gram_domain", ctypes.c_int32)]
+                ("gram_domain", ctypes.c_int32), ("flag_near_ties", ctypes.c_int32)]
 
 
 class OmpProblemStruct(ctypes.Structure):
@@ -157,6 +158,17 @@ def _stream_handle(stream: Optional[torch.cuda.Stream], device) -> ctypes.c_void
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def _used_on(stream: Optional[torch.cuda.Stream], *tensors) -> None:
+    """Tells torch's caching allocator that `tensors` (allocated here, on torch's
+    current stream) are used by work enqueued on `stream`: their memory is then
+    not handed out again before that work is done, even if they are freed first."""
+    if stream is None:
+        return
+    for t in tensors:
+        if t is not None:
+            t.record_stream(stream)
+
+
 def _check_matrix(t: torch.Tensor, name: str, cols: int = None):
     if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32 or t.dim() != 2:
         raise TypeError(f"{name} must be a 2-D float32 CUDA tensor")
@@ -187,19 +199,21 @@ class Dictionary:
                                    _ptr(self.mem), nbytes, _stream_handle(stream, A.device))
         if rc != OMP_OK:
             raise OmpError(rc, "omp_dict_init")
+        _used_on(stream, self.mem)
 
 
 Result = namedtuple("Result", "X support coef status rnorm")
 
 
 def workspace_bytes(M: int, N: int, B: int, S: int, precision: str = "fp32", with_dict: bool = False,
-                    tile_config: int = 0, gram_domain=False) -> int:
+                    tile_config: int = 0, gram_domain=False, flag_near_ties: bool = False) -> int:
     lib = load()
     o = OmpOptsStruct()
     lib.omp_opts_default(ctypes.byref(o))
     o.precision = PREC[precision]
     o.tile_config = int(tile_config)
     o.gram_domain = 2 if gram_domain == "auto" else (1 if gram_domain else 0)
+    o.flag_near_ties = 1 if flag_near_ties else 0
     d = OmpDictStruct()
     if with_dict:
         o.dict = ctypes.pointer(d)
@@ -211,7 +225,8 @@ def solve(A: torch.Tensor, Y: torch.Tensor, S: int, eps: float = 0.0, *, precisi
           eps_per_signal: Optional[torch.Tensor] = None, dense: bool = True,
           workspace: Optional[torch.Tensor] = None, out: Optional[Result] = None, stream=None,
           timing: Optional[dict] = None, tile_config: int = 0, graph: bool = True,
-          gram_on_the_fly: bool = False, refactor: bool = False, gram_domain=False) -> Result:
+          gram_on_the_fly: bool = False, refactor: bool = False, gram_domain=False,
+          flag_near_ties: bool = False) -> Result:
     """Batched OMP (Algorithm 1) on the GPU.
 
     A: (N, M) float32 atom-major dictionary; Y: (B, M) float32 signals.
@@ -228,6 +243,8 @@ def solve(A: torch.Tensor, Y: torch.Tensor, S: int, eps: float = 0.0, *, precisi
     appending one row to it. `gram_domain` (FP32 only; for tall dictionaries, M >= N)
     takes each step's correlations from P = A^T y and the Gram matrix instead of from
     residual vectors; gram_domain="auto" picks that form for FP32 solves with M >= N.
+    `flag_near_ties` sets status bit SIG_NEARTIE on signals where, at some step, the
+    runner-up atom scored within 1e-5 (relative) of the picked one.
     """
     _check_matrix(A, "A")
     N, M = A.shape
@@ -243,6 +260,7 @@ def solve(A: torch.Tensor, Y: torch.Tensor, S: int, eps: float = 0.0, *, precisi
     o.gram_on_the_fly = 1 if gram_on_the_fly else 0
     o.refactor = 1 if refactor else 0
     o.gram_domain = 2 if gram_domain == "auto" else (1 if gram_domain else 0)
+    o.flag_near_ties = 1 if flag_near_ties else 0
     if dictionary is not None:
         if dictionary.A is not A or dictionary.precision != precision:
             raise ValueError("dictionary was prepared for another A or precision")
@@ -282,6 +300,7 @@ def solve(A: torch.Tensor, Y: torch.Tensor, S: int, eps: float = 0.0, *, precisi
                            _ptr(out.X), _ptr(out.support), ctypes.byref(o), _stream_handle(stream, dev))
     if rc != OMP_OK:
         raise OmpError(rc, "omp_solve")
+    _used_on(stream, workspace, *out)
     if timing is not None:
         for p, name in enumerate(PHASES):
             t0, n0 = timing.get(name, (0.0, 0))
@@ -438,6 +457,7 @@ class MLP:
             rc = load().omp_mlp_export(ctypes.byref(self.struct), ptrs, _stream_handle(stream, self.device))
         if rc != OMP_OK:
             raise OmpError(rc, "omp_mlp_export")
+        _used_on(stream, *out.values())
         return out
 
     def features(self, dictionary: Dictionary, Y: torch.Tensor, stream=None) -> torch.Tensor:
@@ -452,6 +472,7 @@ class MLP:
                                          _stream_handle(stream, self.device))
         if rc != OMP_OK:
             raise OmpError(rc, "omp_mlp_features")
+        _used_on(stream, ws, F)
         return F
 
     def forward(self, F: torch.Tensor, stream=None) -> torch.Tensor:
@@ -463,6 +484,7 @@ class MLP:
                                         ws.numel(), _stream_handle(stream, self.device))
         if rc != OMP_OK:
             raise OmpError(rc, "omp_mlp_forward")
+        _used_on(stream, ws, Z)
         return Z
 
     def grad(self, F: torch.Tensor, support: torch.Tensor, rows: Optional[torch.Tensor] = None, stream=None):
@@ -482,6 +504,7 @@ class MLP:
                                      _stream_handle(stream, self.device))
         if rc != OMP_OK:
             raise OmpError(rc, "omp_mlp_grad")
+        _used_on(stream, ws, loss, *g.values())
         return loss, g
 
     def train_step(self, F: torch.Tensor, support: torch.Tensor, lr: float, loss: Optional[torch.Tensor] = None,
@@ -497,6 +520,7 @@ class MLP:
                                            _stream_handle(stream, self.device))
         if rc != OMP_OK:
             raise OmpError(rc, "omp_mlp_train_step")
+        _used_on(stream, ws)
         return loss
 
 
@@ -532,4 +556,5 @@ def learned_solve(dictionary: Dictionary, mlp: MLP, Y: torch.Tensor, S: int, eps
                                    _stream_handle(stream, dev))
     if rc != OMP_OK:
         raise OmpError(rc, "omp_learned_solve")
+    _used_on(stream, workspace, *out)
     return out, int(acc.value)

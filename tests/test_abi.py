@@ -48,7 +48,7 @@ def test_version_and_strings(lib):
 def test_struct_layout_matches_header():
     from paper_2407_06434_amd import omp
     assert ctypes.sizeof(omp.OmpDictStruct) == 64
-    assert ctypes.sizeof(omp.OmpOptsStruct) == 8 + 8 * 7 + 8 + 16 + 16
+    assert ctypes.sizeof(omp.OmpOptsStruct) == 8 + 8 * 7 + 8 + 16 + 16 + 8
 
 
 def _opts(ws=1 << 30, prec=0):

@@ -4,7 +4,8 @@ Results are built by the oracle (with forced picks where a mistake is planted), 
 they are self-consistent apart from the planted pick: the oracle's own result
 passes; a wrong pick on a large residual fails with or without the FP32
 residual-rounding tie bound; a different last pick taken on a residual near the
-rounding level of y passes only with that bound.
+rounding level of y fails without that bound and, with it, is counted as
+unresolved in FP32 (neither a failure nor a pass).
 """
 import numpy as np
 
@@ -38,7 +39,7 @@ def test_oracle_result_passes(orc):
     r = orc.omp(w.A, w.Y, w.S)
     for rr in (False, True):
         rep = parity.check(w, _as_gpu(r), orc, residual_rounding=rr)
-        assert rep["n_fail"] == 0
+        assert rep["n_fail"] == 0 and rep["unresolved_fp32"] == 0 and rep["passed"] == w.B
 
 
 def test_wrong_early_pick_fails_with_either_bound(orc):
@@ -49,6 +50,7 @@ def test_wrong_early_pick_fails_with_either_bound(orc):
     for rr in (False, True):
         rep = parity.check(w, _as_gpu(bad), orc, residual_rounding=rr, raise_on_fail=False)
         assert any("pick 2 " in f[1] for f in rep["fails"]), rep
+        assert rep["passed"] == 0 and rep["unresolved_fp32"] == 0
 
 
 def test_last_pick_on_a_rounding_level_residual(orc):
@@ -71,3 +73,7 @@ def test_last_pick_on_a_rounding_level_residual(orc):
     assert any("pick 31 " in f[1] for f in strict["fails"]), strict
     loose = parity.check(sub, _as_gpu(bad), orc, residual_rounding=True, raise_on_fail=False)
     assert loose["n_fail"] == 0, loose
+    assert loose["unresolved_fp32"] == 1 and loose["unresolved_fp32_picks"] == 1 and loose["passed"] == 0, loose
+    # the FP64 form's checks take no rounding allowance
+    strict64 = parity.check(sub, _as_gpu(bad), orc, residual_rounding=True, fp64=True, raise_on_fail=False)
+    assert any("pick 31 " in f[1] for f in strict64["fails"]), strict64

@@ -285,6 +285,66 @@ def test_clustered_atoms(orc, prec):
         assert widened > 0
 
 
+@pytest.mark.parametrize("form", FORMS)
+def test_near_tie_flags_match_the_oracle_gaps(orc, form):
+    """flag_near_ties: OMP_SIG_NEARTIE marks the signals where, at some step, the
+    runner-up atom scored within 1e-5 of the pick. Half of the signals are built from
+    atoms that have a twin (an exact copy, or a copy perturbed by 1e-6 of its norm),
+    half from atoms without one. Judged against the oracle's top-two scores on the
+    GPU's own pick sequence, each step's gap widened or narrowed by twice the bound on
+    the form's score error (the FP32 product: gamma_M ||r||; the FP32 residual:
+    (j + 1) u ||y||): a signal with a step surely inside the 1e-5 band (or an exact
+    tie: equal atoms score bit-equal in every form) must be flagged, a flagged signal
+    must have a step possibly inside it. The flag changes no result."""
+    torch = _torch()
+    from paper_2407_06434_amd import omp, workloads
+    g = np.random.default_rng(41)
+    M, nbase, nuniq, B, S = 128, 128, 256, 128, 8
+    D = g.normal(size=(nbase + nuniq, M))
+    D /= np.linalg.norm(D, axis=1, keepdims=True)
+    twins = D[:nbase].copy()
+    twins[nbase // 2:] += 1e-6 * g.normal(size=(nbase - nbase // 2, M)) / np.sqrt(M)
+    A = np.concatenate([D[:nbase], twins, D[nbase:]]).astype(np.float32)
+    perm = g.permutation(A.shape[0])
+    A = A[perm]
+    inv = np.argsort(perm)
+    Y = np.zeros((B, M))
+    for b in range(B):
+        src = g.choice(nbase, 4, replace=False) if b < B // 2 else 2 * nbase + g.choice(nuniq, 4, replace=False)
+        Y[b] = (1.0 + g.random(4)) * np.sign(g.normal(size=4)) @ A[inv[src]].astype(np.float64)
+        Y[b] += 1e-2 * g.normal(size=M) / np.sqrt(M)
+    w = workloads.Workload("twins_128x512", A, Y.astype(np.float32), S, 0.0)
+    prec, gdom = _form(form)
+    dev = torch.device("cuda:0")
+    At = torch.from_numpy(w.A).to(dev)
+    Yt = torch.from_numpy(w.Y).to(dev)
+    print(f"case near-tie flags {form}", flush=True)
+    plain = omp.solve(At, Yt, S, precision=prec, gram_domain=gdom)
+    flagged = omp.solve(At, Yt, S, precision=prec, gram_domain=gdom, flag_near_ties=True)
+    torch.cuda.synchronize()
+    for k in ("support", "coef", "rnorm", "X"):
+        assert torch.equal(getattr(plain, k), getattr(flagged, k)), k
+    st = flagged.status.cpu().numpy()
+    assert np.array_equal(st & ~omp.SIG_NEARTIE, plain.status.cpu().numpy())
+    gpu_flag = (st & omp.SIG_NEARTIE) != 0
+    sup = flagged.support.cpu().numpy()
+    k = st >> 8
+    rep = orc.omp(w.A, w.Y, S, prefix=sup, nprefix=k.astype(np.int32))
+    u = 2.0 ** -24
+    must, may = np.zeros(B, bool), np.zeros(B, bool)
+    for b in range(B):
+        for j in range(k[b]):
+            s1, s2 = rep["s_best"][b, j], rep["s_second"][b, j]
+            rn, yn = rep["rnorm_hist"][b, j], rep["rnorm_hist"][b, 0]
+            err = (j + 1) * u * yn + (0.0 if prec == "bf16" else M * u / (1 - M * u) * rn)
+            must[b] |= s1 - s2 <= 1e-5 * s1 - 2 * err or s1 == s2
+            may[b] |= s1 - s2 <= 1e-5 * s1 + 2 * err
+    print("flagged", int(gpu_flag.sum()), "surely tied", int(must.sum()), "possibly tied", int(may.sum()))
+    assert must[: B // 2].sum() >= B // 4  # the twins produce near-ties
+    assert np.all(gpu_flag[must]), np.nonzero(must & ~gpu_flag)
+    assert np.all(may[gpu_flag]), np.nonzero(gpu_flag & ~may)
+
+
 @pytest.mark.parametrize("prec", PRECS)
 def test_large_support_four_rows_per_lane(orc, prec):
     """S = 160: the solve keeps four factor rows per lane (S > 128)."""
@@ -451,6 +511,32 @@ def test_gram_domain_form(orc, M, N, B, S, eps_frac):
     same = np.mean([set(x.tolist()) == set(y.tolist()) for x, y in zip(a.support.cpu().numpy(), out["support"])])
     print("same supports as the residual-vector form:", same)
     assert same >= 0.95
+
+
+@pytest.mark.parametrize("snr_db", [60.0, None])
+def test_gram_domain_high_snr_and_noiseless_past_the_true_support(orc, snr_db):
+    """Gram-domain form on a tall dictionary with S above the true sparsity and no
+    early stop (eps = 0), at 60 dB and noiseless: the running ||r||^2 = ||y||^2 -
+    sum u_i^2 falls to its own rounding level, where the solve forms ||y - A_S x||
+    explicitly. Every signal must run to S (no stop on a rounded-away residual),
+    the picks up to the true sparsity must be exact, and the reported ||r|| must
+    match the oracle's. Picks after the true sparsity are taken on a residual of
+    1e-3 ||y|| (60 dB) or at rounding level (noiseless), where the correlations
+    c = P - G[:, S] x (each term of size ||y||) carry FP32 cancellation errors of
+    the order of the score gaps: such picks are counted as unresolved in FP32."""
+    from paper_2407_06434_amd import workloads
+    M, N, B, S, kt = 512, 128, 64, 24, 12
+    w = workloads.custom(M, N, B, S, seed=77, k_true=kt, column_norm="unit", snr_db=snr_db)
+    print(f"case Gram-domain form M={M} N={N} B={B} S={S} k_true={kt} snr={snr_db}", flush=True)
+    out = run_gpu(w, "fp32", gram_domain=True)
+    k = out["status"] >> 8
+    assert np.all(k == S), np.unique(k)
+    assert np.all(out["status"] & 0xFF == 2)  # OMP_SIG_SMAX only
+    rep = parity.check(w, out, orc, residual_rounding=True)
+    print(rep)
+    ref = orc.omp(w.A, w.Y, kt)
+    for b in range(B):
+        assert set(out["support"][b, :kt].tolist()) == set(ref["support"][b].tolist()), b
 
 
 def test_gram_domain_face_shape_sampled(orc):
