@@ -246,6 +246,25 @@ def test_graph_replays_match_direct_launches(form):
             assert all(v[0] > 0 for k, v in timing.items() if v[1] > 0)
 
 
+def test_graph_cache_eviction_with_solves_in_flight():
+    """More distinct argument sets than the graph cache holds (16), enqueued back to back
+    with no host synchronisation: each evicted graph is destroyed only after its last
+    launch, so every one of the 24 solves must equal its direct-launch result."""
+    torch = _torch()
+    from paper_2407_06434_amd import omp, workloads
+    w = workloads.custom(96, 320, 150, 12, seed=19, k_true=12)
+    dev = torch.device("cuda:0")
+    A = torch.from_numpy(w.A).to(dev)
+    Y = torch.from_numpy(w.Y).to(dev)
+    print("case graph cache eviction, 24 argument sets in flight", flush=True)
+    ref = omp.solve(A, Y, w.S, graph=False)
+    outs = [omp.solve(A, Y, w.S) for _ in range(24)]  # fresh outputs: a new argument set each time
+    torch.cuda.synchronize()
+    for i, o in enumerate(outs):
+        for k in ("support", "coef", "status", "rnorm", "X"):
+            assert torch.equal(getattr(o, k), getattr(ref, k)), (i, k)
+
+
 @pytest.mark.parametrize("prec", PRECS)
 def test_many_atom_tiles_keys_read_in_batches(orc, prec):
     """N = 8192 gives 768 BF16 keys per signal, more than the solve keeps in registers,
