@@ -26,7 +26,8 @@
  *   - All array pointers are DEVICE pointers on the caller's current HIP
  *     device, unless a comment says "host".
  *   - The caller allocates and owns every buffer (inputs, outputs, workspace,
- *     dictionary memory). The library allocates no device memory.
+ *     dictionary memory). The library allocates no device memory (the one
+ *     static array of omp_solve_noalloc aside).
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *     Calls only enqueue work; results are valid once the stream has reached
  *     the enqueued work (e.g. after hipStreamSynchronize).
@@ -212,6 +213,33 @@ size_t omp_workspace_size(int64_t M, int64_t N, int64_t B, int32_t S, const omp_
 int omp_solve(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y, int64_t B,
               int64_t ldy, int32_t S, float eps, float *X_out, int32_t *support_out,
               const omp_opts_t *opts, void *stream);
+
+/* ---- allocation-free solve ---------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ * omp_solve_noalloc is omp_solve (same arguments, same kernels, the same
+ * results bit for bit) with the workspace taken from a static device array of
+ * OMP_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on
+ * until the process ends. It calls no allocating routine, captures no graph
+ * and launches the kernels one by one.
+ *   opts->workspace, workspace_bytes and use_graph are ignored; phase_ms and
+ *   phase_launches must be NULL (else OMP_EINVAL). Inputs, outputs and the
+ *   optional prepared dictionary stay the caller's, as in omp_solve (without a
+ *   prepared dictionary the dictionary is prepared inside the array too).
+ *   A request whose workspace (omp_workspace_size with the same arguments)
+ *   exceeds OMP_NOALLOC_SCRATCH_BYTES returns OMP_ENOTSUPP and enqueues nothing.
+ *   Every call on one GPU uses that GPU's one array and leaves its contents
+ *   behind (each call initialises what it reads): calls that overlap in time on
+ *   one GPU (several streams or host threads) race, and the caller must
+ *   serialise them. */
+#define OMP_NOALLOC_SCRATCH_BYTES 67108864 /* 64 MiB per GPU */
+
+int omp_solve_noalloc(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y, int64_t B,
+                      int64_t ldy, int32_t S, float eps, float *X_out, int32_t *support_out,
+                      const omp_opts_t *opts, void *stream);
+
+/* OMP_NOALLOC_SCRATCH_BYTES, as built into the library. */
+size_t omp_noalloc_max_bytes(void);
 
 /* ---- uneven batches: several problems, slot scheduling ------------------
  * Batches whose signals stop at very different iterations (per-signal S_b and

@@ -30,7 +30,7 @@ EXPORTED = ("omp_dict_size", "omp_dict_init", "omp_opts_default", "omp_workspace
             "omp_status_string", "omp_last_hip_error", "omp_version", "omp_multi_workspace_size",
             "omp_solve_multi", "omp_tune", "omp_mlp_size", "omp_mlp_init", "omp_mlp_export",
             "omp_mlp_workspace_size", "omp_mlp_features", "omp_mlp_forward", "omp_mlp_grad", "omp_mlp_train_step",
-            "omp_learned_workspace_size", "omp_learned_solve")
+            "omp_learned_workspace_size", "omp_learned_solve", "omp_solve_noalloc", "omp_noalloc_max_bytes")
 SIG_LEARNED = 128
 OMP_MAX_PROBLEMS = 8
 
@@ -139,6 +139,10 @@ def load():
     lib.omp_learned_solve.restype = ctypes.c_int
     lib.omp_learned_solve.argtypes = [PD, PM, P, I64, I64, I32, ctypes.c_float, P, P, P, P, P,
                                       ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(OmpOptsStruct), P, SZ, P]
+    lib.omp_solve_noalloc.restype = ctypes.c_int
+    lib.omp_solve_noalloc.argtypes = lib.omp_solve.argtypes
+    lib.omp_noalloc_max_bytes.restype = SZ
+    lib.omp_noalloc_max_bytes.argtypes = []
     lib.omp_status_string.restype = ctypes.c_char_p
     lib.omp_status_string.argtypes = [ctypes.c_int]
     lib.omp_last_hip_error.restype = ctypes.c_int
@@ -305,6 +309,51 @@ def solve(A: torch.Tensor, Y: torch.Tensor, S: int, eps: float = 0.0, *, precisi
         for p, name in enumerate(PHASES):
             t0, n0 = timing.get(name, (0.0, 0))
             timing[name] = (t0 + float(ms[p]), n0 + int(nl[p]))
+    return out
+
+
+def solve_noalloc(A: torch.Tensor, Y: torch.Tensor, S: int, eps: float = 0.0, *, precision: str = "fp32",
+                  dictionary: Optional[Dictionary] = None, S_per_signal: Optional[torch.Tensor] = None,
+                  eps_per_signal: Optional[torch.Tensor] = None, dense: bool = True,
+                  out: Optional[Result] = None, stream=None, tile_config: int = 0, gram_domain=False) -> Result:
+    """omp_solve_noalloc: the solve of `solve` with the library's static device scratch as
+    its workspace (no workspace tensor; the library allocates nothing). Outputs are
+    allocated here unless `out` is given. Calls overlapping on one GPU race."""
+    _check_matrix(A, "A")
+    N, M = A.shape
+    _check_matrix(Y, "Y", M)
+    B = Y.shape[0]
+    dev = A.device
+    lib = load()
+    o = OmpOptsStruct()
+    lib.omp_opts_default(ctypes.byref(o))
+    o.precision = PREC[precision]
+    o.tile_config = int(tile_config)
+    o.gram_domain = 2 if gram_domain == "auto" else (1 if gram_domain else 0)
+    if dictionary is not None:
+        if dictionary.A is not A or dictionary.precision != precision:
+            raise ValueError("dictionary was prepared for another A or precision")
+        o.dict = ctypes.pointer(dictionary.struct)
+    for name, t, dt in (("S_per_signal", S_per_signal, torch.int32), ("eps_per_signal", eps_per_signal,
+                                                                       torch.float32)):
+        if t is not None and (t.dtype != dt or t.shape != (B,) or not t.is_contiguous()):
+            raise TypeError(f"{name} must be a contiguous {dt} tensor of shape (B,)")
+    o.S_per_signal = _ptr(S_per_signal)
+    o.eps_per_signal = _ptr(eps_per_signal)
+    if out is None:
+        out = Result(torch.empty((B, N), dtype=torch.float32, device=dev) if dense else None,
+                     torch.empty((B, S), dtype=torch.int32, device=dev),
+                     torch.empty((B, S), dtype=torch.float32, device=dev),
+                     torch.empty(B, dtype=torch.int32, device=dev), torch.empty(B, dtype=torch.float32, device=dev))
+    o.status_out = _ptr(out.status)
+    o.rnorm_out = _ptr(out.rnorm)
+    o.coef_out = _ptr(out.coef)
+    with torch.cuda.device(dev):
+        rc = lib.omp_solve_noalloc(_ptr(A), M, N, A.stride(0), _ptr(Y), B, Y.stride(0), int(S), float(eps),
+                                   _ptr(out.X), _ptr(out.support), ctypes.byref(o), _stream_handle(stream, dev))
+    if rc != OMP_OK:
+        raise OmpError(rc, "omp_solve_noalloc")
+    _used_on(stream, *out)
     return out
 
 

@@ -406,3 +406,22 @@ def test_learned_solve_rejects_invalid(lib):
     a[13] = 1024
     assert lib.omp_learned_solve(ctypes.byref(d), ctypes.byref(fm), *a) == omp.OMP_EWORKSPACE
     assert lib.omp_learned_solve(ctypes.byref(d0), ctypes.byref(fm), *args) == omp.OMP_EINVAL
+
+
+def test_noalloc_limits_checked_on_the_host(lib):
+    """omp_solve_noalloc refuses, before any device work, a request whose workspace
+    exceeds its static scratch (OMP_ENOTSUPP) and a timed call (OMP_EINVAL)."""
+    from paper_2407_06434_amd import omp
+    cap = lib.omp_noalloc_max_bytes()
+    assert cap == 64 << 20
+    o = _opts(ws=0)
+    o.workspace = None
+    M, N, B, S = 1024, 4096, 4096, 64
+    assert lib.omp_workspace_size(M, N, B, S, ctypes.byref(o)) > cap
+    rc = lib.omp_solve_noalloc(FAKE, M, N, M, FAKE, B, M, S, 0.0, None, FAKE, ctypes.byref(o), None)
+    assert rc == omp.OMP_ENOTSUPP
+    ms = (ctypes.c_float * omp.NPHASE)()
+    o.phase_ms = ms
+    rc = lib.omp_solve_noalloc(FAKE, 64, 256, 64, FAKE, 10, 64, 8, 0.0, None, FAKE, ctypes.byref(o), None)
+    assert rc == omp.OMP_EINVAL
+    assert lib.omp_solve_noalloc(FAKE, 64, 256, 64, FAKE, 10, 64, 8, 0.0, None, FAKE, None, None) == omp.OMP_EINVAL
