@@ -55,6 +55,14 @@ def corr_flops_per_launch(M, N, B):
     return 2.0 * M * N * B
 
 
+def corr_operand_bytes_per_launch(M, N, B, bf16, keys_per_signal):
+    """Operand bytes of one correlation launch, each read or written once: the
+    dictionary (N M elements), the residuals (B M), the selected-atom masks (N / 8 per
+    signal) and the select keys written (4 bytes each in the BF16 form, 8 in FP32)."""
+    e = 2.0 if bf16 else 4.0
+    return e * N * M + e * B * M + B * N / 8.0 + B * keys_per_signal * (4.0 if bf16 else 8.0)
+
+
 def solve_bytes_per_launch(M, S, B):
     """Algorithmic bytes of one solve launch, averaged over the S iterations. Per
     signal at support size K: the atom n* and y for beta (8 M), the packed factor
@@ -98,8 +106,11 @@ def kernel_rooflines(w, precision, tim):
             e.update(extra)
         out[name] = e
 
+    # keys per signal on the benchmark shape: 16 tiles of 256 atoms, 24 BF16 keys or 1 FP32 key each
+    keys = (w.N // 256) * (24 if bf16 else 1)
     entry("k_corr_select", "corr", "mfma", corr_flops_per_launch(w.M, w.N, w.B), 1e12,
-          PEAK["bf16_mfma"] if bf16 else PEAK["fp32_mfma"], "TFLOP/s")
+          PEAK["bf16_mfma"] if bf16 else PEAK["fp32_mfma"], "TFLOP/s",
+          extra=dict(operand_bytes_per_launch=float(f"{corr_operand_bytes_per_launch(w.M, w.N, w.B, bf16, keys):.5e}")))
     entry("k_solve", "update", "hbm", solve_bytes_per_launch(w.M, w.S, w.B), 1e9, PEAK["hbm"], "GB/s")
     gb = residual_gather_bytes_per_launch(w.M, w.S, w.B)
     ms, n = tim["residual"]
@@ -535,13 +546,24 @@ def run_sweep_tall(B=2000, S=32, steps=3, warmup=1):
     return rows
 
 
+def cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, target_s):
-    """The oracle, as it stands, on the first n signals of the same workload."""
+    """The oracle, as it stands, on the first n signals of the same workload. Returns
+    the baseline entry and the oracle's results on those n signals."""
     import oracle
     threads = oracle.default_threads()
     n0 = threads
     t0 = time.perf_counter()
-    first = oracle.omp(w.A, w.Y[:n0], w.S, w.eps, threads=threads)
+    parts = [oracle.omp(w.A, w.Y[:n0], w.S, w.eps, threads=threads)]
     t1 = time.perf_counter() - t0
     n = n0
     if t1 < target_s:
@@ -549,12 +571,24 @@ def cpu_baseline(w, target_s):
         extra = min(extra, w.B - n0)
         if extra > 0:
             t0 = time.perf_counter()
-            oracle.omp(w.A, w.Y[n0:n0 + extra], w.S, w.eps, threads=threads)
+            parts.append(oracle.omp(w.A, w.Y[n0:n0 + extra], w.S, w.eps, threads=threads))
             t1 += time.perf_counter() - t0
             n += extra
-    return dict(value=n / t1, unit="signals/s", cores=threads, kind="oracle",
+    res = {k: np.concatenate([p[k] for p in parts]) for k in parts[0]}
+    return dict(value=n / t1, unit="signals/s", cores=threads, cpu_model=cpu_model(), kind="oracle",
                 sample=f"first {n} of the {w.B} signals of the benchmark workload, FP64, "
-                       f"{threads} host threads, {t1:.1f} s"), first
+                       f"{threads} host threads, {t1:.1f} s"), res
+
+
+def oracle_parity(w, gpu_res, free, n):
+    """The GPU's results on the n signals the oracle solved, checked pick by pick and
+    coefficient by coefficient against it (tests/parity.py rules)."""
+    import oracle
+    from tests import parity
+    idx = np.arange(n)
+    rep = parity.check(w, gpu_res, oracle, idx=idx, free=free, raise_on_fail=False)
+    return {k: rep[k] for k in ("checked", "passed", "exact_support", "near_tie_picks", "unresolved_fp32",
+                                "n_fail", "worst_coef_rel", "worst_pick_ratio")}
 
 
 def main():
@@ -636,7 +670,10 @@ def main():
     roof = dict(kernel=dom, **{k: v for k, v in kern[dom].items() if k != "total_ms"})
     roof["traffic"] = measured_traffic(dom, args.precision)
     if roof["traffic"] is not None:
-        roof["traffic_over_algorithmic"] = round(roof["traffic"] / roof["algorithmic_per_launch"], 3)
+        # bytes against bytes: an MFMA-bound kernel's counted traffic over its operand bytes
+        base = roof.get("operand_bytes_per_launch", roof["algorithmic_per_launch"])
+        roof["traffic_over_operand_bytes" if "operand_bytes_per_launch" in roof else
+             "traffic_over_algorithmic"] = round(roof["traffic"] / base, 3)
 
     line = {
         "metric": METRIC, "value": round(sps, 1), "unit": "signals/s", "n_gpus": 1, "steps": args.steps,
@@ -705,12 +742,13 @@ def main():
         log(f"learned: {lr}")
 
     if not args.no_cpu_baseline:
-        cb, first = cpu_baseline(w, args.cpu_seconds)
+        cb, free = cpu_baseline(w, args.cpu_seconds)
         line["cpu_baseline"] = cb
-        n = first["support"].shape[0]
-        same = [set(first["support"][i].tolist()) == set(g["res"]["support"][i].tolist()) for i in range(n)]
-        line["oracle_same_supports"] = f"{sum(same)}/{n}"
         log(f"cpu baseline {cb}")
+        n = free["support"].shape[0]
+        t = time.perf_counter()
+        line["oracle_parity"] = oracle_parity(w, g["res"], free, n)
+        log(f"oracle parity on {n} signals ({time.perf_counter() - t:.1f} s): {line['oracle_parity']}")
     print(json.dumps(line), flush=True)
 
 

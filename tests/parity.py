@@ -41,7 +41,11 @@ SIG_MASK = 0xFF
 
 
 def check(w, gpu: dict, orc, idx=None, tie=1e-5, coef_tol=1e-4, stop_tol=1e-5, threads=None,
-          S_per=None, eps_per=None, eps=None, raise_on_fail=True, residual_rounding=False, fp64=False) -> dict:
+          S_per=None, eps_per=None, eps=None, raise_on_fail=True, residual_rounding=False, fp64=False,
+          free=None) -> dict:
+    """Check the GPU results `gpu` (support, coef, status, rnorm, optional X) on the
+    signals `idx` (default all). `free`: the oracle's own run on those signals, if the
+    caller already has it (it is recomputed otherwise)."""
     B = w.Y.shape[0]
     idx = np.arange(B) if idx is None else np.asarray(idx)
     A = w.A
@@ -60,7 +64,8 @@ def check(w, gpu: dict, orc, idx=None, tie=1e-5, coef_tol=1e-4, stop_tol=1e-5, t
     g_k = g_status >> 8
     g_bits = g_status & SIG_MASK
 
-    free = orc.omp(A, Y, S, eps, S_per_signal=Sp, eps_per_signal=Ep, threads=threads)
+    if free is None:
+        free = orc.omp(A, Y, S, eps, S_per_signal=Sp, eps_per_signal=Ep, threads=threads)
     rep = orc.omp(A, Y, S, eps, S_per_signal=Sp, eps_per_signal=Ep, prefix=g_sup,
                   nprefix=g_k.astype(np.int32), threads=threads)
 
