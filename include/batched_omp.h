@@ -170,6 +170,17 @@ typedef struct omp_opts {
                                    (workspace: omp_workspace_size with the same opts) and wider
                                    re-scoring; for debugging and parity runs. 0 (default): off.
                                    Other values: OMP_EINVAL. */
+  int32_t v0;                   /* 1 = the paper's Algorithm v0 (Section 2.3): the inverse
+                                   Cholesky factor F_k = V_k^{-T} and D_k = A^T A_k F_k are
+                                   updated instead of a Cholesky factor and residual vectors;
+                                   c = A^T r is kept per signal from P = A^T y and updated by
+                                   one N-long column of D per step (O(N k) bytes per signal and
+                                   step, no correlation product); x = F u at the end. FP32 only,
+                                   with an FP64 pivot; not with gram_domain = 1, refactor or
+                                   gram_on_the_fly (else OMP_EINVAL; gram_domain = 2 is ignored).
+                                   The workspace grows by B_pad N_pad (S + 1 + c) 4 bytes (c as
+                                   for the Gram-domain form): 4.3 GB for 4096 signals of a
+                                   4096-atom dictionary at S = 64. 0 (default): off. */
 } omp_opts_t;
 
 /* Phases reported through omp_opts_t.phase_ms. */

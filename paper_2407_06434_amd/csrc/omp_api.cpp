@@ -62,12 +62,12 @@ struct WorkLayout {
   int ntile;
   int nslice, slice_len;
   int64_t vstride;
-  size_t Yp, R32, R16, part, mask, k, flags, pnorm, pdelta, Sb, epsb, sup, u, xh, V, P, Pk, total;
+  size_t Yp, R32, R16, part, mask, k, flags, pnorm, pdelta, Sb, epsb, sup, u, xh, V, P, Pk, D, total;
   int pchunks;
 };
 
 WorkLayout work_layout(int64_t M, int64_t N, int64_t B, int S, int precision, int cfg, bool gram_dom = false,
-                       bool ties = false) {
+                       bool ties = false, bool v0 = false) {
   WorkLayout L;
   L.Mp = round_up(M, KPAD);
   L.Np = round_up(N, NPAD);
@@ -84,7 +84,7 @@ WorkLayout work_layout(int64_t M, int64_t N, int64_t B, int S, int precision, in
   L.R16 = precision == OMP_PREC_BF16 ? c.take<uint16_t>(Bp * L.Mp) : 0;
   // (the Gram-domain select writes GSLICE keys per signal, twice that with near-tie flagging)
   L.part = c.take<uint64_t>(Bp * (size_t)std::max<int64_t>((int64_t)L.ntile * L.g.keys_per_tile,
-                                                            gram_dom ? GSLICE * (ties ? 2 : 1) : 1));
+                                                            gram_dom ? GSLICE * (ties ? 2 : 1) : 2));
   L.mask = c.take<uint32_t>(Bp * (L.Np / 32));
   L.k = c.take<int32_t>(Bp);
   L.flags = c.take<int32_t>(Bp);
@@ -97,9 +97,11 @@ WorkLayout work_layout(int64_t M, int64_t N, int64_t B, int S, int precision, in
   L.xh = c.take<float>(Bp * Sz);
   L.vstride = round_up((int64_t)(Sz * (Sz + 1) / 2), 4);
   L.V = c.take<float>(Bp * (size_t)L.vstride);
-  L.P = gram_dom ? c.take<float>(Bp * (size_t)L.Np) : 0;
-  L.pchunks = gram_dom ? project_chunks(L.Bp, L.Np, L.Mp) : 1;
+  const bool proj = gram_dom || v0;  // forms that start from P = A^T y
+  L.P = proj ? c.take<float>(Bp * (size_t)L.Np) : 0;
+  L.pchunks = proj ? project_chunks(L.Bp, L.Np, L.Mp) : 1;
   L.Pk = L.pchunks > 1 ? c.take<float>((size_t)L.pchunks * Bp * (size_t)L.Np) : 0;
+  L.D = v0 ? c.take<float>(Bp * Sz * (size_t)L.Np) : 0;
   L.total = (c.off + ALIGN - 1) / ALIGN * ALIGN;
   return L;
 }
@@ -237,8 +239,9 @@ DictView dict_view(void *mem, int64_t M, int64_t N, int precision) {
   return d;
 }
 
-size_t work_bytes(int64_t M, int64_t N, int64_t B, int S, int precision, int cfg, bool gram_dom, bool ties) {
-  return work_layout(M, N, B, S, precision, cfg, gram_dom, ties).total;
+size_t work_bytes(int64_t M, int64_t N, int64_t B, int S, int precision, int cfg, bool gram_dom, bool ties,
+                  bool v0) {
+  return work_layout(M, N, B, S, precision, cfg, gram_dom, ties, v0).total;
 }
 
 bool solve_fits(int64_t M, int64_t N, int64_t B, int S, int precision, int cfg) {
@@ -247,8 +250,8 @@ bool solve_fits(int64_t M, int64_t N, int64_t B, int S, int precision, int cfg) 
 }
 
 WorkView work_view(void *mem, int64_t M, int64_t N, int64_t B, int S, int precision, int cfg, bool gram_dom,
-                   bool ties) {
-  const WorkLayout L = work_layout(M, N, B, S, precision, cfg, gram_dom, ties);
+                   bool ties, bool v0) {
+  const WorkLayout L = work_layout(M, N, B, S, precision, cfg, gram_dom, ties, v0);
   WorkView w;
   w.B = B;
   w.Bp = L.Bp;
@@ -283,7 +286,9 @@ WorkView work_view(void *mem, int64_t M, int64_t N, int64_t B, int S, int precis
   w.gram_fly = 0;
   w.refactor = 0;
   w.gram_dom = gram_dom ? 1 : 0;
-  w.P = gram_dom ? at<float>(mem, L.P) : nullptr;
+  w.P = (gram_dom || v0) ? at<float>(mem, L.P) : nullptr;
+  w.v0 = v0 ? 1 : 0;
+  w.D = v0 ? at<float>(mem, L.D) : nullptr;
   w.pchunks = L.pchunks;
   w.Pk = L.pchunks > 1 ? at<float>(mem, L.Pk) : nullptr;
   w.flag_ties = ties ? 1 : 0;
@@ -371,8 +376,10 @@ size_t bomp::solve_bytes(int64_t M, int64_t N, int64_t B, int32_t S, const omp_o
   if (prec != OMP_PREC_FP32 && prec != OMP_PREC_BF16) return 0;
   const int cfg = opts ? opts->tile_config : 0;
   if (cfg < 0 || cfg > MAX_TILE_CFG) return 0;
-  size_t total = work_bytes(M, N, B, S, prec, cfg, opts && gram_domain_form(opts->gram_domain, prec, M, N),
-                            opts && opts->flag_near_ties == 1);
+  const bool v0 = opts && opts->v0 == 1;
+  size_t total = work_bytes(M, N, B, S, prec, cfg,
+                            !v0 && opts && gram_domain_form(opts->gram_domain, prec, M, N),
+                            opts && opts->flag_near_ties == 1, v0);
   if (!opts || !opts->dict) total += dict_bytes(M, N, prec);
   return total;
 }
@@ -393,7 +400,11 @@ int solve_impl(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y
   if (opts->gram_domain < 0 || opts->gram_domain > 2) return OMP_EINVAL;
   if (opts->gram_domain == 1 && prec != OMP_PREC_FP32) return OMP_EINVAL;
   if (opts->flag_near_ties != 0 && opts->flag_near_ties != 1) return OMP_EINVAL;
-  const bool gdom = gram_domain_form(opts->gram_domain, prec, M, N);
+  if (opts->v0 != 0 && opts->v0 != 1) return OMP_EINVAL;
+  const bool v0 = opts->v0 == 1;
+  if (v0 && (prec != OMP_PREC_FP32 || opts->gram_domain == 1 || opts->gram_on_the_fly || opts->refactor))
+    return OMP_EINVAL;
+  const bool gdom = !v0 && gram_domain_form(opts->gram_domain, prec, M, N);
   const bool ties = opts->flag_near_ties == 1;
   if (!dims_ok(M, N) || B < 0 || B > ((int64_t)1 << 26)) return OMP_EINVAL;
   if (S < 1 || S > M || S > N) return OMP_EINVAL;
@@ -408,7 +419,7 @@ int solve_impl(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y
         !dd->mem)
       return OMP_EINVAL;
   }
-  const size_t wneed = work_bytes(M, N, B, S, prec, cfg, gdom, ties);
+  const size_t wneed = work_bytes(M, N, B, S, prec, cfg, gdom, ties, v0);
   const size_t need = wneed + (opts->dict ? 0 : dict_bytes(M, N, prec));
   if (!workspace || workspace_bytes < need || !aligned(workspace, ALIGN)) return OMP_EWORKSPACE;
   if (B == 0) return OMP_OK;
@@ -431,14 +442,21 @@ int solve_impl(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y
       if (e == hipSuccess) e = timer.run(OMP_PHASE_DICT, [&] { return launch_gram(d, cs); });
       if (e != hipSuccess) return e;
     }
-    WorkView w = work_view(workspace, M, N, B, S, prec, cfg, gdom, ties);
+    WorkView w = work_view(workspace, M, N, B, S, prec, cfg, gdom, ties, v0);
     w.gram_fly = opts->gram_on_the_fly;
     w.refactor = opts->refactor;
     e = timer.run(OMP_PHASE_INIT, [&] {
       return launch_init(Y, ldy, opts->S_per_signal, opts->eps_per_signal, eps, d, w, prec, cs);
     });
-    if (gdom && e == hipSuccess) e = timer.run(OMP_PHASE_INIT, [&] { return launch_project(d, w, cs); });
-    for (int it = 0; it < S && e == hipSuccess; ++it) {
+    if ((gdom || v0) && e == hipSuccess) e = timer.run(OMP_PHASE_INIT, [&] { return launch_project(d, w, cs); });
+    if (v0) {
+      // Algorithm v0: one kernel per step, the coefficients x = F u at the end
+      if (e == hipSuccess) e = timer.run(OMP_PHASE_INIT, [&] { return launch_v0_first(d, w, cs); });
+      for (int it = 0; it < S && e == hipSuccess; ++it)
+        e = timer.run(OMP_PHASE_UPDATE, [&] { return launch_v0_step(d, w, cs); });
+      if (e == hipSuccess) e = timer.run(OMP_PHASE_OUTPUT, [&] { return launch_v0_coef(w, cs); });
+    }
+    for (int it = 0; it < S && e == hipSuccess && !v0; ++it) {
       if (gdom) {
         // Gram-domain form: correlations from P and G; no residual vectors
         e = timer.run(OMP_PHASE_CORR, [&] { return launch_gram_select(d, w, cs); });
@@ -465,8 +483,8 @@ int solve_impl(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y
     struct Key {
       const void *A, *Y, *X, *sup, *Sp, *Ep, *st_out, *rn_out, *coef, *dmem, *ws, *pool;
       int64_t M, N, lda, B, ldy;
-      int32_t S, prec, cfg, gram_fly, refactor, gram_dom, ties;
-      uint32_t eps_bits;
+      int32_t S, prec, cfg, gram_fly, refactor, gram_dom, ties, v0;
+      uint32_t eps_bits, pad;
     } key;
     std::memset(&key, 0, sizeof(key));
     key.A = A;
@@ -493,11 +511,12 @@ int solve_impl(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y
     key.refactor = opts->refactor;
     key.gram_dom = gdom ? 1 : 0;
     key.ties = ties ? 1 : 0;
+    key.v0 = v0 ? 1 : 0;
     std::memcpy(&key.eps_bits, &eps, sizeof(float));
     {
       const DictView dp = opts->dict ? dict_view(opts->dict->mem, M, N, prec)
                                      : dict_view(static_cast<char *>(workspace) + wneed, M, N, prec);
-      e = prepare_kernels(dp, work_view(workspace, M, N, B, S, prec, cfg, gdom, ties), prec, 0);
+      e = prepare_kernels(dp, work_view(workspace, M, N, B, S, prec, cfg, gdom, ties, v0), prec, 0);
     }
     if (e == hipSuccess)
       e = graph_launch_cached(std::string(reinterpret_cast<const char *>(&key), sizeof(key)),

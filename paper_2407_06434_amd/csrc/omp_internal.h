@@ -94,6 +94,8 @@ struct WorkView {
   float *Pk;      // [pchunks][Bp][Np] split-K partial products of P (pchunks > 1), else nullptr
   int pchunks;    // K chunks of the P product (1: no split)
   int flag_ties;  // 1: near-tie flagging (the select stages keep the second best atom too)
+  int v0;         // 1: Algorithm v0 (inverse Cholesky factor F in V, D = A^T Q, correlations in P)
+  float *D;       // [Bp][S][Np] v0: D's columns d_j = A^T q_j, each Np long (else nullptr)
 };
 
 // Gram-domain select: the atoms are split into this many contiguous slices, one
@@ -111,11 +113,12 @@ inline int project_chunks(int64_t Bp, int64_t Np, int64_t Mp) {
 }
 
 // `gram_dom` adds the Gram-domain form's P buffer to the layout; `ties` (near-tie
-// flagging) doubles the FP32 and Gram-domain select keys (best and second best).
+// flagging) doubles the FP32, Gram-domain and v0 select keys (best and second
+// best); `v0` adds P and the D columns of Algorithm v0.
 size_t work_bytes(int64_t M, int64_t N, int64_t B, int S, int precision, int cfg, bool gram_dom = false,
-                  bool ties = false);
+                  bool ties = false, bool v0 = false);
 WorkView work_view(void *mem, int64_t M, int64_t N, int64_t B, int S, int precision, int cfg,
-                   bool gram_dom = false, bool ties = false);
+                   bool gram_dom = false, bool ties = false, bool v0 = false);
 
 // ---- the solve kernel's LDS (shared by its launcher and the entry points'
 // validation) ---------------------------------------------------------------
@@ -223,6 +226,12 @@ hipError_t launch_densify(const int32_t *support, const float *coef, int64_t nsi
 // Raise the LDS limits of every kernel a solve with these views launches (no launch).
 hipError_t prepare_kernels(const DictView &d, const WorkView &w, int precision, int lanes);
 hipError_t prepare_corr(const DictView &d, const WorkView &w, int precision);
+
+// Algorithm v0 (FP32): each signal's first pick from P = A^T y; one step (pick, pivot,
+// new columns of F and D, correlation update, next pick) per live signal; x = F u.
+hipError_t launch_v0_first(const DictView &d, const WorkView &w, hipStream_t st);
+hipError_t launch_v0_step(const DictView &d, const WorkView &w, hipStream_t st);
+hipError_t launch_v0_coef(const WorkView &w, hipStream_t st);
 
 // Outputs: dense X, support, coefficients, status, residual norm.
 hipError_t launch_finalize(const DictView &d, const WorkView &w, float *X_out,

@@ -625,8 +625,8 @@ __device__ void init_column(const WorkView &w, int64_t b, const float *__restric
   const bool all_finite = __all(finite);
   if (lane < NSLICE_MAX) {
     w.pnorm[b * NSLICE_MAX + lane] = (lane == 0 && all_finite) ? s : 0.0;
-    // (the Gram-domain form keeps ||y||^2 there: the rounding scale of its running ||r||^2)
-    w.pdelta[b * NSLICE_MAX + lane] = (lane == 0 && all_finite) ? (w.gram_dom ? s : dl) : 0.0;
+    // (the Gram-domain and v0 forms keep ||y||^2 there: the rounding scale of their running ||r||^2)
+    w.pdelta[b * NSLICE_MAX + lane] = (lane == 0 && all_finite) ? ((w.gram_dom || w.v0) ? s : dl) : 0.0;
   }
   if (lane == 0) {
     eb = fmaxf(eb, 0.f);  // also maps NaN to 0
@@ -1221,6 +1221,232 @@ __global__ __launch_bounds__(64) void k_gram_select(DictView d, WorkView w) {
 }
 
 // ---------------------------------------------------------------------------
+// Algorithm v0 of the paper (Section 2.3): the inverse Cholesky factor
+// F_k = V_k^{-T} (upper triangular) and D_k = A^T A_k F_k = A^T Q_k, Q_k = A_k F_k
+// having orthonormal columns. No correlation product and no residual vectors:
+// every step works on N-long rows of one signal.
+//   c_0 = A^T y (the projection product, stored in w.P), n* = argmax |c| / ||a||
+//   z   = D_{k-1}[n*, :]                 (a_n*^T q_j, j < k)
+//   g   = 1 / sqrt(||a_n*||^2 - ||z||^2)   (FP64 pivot)
+//   d_k = g (G[:, n*] - D_{k-1} z)        (new column of D: A^T q_k)
+//   u_k = g c_{k-1}[n*]                   (q_k^T y)
+//   c_k = c_{k-1} - u_k d_k               (A^T r_k)
+//   F_k = [[F_{k-1}, -g F_{k-1} z], [0, g]]
+//   ||r_k||^2 = ||r_{k-1}||^2 - u_k^2, and at the end x = F_S u.
+// The signal's next pick is found while c_k is written (one key per signal in
+// w.part), so a step reads c once. One workgroup of V0_THREADS per signal;
+// D is [Bp][S][Np] (column j of D_k contiguous), F packed by columns in w.V.
+// ---------------------------------------------------------------------------
+constexpr int V0_THREADS = 256;
+
+// Block-wide maximum of a 64-bit key (every thread gets it). red: LDS [V0_THREADS / 64].
+__device__ inline uint64_t block_max(uint64_t v, uint64_t *red) {
+  v = wave_max(v);
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) red[wv] = v;
+  __syncthreads();
+  uint64_t m = red[0];
+#pragma unroll
+  for (int i = 1; i < V0_THREADS / 64; ++i) m = red[i] > m ? red[i] : m;
+  __syncthreads();
+  return m;
+}
+
+// Key of atom n with correlation c (0: not a candidate), as the FP32 select writes it.
+__device__ inline uint64_t v0_key(float c, float iv, bool taken, int64_t n) {
+  return (iv > 0.f && !taken) ? ((uint64_t)__float_as_uint(fabsf(c) * iv) << 32) | (0xFFFFFFFFull - (uint64_t)n)
+                              : 0ull;
+}
+
+// The block's best and second best keys (threads hold their own best and second),
+// stored as the signal's two keys for the next step.
+__device__ inline void v0_store_pick(const WorkView &w, int64_t b, uint64_t best, uint64_t sec, uint64_t *red) {
+  const uint64_t top = block_max(best, red);
+  const uint64_t second = block_max(best == top ? sec : best, red);
+  if (threadIdx.x == 0) {
+    w.part[2 * b] = top;
+    w.part[2 * b + 1] = second;
+  }
+}
+
+// First pick of every signal from c_0 = P (one workgroup per signal).
+__global__ __launch_bounds__(V0_THREADS) void k_v0_first(DictView d, WorkView w) {
+  __shared__ uint64_t red[V0_THREADS / 64];
+  const int64_t b = blockIdx.x;
+  const float *c = w.P + b * d.Np;
+  uint64_t best = 0, sec = 0;
+  for (int64_t n = threadIdx.x; n < d.Np; n += V0_THREADS) {
+    const uint64_t key = v0_key(c[n], d.inv_nu[n], false, n);
+    sec = max(sec, min(best, key));
+    best = key > best ? key : best;
+  }
+  v0_store_pick(w, b, best, sec, red);
+}
+
+// One v0 step for every live signal.
+__global__ __launch_bounds__(V0_THREADS) void k_v0_step(DictView d, WorkView w) {
+  extern __shared__ uint32_t v0s[];
+  __shared__ uint64_t red[V0_THREADS / 64];
+  __shared__ double zzs;
+  const int64_t b = blockIdx.x;
+  const int tid = threadIdx.x;
+  int fl = w.flags[b];
+  if (fl & FLAG_DONE) return;  // the whole block leaves
+  const int k = w.k[b];
+  const int S = w.S;
+  const int64_t Np = d.Np, mwords = Np / 32;
+  float *zs = reinterpret_cast<float *>(v0s);                 // [S]
+  uint32_t *mk = v0s + S;                                     // [Np / 32] selected-atom mask
+  const double rn = sqrt(w.pnorm[b * NSLICE_MAX]);
+  const float eps_b = w.epsb[b];
+  const uint64_t key = w.part[2 * b], key2 = w.part[2 * b + 1];
+  // stop test on the current residual, then the pick found by the previous step
+  if (rn <= (double)eps_b || key == 0ull) {
+    if (tid == 0) w.flags[b] = fl | FLAG_DONE | (rn <= (double)eps_b ? 0 : OMP_SIG_EXHAUSTED);
+    return;
+  }
+  const int nstar = (int)(0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull));
+  if (w.flag_ties && key2 != 0ull &&
+      (double)__uint_as_float((uint32_t)(key2 >> 32)) >= (1.0 - TIE_REL) * (double)__uint_as_float((uint32_t)(key >> 32)))
+    fl |= OMP_SIG_NEARTIE;
+  float *Db = w.D + b * (int64_t)S * Np;
+  float *c = w.P + b * Np;
+  for (int j = tid; j < k; j += V0_THREADS) zs[j] = Db[(int64_t)j * Np + nstar];
+  for (int64_t t = tid; t < mwords; t += V0_THREADS) mk[t] = w.mask[b * mwords + t];
+  if (tid < 64) {
+    double zz = 0.0;
+    for (int j = tid; j < k; j += 64) {
+      const double z = (double)Db[(int64_t)j * Np + nstar];
+      zz += z * z;
+    }
+    zz = wave_sum(zz);
+    if (tid == 0) zzs = zz;
+  }
+  __syncthreads();
+  const double nu2 = d.nu2[nstar];
+  const double d2 = nu2 - zzs;
+  if (!(d2 > DEP_TOL2 * nu2)) {  // dependent atom: stop without appending
+    if (tid == 0) w.flags[b] = fl | FLAG_DONE | OMP_SIG_DEPENDENT;
+    return;
+  }
+  const double gd = 1.0 / sqrt(d2);
+  const float g = (float)gd;
+  const float uk = (float)(gd * (double)c[nstar]);
+  // new column of F: f_i = -g sum_{j=i}^{k-1} F[i][j] z_j (i < k), f_k = g
+  const float *Fb = w.V + b * w.vstride;
+  float *Fk = w.V + b * w.vstride + (int64_t)k * (k + 1) / 2;
+  for (int i = tid; i <= k; i += V0_THREADS) {
+    if (i == k) {
+      Fk[k] = g;
+    } else {
+      double acc = 0.0;
+      for (int j = i; j < k; ++j) acc += (double)Fb[(int64_t)j * (j + 1) / 2 + i] * (double)zs[j];
+      Fk[i] = (float)(-gd * acc);
+    }
+  }
+  // d_k = g (G[n*, :] - D_{k-1} z), c_k = c_{k-1} - u_k d_k, and the next pick
+  const float4 *G4 = reinterpret_cast<const float4 *>(d.G + (int64_t)nstar * Np);
+  const float4 *D4 = reinterpret_cast<const float4 *>(Db);
+  float4 *Dk4 = reinterpret_cast<float4 *>(Db + (int64_t)k * Np);
+  float4 *c4 = reinterpret_cast<float4 *>(c);
+  const int64_t n4 = Np / 4;
+  uint64_t best = 0, sec = 0;
+  for (int64_t t = tid; t < n4; t += V0_THREADS) {
+    float4 a = G4[t];
+    int j = 0;
+    for (; j + 4 <= k; j += 4) {
+      const float4 e0 = D4[(int64_t)j * n4 + t], e1 = D4[(int64_t)(j + 1) * n4 + t];
+      const float4 e2 = D4[(int64_t)(j + 2) * n4 + t], e3 = D4[(int64_t)(j + 3) * n4 + t];
+      const float z0 = zs[j], z1 = zs[j + 1], z2 = zs[j + 2], z3 = zs[j + 3];
+      a.x = fmaf(-z0, e0.x, a.x); a.y = fmaf(-z0, e0.y, a.y); a.z = fmaf(-z0, e0.z, a.z); a.w = fmaf(-z0, e0.w, a.w);
+      a.x = fmaf(-z1, e1.x, a.x); a.y = fmaf(-z1, e1.y, a.y); a.z = fmaf(-z1, e1.z, a.z); a.w = fmaf(-z1, e1.w, a.w);
+      a.x = fmaf(-z2, e2.x, a.x); a.y = fmaf(-z2, e2.y, a.y); a.z = fmaf(-z2, e2.z, a.z); a.w = fmaf(-z2, e2.w, a.w);
+      a.x = fmaf(-z3, e3.x, a.x); a.y = fmaf(-z3, e3.y, a.y); a.z = fmaf(-z3, e3.z, a.z); a.w = fmaf(-z3, e3.w, a.w);
+    }
+    for (; j < k; ++j) {
+      const float4 e = D4[(int64_t)j * n4 + t];
+      const float z = zs[j];
+      a.x = fmaf(-z, e.x, a.x); a.y = fmaf(-z, e.y, a.y); a.z = fmaf(-z, e.z, a.z); a.w = fmaf(-z, e.w, a.w);
+    }
+    a.x *= g; a.y *= g; a.z *= g; a.w *= g;
+    Dk4[t] = a;
+    float4 cv = c4[t];
+    const float dv[4] = {a.x, a.y, a.z, a.w};
+    float cc[4] = {cv.x, cv.y, cv.z, cv.w};
+    const float4 iv4 = reinterpret_cast<const float4 *>(d.inv_nu)[t];
+    const float iv[4] = {iv4.x, iv4.y, iv4.z, iv4.w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t n = 4 * t + e;
+      const bool taken = n == nstar || ((mk[n >> 5] >> (n & 31)) & 1u);
+      cc[e] = taken ? 0.f : fmaf(-uk, dv[e], cc[e]);
+      const uint64_t kk = v0_key(cc[e], iv[e], taken, n);
+      sec = max(sec, min(best, kk));
+      best = kk > best ? kk : best;
+    }
+    c4[t] = make_float4(cc[0], cc[1], cc[2], cc[3]);
+  }
+  v0_store_pick(w, b, best, sec, red);
+  const int K = k + 1;
+  // ||r_K||^2 = ||r_k||^2 - u_K^2 (FP64 running value); at its own rounding level,
+  // or within it of eps_b^2, formed explicitly from y - A_S x, x = F_K u.
+  double r2 = rn * rn - (double)uk * (double)uk;
+  const double y2 = w.pdelta[b * NSLICE_MAX];
+  const double floor2 = 64.0 * (double)(K + 1) * (1.0 / 16777216.0) * y2;
+  const double e2 = (double)eps_b * (double)eps_b;
+  if (!(r2 > floor2) || fabs(r2 - e2) <= floor2) {
+    // x_i = sum_{j=i}^{K-1} F[i][j] u_j into LDS (zs reused), then r over m
+    __syncthreads();
+    const float *Fu = w.V + b * w.vstride;
+    for (int i = tid; i < K; i += V0_THREADS) {
+      double acc = 0.0;
+      for (int j = i; j < K; ++j)
+        acc += (double)Fu[(int64_t)j * (j + 1) / 2 + i] * (double)(j == k ? uk : w.u[b * S + j]);
+      zs[i] = (float)acc;
+    }
+    __syncthreads();
+    const float *yb = w.Yp + b * w.Mp;
+    double acc = 0.0;
+    for (int64_t m = tid; m < d.M; m += V0_THREADS) {
+      double rm = (double)yb[m];
+      for (int j = 0; j < K; ++j) {
+        const int sj = j == k ? nstar : w.sup[b * S + j];
+        rm -= (double)zs[j] * (double)d.A32[(int64_t)sj * d.Mp + m];
+      }
+      acc += rm * rm;
+    }
+    acc = wave_sum(acc);
+    __shared__ double part4[V0_THREADS / 64];
+    if ((tid & 63) == 0) part4[tid >> 6] = acc;
+    __syncthreads();
+    r2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < V0_THREADS / 64; ++i) r2 += part4[i];
+  }
+  if (tid == 0) {
+    w.pnorm[b * NSLICE_MAX] = r2;
+    w.sup[b * S + k] = nstar;
+    w.u[b * S + k] = uk;
+    w.mask[b * mwords + nstar / 32] = mk[nstar / 32] | (1u << (nstar & 31));
+    w.k[b] = K;
+    w.flags[b] = fl | (K >= w.Sb[b] ? FLAG_DONE : 0);
+  }
+}
+
+// Coefficients x = F_k u of every signal (one wavefront per signal), into w.xh.
+__global__ __launch_bounds__(64) void k_v0_coef(WorkView w) {
+  const int64_t b = blockIdx.x;
+  const int k = w.k[b];
+  const int S = w.S;
+  const float *F = w.V + b * w.vstride;
+  for (int i = threadIdx.x; i < k; i += 64) {
+    double acc = 0.0;
+    for (int j = i; j < k; ++j) acc += (double)F[(int64_t)j * (j + 1) / 2 + i] * (double)w.u[b * S + j];
+    w.xh[b * S + i] = (float)acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Residual: r = y - sum_j x_j a_{s_j} on one slice of M for every signal whose
 // coefficients changed in this iteration, and that slice's ||r||^2 (FP64).
 // Block of 256 lanes; an item (signal, slice) takes LP lanes, 64 / LP items per
@@ -1487,6 +1713,27 @@ hipError_t launch_gram_select(const DictView &d, const WorkView &w, hipStream_t 
       d.Np % (32 * GSLICE))
     return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_gram_select, dim3((unsigned)(w.B * GSLICE)), dim3(64), 0, st, d, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_v0_first(const DictView &d, const WorkView &w, hipStream_t st) {
+  if (!w.v0 || !w.P || !w.D || w.Np != d.Np || w.B == 0) return w.B == 0 ? hipSuccess : hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_v0_first, dim3((unsigned)w.B), dim3(V0_THREADS), 0, st, d, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_v0_step(const DictView &d, const WorkView &w, hipStream_t st) {
+  if (!w.v0 || !w.P || !w.D || w.Np != d.Np || d.Np % 4 || w.B == 0) return w.B == 0 ? hipSuccess : hipErrorInvalidValue;
+  const size_t lds = (size_t)(w.S + d.Np / 32) * 4;
+  hipError_t e = allow_lds(k_v0_step, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_v0_step, dim3((unsigned)w.B), dim3(V0_THREADS), lds, st, d, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_v0_coef(const WorkView &w, hipStream_t st) {
+  if (w.B == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_v0_coef, dim3((unsigned)w.B), dim3(64), 0, st, w);
   return hipGetLastError();
 }
 

@@ -60,7 +60,7 @@ class OmpOptsStruct(ctypes.Structure):
                 ("phase_ms", ctypes.POINTER(ctypes.c_float)),
                 ("phase_launches", ctypes.POINTER(ctypes.c_int32)), ("use_graph", ctypes.c_int32),
                 ("gram_on_the_fly", ctypes.c_int32), ("refactor", ctypes.c_int32),
-                ("gram_domain", ctypes.c_int32), ("flag_near_ties", ctypes.c_int32)]
+                ("gram_domain", ctypes.c_int32), ("flag_near_ties", ctypes.c_int32), ("v0", ctypes.c_int32)]
 
 
 class OmpProblemStruct(ctypes.Structure):
@@ -210,7 +210,7 @@ Result = namedtuple("Result", "X support coef status rnorm")
 
 
 def workspace_bytes(M: int, N: int, B: int, S: int, precision: str = "fp32", with_dict: bool = False,
-                    tile_config: int = 0, gram_domain=False, flag_near_ties: bool = False) -> int:
+                    tile_config: int = 0, gram_domain=False, flag_near_ties: bool = False, v0: bool = False) -> int:
     lib = load()
     o = OmpOptsStruct()
     lib.omp_opts_default(ctypes.byref(o))
@@ -218,6 +218,7 @@ def workspace_bytes(M: int, N: int, B: int, S: int, precision: str = "fp32", wit
     o.tile_config = int(tile_config)
     o.gram_domain = 2 if gram_domain == "auto" else (1 if gram_domain else 0)
     o.flag_near_ties = 1 if flag_near_ties else 0
+    o.v0 = 1 if v0 else 0
     d = OmpDictStruct()
     if with_dict:
         o.dict = ctypes.pointer(d)
@@ -230,7 +231,7 @@ def solve(A: torch.Tensor, Y: torch.Tensor, S: int, eps: float = 0.0, *, precisi
           workspace: Optional[torch.Tensor] = None, out: Optional[Result] = None, stream=None,
           timing: Optional[dict] = None, tile_config: int = 0, graph: bool = True,
           gram_on_the_fly: bool = False, refactor: bool = False, gram_domain=False,
-          flag_near_ties: bool = False) -> Result:
+          flag_near_ties: bool = False, v0: bool = False) -> Result:
     """Batched OMP (Algorithm 1) on the GPU.
 
     A: (N, M) float32 atom-major dictionary; Y: (B, M) float32 signals.
@@ -248,7 +249,8 @@ def solve(A: torch.Tensor, Y: torch.Tensor, S: int, eps: float = 0.0, *, precisi
     takes each step's correlations from P = A^T y and the Gram matrix instead of from
     residual vectors; gram_domain="auto" picks that form for FP32 solves with M >= N.
     `flag_near_ties` sets status bit SIG_NEARTIE on signals where, at some step, the
-    runner-up atom scored within 1e-5 (relative) of the picked one.
+    runner-up atom scored within 1e-5 (relative) of the picked one. `v0` (FP32 only)
+    runs the paper's Algorithm v0 (inverse Cholesky factor and D = A^T Q).
     """
     _check_matrix(A, "A")
     N, M = A.shape
@@ -265,6 +267,7 @@ def solve(A: torch.Tensor, Y: torch.Tensor, S: int, eps: float = 0.0, *, precisi
     o.refactor = 1 if refactor else 0
     o.gram_domain = 2 if gram_domain == "auto" else (1 if gram_domain else 0)
     o.flag_near_ties = 1 if flag_near_ties else 0
+    o.v0 = 1 if v0 else 0
     if dictionary is not None:
         if dictionary.A is not A or dictionary.precision != precision:
             raise ValueError("dictionary was prepared for another A or precision")
@@ -315,7 +318,8 @@ def solve(A: torch.Tensor, Y: torch.Tensor, S: int, eps: float = 0.0, *, precisi
 def solve_noalloc(A: torch.Tensor, Y: torch.Tensor, S: int, eps: float = 0.0, *, precision: str = "fp32",
                   dictionary: Optional[Dictionary] = None, S_per_signal: Optional[torch.Tensor] = None,
                   eps_per_signal: Optional[torch.Tensor] = None, dense: bool = True,
-                  out: Optional[Result] = None, stream=None, tile_config: int = 0, gram_domain=False) -> Result:
+                  out: Optional[Result] = None, stream=None, tile_config: int = 0, gram_domain=False,
+                  v0: bool = False) -> Result:
     """omp_solve_noalloc: the solve of `solve` with the library's static device scratch as
     its workspace (no workspace tensor; the library allocates nothing). Outputs are
     allocated here unless `out` is given. Calls overlapping on one GPU race."""
@@ -330,6 +334,7 @@ def solve_noalloc(A: torch.Tensor, Y: torch.Tensor, S: int, eps: float = 0.0, *,
     o.precision = PREC[precision]
     o.tile_config = int(tile_config)
     o.gram_domain = 2 if gram_domain == "auto" else (1 if gram_domain else 0)
+    o.v0 = 1 if v0 else 0
     if dictionary is not None:
         if dictionary.A is not A or dictionary.precision != precision:
             raise ValueError("dictionary was prepared for another A or precision")

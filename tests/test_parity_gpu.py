@@ -21,7 +21,7 @@ def _torch():
 
 
 def run_gpu(w, precision="fp32", dense=True, S_per=None, eps_per=None, dictionary=False, A_pad=0, Y_pad=0,
-            gram_domain=False):
+            gram_domain=False, v0=False):
     torch = _torch()
     from paper_2407_06434_amd import omp
     dev = torch.device("cuda:0")
@@ -41,7 +41,8 @@ def run_gpu(w, precision="fp32", dense=True, S_per=None, eps_per=None, dictionar
     if eps_per is not None:
         kw["eps_per_signal"] = torch.from_numpy(np.asarray(eps_per, np.float32)).to(dev)
     d = omp.Dictionary(A, precision) if dictionary else None
-    res = omp.solve(A, Y, w.S, w.eps, precision=precision, dictionary=d, dense=dense, gram_domain=gram_domain, **kw)
+    res = omp.solve(A, Y, w.S, w.eps, precision=precision, dictionary=d, dense=dense, gram_domain=gram_domain, v0=v0,
+                    **kw)
     torch.cuda.synchronize()
     out = dict(support=res.support.cpu().numpy(), coef=res.coef.cpu().numpy(),
                status=res.status.cpu().numpy(), rnorm=res.rnorm.cpu().numpy())
@@ -51,13 +52,18 @@ def run_gpu(w, precision="fp32", dense=True, S_per=None, eps_per=None, dictionar
 
 
 PRECS = ["fp32", "bf16"]
-# every form of the solve: the two precisions of the residual-vector form and the
-# Gram-domain form (FP32)
-FORMS = ["fp32", "bf16", "gram"]
+# every form of the solve: the two precisions of the residual-vector form, the
+# Gram-domain form and Algorithm v0 (both FP32)
+FORMS = ["fp32", "bf16", "gram", "v0"]
 
 
 def _form(f):
-    return ("fp32", True) if f == "gram" else (f, False)
+    """(precision, solve options) of a form."""
+    if f == "gram":
+        return "fp32", {"gram_domain": True}
+    if f == "v0":
+        return "fp32", {"v0": True}
+    return f, {}
 
 
 @pytest.mark.parametrize("prec", PRECS)
@@ -71,12 +77,16 @@ def test_plain_64x256_full(orc, prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
-def test_batched_256x1024_prefix(orc, prec):
+def test_batched_256x1024_full(orc, prec):
+    """The 256 x 1024 workload in full (10,000 signals, S = 32), every signal against
+    the oracle pick by pick and coefficient by coefficient."""
     from paper_2407_06434_amd import workloads
-    w = workloads.batched_256x1024(B=512)
-    print(f"case batched_256x1024 B=512 {prec}", flush=True)
+    w = workloads.batched_256x1024()
+    assert w.B == 10000
+    print(f"case batched_256x1024 B=10000 {prec}", flush=True)
     rep = parity.check(w, run_gpu(w, prec, dictionary=True), orc)
     print(rep)
+    assert rep["passed"] == w.B
 
 
 @pytest.mark.parametrize("prec", PRECS)
@@ -90,21 +100,50 @@ def test_ragged_shapes(orc, M, N, B, S, prec):
     print(rep)
 
 
+def ls_invariants(A, Y, sup, coef, chunk=256):
+    """FP64 checks of every signal's GPU result on its own support: the coefficients
+    against the least-squares solution on that support (QR of A_S in FP64), and the
+    residual r = y - A_S x of the GPU's coefficients against the selected atoms,
+    max_j |a_j^T r| / (||a_j|| ||r||). Returns the worst of each."""
+    A64 = A.astype(np.float64)
+    worst_c, worst_o = 0.0, 0.0
+    for i in range(0, Y.shape[0], chunk):
+        s = sup[i:i + chunk]
+        As = np.transpose(A64[s], (0, 2, 1))                    # (b, M, k)
+        y = Y[i:i + chunk].astype(np.float64)
+        q, r = np.linalg.qr(As)
+        xls = np.linalg.solve(r, np.einsum("bmk,bm->bk", q, y)[..., None])[..., 0]
+        x = coef[i:i + chunk].astype(np.float64)
+        scale = np.maximum(np.abs(xls), 1e-2 * np.abs(xls).max(axis=1, keepdims=True))
+        worst_c = max(worst_c, float((np.abs(x - xls) / scale).max()))
+        res = y - np.einsum("bmk,bk->bm", As, x)
+        ortho = np.abs(np.einsum("bmk,bm->bk", As, res)) / (
+            np.linalg.norm(As, axis=1) * np.linalg.norm(res, axis=1, keepdims=True))
+        worst_o = max(worst_o, float(ortho.max()))
+    return worst_c, worst_o
+
+
 @pytest.mark.parametrize("prec", PRECS)
-def test_full_size_1024x4096_sampled(orc, prec):
-    """The benchmark's workload at full size (B=4096), 26 sampled signals against the oracle."""
+def test_full_size_1024x4096(orc, prec):
+    """The benchmark's workload at full size (B = 4096) in the benchmark's launch
+    configuration: the first 256 signals against the oracle pick by pick; on all 4096,
+    FP64 checks on the GPU's own supports (coefficients equal least squares there to
+    1e-4, the residual of the GPU's coefficients orthogonal to the selected atoms)."""
     from paper_2407_06434_amd import workloads
     w = workloads.bf16_1024x4096()
     print(f"case bf16_1024x4096 B=4096 {prec}", flush=True)
     out = run_gpu(w, prec, dictionary=True)
-    idx = np.random.default_rng(0).choice(w.B, 24, replace=False)
-    idx = np.concatenate([idx, [0, w.B - 1]])
-    rep = parity.check(w, out, orc, idx=idx)
-    print(rep)
     k = out["status"] >> 8
-    assert np.all(k == 64)
+    assert np.all(k == 64) and np.all(out["status"] & 0xFF & ~64 == 2)
     s = out["support"]
-    assert all(len(set(r.tolist())) == 64 for r in s)
+    assert all(len(set(r.tolist())) == 64 for r in s) and s.min() >= 0 and s.max() < w.N
+    rep = parity.check(w, out, orc, idx=np.arange(256))
+    print(rep)
+    assert rep["passed"] == 256
+    worst_c, worst_o = ls_invariants(w.A, w.Y, s, out["coef"])
+    print(f"all 4096: worst coefficient error vs FP64 least squares {worst_c:.2e}, "
+          f"worst orthogonality |a_j^T r| / (||a_j|| ||r||) {worst_o:.2e}")
+    assert worst_c <= 1e-4 and worst_o <= 1e-4
     if prec == "bf16":
         print("widened signals:", int(np.sum(out["status"] & 64 != 0)))
 
@@ -135,7 +174,7 @@ def test_bf16_same_supports_as_fp32_full_batch(orc):
 @pytest.mark.parametrize("form", FORMS)
 def test_edge_cases(orc, form):
     """y = 0, non-finite y, eps >= ||y||, per-signal S and eps, a dependent atom, a zero atom."""
-    prec, gd = _form(form)
+    prec, kw = _form(form)
     from paper_2407_06434_amd import workloads
     w = workloads.custom(48, 160, 12, 8, seed=3, k_true=6)
     w.A[17] = 0.0            # zero-norm atom: never selectable
@@ -149,7 +188,7 @@ def test_edge_cases(orc, form):
     eps_per[7] = 0.3 * np.linalg.norm(w.Y[7].astype(np.float64))
     w.S_per_signal, w.eps_per_signal = S_per, eps_per
     print(f"case edge cases {form}", flush=True)
-    out = run_gpu(w, prec, S_per=S_per, eps_per=eps_per, gram_domain=gd)
+    out = run_gpu(w, prec, S_per=S_per, eps_per=eps_per, **kw)
     rep = parity.check(w, out, orc)
     print(rep)
     st = out["status"]
@@ -163,7 +202,7 @@ def test_edge_cases(orc, form):
 @pytest.mark.parametrize("form", FORMS)
 def test_dependent_atom_stops(orc, form):
     """Two atoms 1e-4 rad apart: the second pick is dependent and is not appended."""
-    prec, gd = _form(form)
+    prec, kw = _form(form)
     from paper_2407_06434_amd import workloads
     a0 = np.zeros(64); a0[0] = 1.0
     a1 = np.zeros(64); a1[0] = 1.0; a1[1] = 1e-4
@@ -172,7 +211,7 @@ def test_dependent_atom_stops(orc, form):
     y = a1 + 0.01 * np.eye(64)[2]
     w = workloads.Workload("dep", A.astype(np.float32), y[None].astype(np.float32), 2, 0.0)
     print(f"case dependent atom {form}", flush=True)
-    out = run_gpu(w, prec, gram_domain=gd)
+    out = run_gpu(w, prec, **kw)
     rep = parity.check(w, out, orc)
     print(rep)
     assert out["status"][0] & 4 and out["status"][0] >> 8 == 1
@@ -208,7 +247,8 @@ def test_graph_replays_match_direct_launches(form):
     on every replay, with other eager GPU work and synchronisations between replays; a
     timed call (which launches directly) between replays gives the same result. The
     Gram-domain form runs on a tall dictionary whose projection is split along K."""
-    prec, gd = _form(form)
+    prec, kw = _form(form)
+    gd = kw.get("gram_domain", False)
     torch = _torch()
     from paper_2407_06434_amd import omp, workloads
     w = workloads.custom(2048, 300, 200, 24, seed=9, k_true=24) if gd else workloads.batched_256x1024(B=300)
@@ -217,17 +257,17 @@ def test_graph_replays_match_direct_launches(form):
     Y = torch.from_numpy(w.Y).to(dev)
     d = omp.Dictionary(A, prec)
     print(f"case graph replays {form}", flush=True)
-    ref = omp.solve(A, Y, w.S, precision=prec, dictionary=d, graph=False, gram_domain=gd)
+    ref = omp.solve(A, Y, w.S, precision=prec, dictionary=d, graph=False, **kw)
     torch.cuda.synchronize()
     ref = {k: v.cpu().numpy() for k, v in ref._asdict().items() if v is not None}
-    ws = torch.empty(omp.workspace_bytes(w.M, w.N, w.B, w.S, prec, with_dict=True, gram_domain=gd),
+    ws = torch.empty(omp.workspace_bytes(w.M, w.N, w.B, w.S, prec, with_dict=True, **kw),
                      dtype=torch.uint8, device=dev)
     out = None
     other = workloads.custom(64, 256, 50, 8, seed=4)
     for rep in range(5):
         timing = {} if rep == 2 else None
         out = omp.solve(A, Y, w.S, precision=prec, dictionary=d, workspace=ws, out=out, graph=True, timing=timing,
-                        gram_domain=gd)
+                        **kw)
         torch.cuda.synchronize()
         got = {k: v.cpu().numpy() for k, v in out._asdict().items() if v is not None}
         for k in ref:
@@ -240,9 +280,12 @@ def test_graph_replays_match_direct_launches(form):
         torch.cuda.synchronize()
         if timing is not None:
             print("graph timing", timing)
-            assert timing["corr"][1] == w.S and timing["update"][1] == w.S
-            assert timing["residual"][1] == (0 if gd else w.S)  # the Gram-domain form keeps no residuals
-            assert timing["init"][1] == (2 if gd else 1) and timing["output"][1] == 1
+            v0 = kw.get("v0", False)
+            assert timing["corr"][1] == (0 if v0 else w.S) and timing["update"][1] == w.S
+            # the Gram-domain and v0 forms keep no residual vectors
+            assert timing["residual"][1] == (0 if gd or v0 else w.S)
+            assert timing["init"][1] == (3 if v0 else 2 if gd else 1)
+            assert timing["output"][1] == (2 if v0 else 1)
             assert all(v[0] > 0 for k, v in timing.items() if v[1] > 0)
 
 
@@ -333,13 +376,13 @@ def test_near_tie_flags_match_the_oracle_gaps(orc, form):
         Y[b] = (1.0 + g.random(4)) * np.sign(g.normal(size=4)) @ A[inv[src]].astype(np.float64)
         Y[b] += 1e-2 * g.normal(size=M) / np.sqrt(M)
     w = workloads.Workload("twins_128x512", A, Y.astype(np.float32), S, 0.0)
-    prec, gdom = _form(form)
+    prec, kw = _form(form)
     dev = torch.device("cuda:0")
     At = torch.from_numpy(w.A).to(dev)
     Yt = torch.from_numpy(w.Y).to(dev)
     print(f"case near-tie flags {form}", flush=True)
-    plain = omp.solve(At, Yt, S, precision=prec, gram_domain=gdom)
-    flagged = omp.solve(At, Yt, S, precision=prec, gram_domain=gdom, flag_near_ties=True)
+    plain = omp.solve(At, Yt, S, precision=prec, **kw)
+    flagged = omp.solve(At, Yt, S, precision=prec, flag_near_ties=True, **kw)
     torch.cuda.synchronize()
     for k in ("support", "coef", "rnorm", "X"):
         assert torch.equal(getattr(plain, k), getattr(flagged, k)), k
@@ -409,6 +452,12 @@ def test_support_fills_the_signal_space(orc, prec, M, N):
     out = run_gpu(w, prec)
     rep = parity.check(w, out, orc, residual_rounding=True)
     print(rep)
+    # every signal passes or is unresolved in FP32 (a pick within the FP32 residual's
+    # rounding of the best score, or a coefficient within FP32 Cholesky's kappa^2 bound);
+    # measured: none at M = 16, 3 of 48 at M = 32, 38 of 48 at M = 64 (the FP64 form
+    # resolves them); the caps leave room for a few more.
+    assert rep["passed"] + rep["unresolved_fp32"] == w.B
+    assert rep["unresolved_fp32"] <= {16: 0, 32: 6, 64: 44}[M], rep
 
 
 @pytest.mark.parametrize("prec", PRECS)
@@ -500,6 +549,57 @@ def test_refactorisation_each_step(orc, prec, S):
     same = np.mean([set(x.tolist()) == set(y.tolist()) for x, y in zip(a.support.cpu().numpy(), out["support"])])
     print("same supports as the progressive update:", same)
     assert same >= 0.95
+
+
+@pytest.mark.parametrize("M,N,B,S,eps_frac", [(64, 256, 100, 8, 0.0), (100, 300, 77, 10, 0.0), (200, 520, 259, 33, 0.0),
+                                              (31, 47, 5, 31, 0.0), (384, 640, 64, 70, 0.0), (128, 512, 90, 24, 0.1)])
+def test_v0_form(orc, M, N, B, S, eps_frac):
+    """Algorithm v0 (inverse Cholesky factor, D = A^T Q, correlations updated from P = A^T y)
+    against the oracle on ragged shapes; with eps_frac > 0 every signal gets
+    eps_b = eps_frac ||y_b||, so the running ||r||^2 decides the stop. Where S = M the
+    last picks make the support square and ill-conditioned: x = F u through the
+    explicit inverse factor then carries FP32 error up to the kappa^2 bound, counted as
+    unresolved in FP32."""
+    from paper_2407_06434_amd import workloads
+    w = workloads.custom(M, N, B, S, seed=M + 3 * N, k_true=min(S, max(1, M // 4)))
+    eps_per = None
+    if eps_frac > 0:
+        eps_per = (eps_frac * np.linalg.norm(w.Y.astype(np.float64), axis=1)).astype(np.float32)
+        w.eps_per_signal = eps_per
+    print(f"case v0 M={M} N={N} B={B} S={S} eps_frac={eps_frac}", flush=True)
+    out = run_gpu(w, "fp32", v0=True, eps_per=eps_per)
+    rep = parity.check(w, out, orc)
+    print(rep)
+    if S < M:
+        assert rep["passed"] == w.B
+    else:
+        assert rep["passed"] + rep["unresolved_fp32"] == w.B
+
+
+def test_v0_256x1024_full(orc):
+    """Algorithm v0 on the 256 x 1024 workload in full (10,000 signals, S = 32)."""
+    from paper_2407_06434_amd import workloads
+    w = workloads.batched_256x1024()
+    print("case v0 batched_256x1024 B=10000", flush=True)
+    rep = parity.check(w, run_gpu(w, "fp32", dictionary=True, v0=True), orc)
+    print(rep)
+    assert rep["passed"] == w.B
+
+
+def test_v0_1024x4096_prefix(orc):
+    """Algorithm v0 on the benchmark workload (B = 4096, S = 64; D takes 4.3 GB), the first
+    256 signals against the oracle, the rest by the FP64 least-squares invariants."""
+    from paper_2407_06434_amd import workloads
+    w = workloads.bf16_1024x4096()
+    print("case v0 bf16_1024x4096 B=4096", flush=True)
+    out = run_gpu(w, "fp32", dictionary=True, v0=True)
+    assert np.all(out["status"] >> 8 == 64)
+    rep = parity.check(w, out, orc, idx=np.arange(256))
+    print(rep)
+    assert rep["passed"] == 256
+    worst_c, worst_o = ls_invariants(w.A, w.Y, out["support"], out["coef"])
+    print(f"all 4096: worst coefficient error {worst_c:.2e}, worst orthogonality {worst_o:.2e}")
+    assert worst_c <= 1e-4 and worst_o <= 1e-4
 
 
 @pytest.mark.parametrize("M,N,B,S,eps_frac", [(512, 128, 100, 20, 0.0), (300, 300, 64, 40, 0.0),
