@@ -62,6 +62,11 @@ extern "C" {
 #define OMP_PREC_FP32 0 /* A^T R with FP32 inputs and FP32 accumulation */
 #define OMP_PREC_BF16 1 /* A^T R in BF16 with FP32 accumulation; the leading candidates
                            are re-scored in FP32 so that the pick is the FP32 argmax */
+#define OMP_PREC_FP64 2 /* everything in FP64 (the FP32 inputs are exact in FP64): the
+                           paper's Algorithm v0 (see omp_opts_t.v0) with FP64 correlations,
+                           Gram matrix, inverse factor and coefficients; the outputs are the
+                           FP64 results rounded once to FP32. Not with gram_domain = 1,
+                           refactor or gram_on_the_fly; not in omp_solve_multi. */
 
 /* ---- per-signal status bits (status_out) -------------------------------
  * status_out[b] = (k_b << 8) | bits, k_b = number of atoms selected. */

@@ -37,7 +37,7 @@ struct Carve {
 
 struct DictLayout {
   int64_t Mp, Np;
-  size_t nu2, inv_nu, A32, G, A16, aerr, aerr_max, total;
+  size_t nu2, inv_nu, A32, G, A16, aerr, aerr_max, G64, inv_nu64, total;
 };
 
 DictLayout dict_layout(int64_t M, int64_t N, int precision) {
@@ -52,6 +52,8 @@ DictLayout dict_layout(int64_t M, int64_t N, int precision) {
   L.A16 = precision == OMP_PREC_BF16 ? c.take<uint16_t>((size_t)L.Np * L.Mp) : 0;
   L.aerr = c.take<float>(L.Np);
   L.aerr_max = c.take<float>(1);
+  L.G64 = precision == OMP_PREC_FP64 ? c.take<double>((size_t)L.Np * L.Np) : 0;
+  L.inv_nu64 = precision == OMP_PREC_FP64 ? c.take<double>(L.Np) : 0;
   L.total = (c.off + ALIGN - 1) / ALIGN * ALIGN;
   return L;
 }
@@ -62,7 +64,8 @@ struct WorkLayout {
   int ntile;
   int nslice, slice_len;
   int64_t vstride;
-  size_t Yp, R32, R16, part, mask, k, flags, pnorm, pdelta, Sb, epsb, sup, u, xh, V, P, Pk, D, total;
+  size_t Yp, R32, R16, part, mask, k, flags, pnorm, pdelta, Sb, epsb, sup, u, xh, V, P, Pk, D, P64, D64, V64, u64,
+      total;
   int pchunks;
 };
 
@@ -83,8 +86,10 @@ WorkLayout work_layout(int64_t M, int64_t N, int64_t B, int S, int precision, in
   L.R32 = c.take<float>(Bp * L.Mp);
   L.R16 = precision == OMP_PREC_BF16 ? c.take<uint16_t>(Bp * L.Mp) : 0;
   // (the Gram-domain select writes GSLICE keys per signal, twice that with near-tie flagging)
+  // (the Gram-domain select writes GSLICE keys per signal, twice that with near-tie
+  // flagging; v0 two keys, the FP64 form two (score, index) pairs of doubles)
   L.part = c.take<uint64_t>(Bp * (size_t)std::max<int64_t>((int64_t)L.ntile * L.g.keys_per_tile,
-                                                            gram_dom ? GSLICE * (ties ? 2 : 1) : 2));
+                                                            gram_dom ? GSLICE * (ties ? 2 : 1) : 4));
   L.mask = c.take<uint32_t>(Bp * (L.Np / 32));
   L.k = c.take<int32_t>(Bp);
   L.flags = c.take<int32_t>(Bp);
@@ -97,11 +102,16 @@ WorkLayout work_layout(int64_t M, int64_t N, int64_t B, int S, int precision, in
   L.xh = c.take<float>(Bp * Sz);
   L.vstride = round_up((int64_t)(Sz * (Sz + 1) / 2), 4);
   L.V = c.take<float>(Bp * (size_t)L.vstride);
-  const bool proj = gram_dom || v0;  // forms that start from P = A^T y
+  const bool f64 = precision == OMP_PREC_FP64;  // the FP64 form (v0 in FP64)
+  const bool proj = (gram_dom || v0) && !f64;   // FP32 forms that start from P = A^T y
   L.P = proj ? c.take<float>(Bp * (size_t)L.Np) : 0;
   L.pchunks = proj ? project_chunks(L.Bp, L.Np, L.Mp) : 1;
   L.Pk = L.pchunks > 1 ? c.take<float>((size_t)L.pchunks * Bp * (size_t)L.Np) : 0;
-  L.D = v0 ? c.take<float>(Bp * Sz * (size_t)L.Np) : 0;
+  L.D = (v0 && !f64) ? c.take<float>(Bp * Sz * (size_t)L.Np) : 0;
+  L.P64 = f64 ? c.take<double>(Bp * (size_t)L.Np) : 0;
+  L.D64 = f64 ? c.take<double>(Bp * Sz * (size_t)L.Np) : 0;
+  L.V64 = f64 ? c.take<double>(Bp * (size_t)L.vstride) : 0;
+  L.u64 = f64 ? c.take<double>(Bp * Sz) : 0;
   L.total = (c.off + ALIGN - 1) / ALIGN * ALIGN;
   return L;
 }
@@ -236,6 +246,8 @@ DictView dict_view(void *mem, int64_t M, int64_t N, int precision) {
   d.A16 = precision == OMP_PREC_BF16 ? at<uint16_t>(mem, L.A16) : nullptr;
   d.aerr = at<float>(mem, L.aerr);
   d.aerr_max = at<float>(mem, L.aerr_max);
+  d.G64 = precision == OMP_PREC_FP64 ? at<double>(mem, L.G64) : nullptr;
+  d.inv_nu64 = precision == OMP_PREC_FP64 ? at<double>(mem, L.inv_nu64) : nullptr;
   return d;
 }
 
@@ -286,9 +298,14 @@ WorkView work_view(void *mem, int64_t M, int64_t N, int64_t B, int S, int precis
   w.gram_fly = 0;
   w.refactor = 0;
   w.gram_dom = gram_dom ? 1 : 0;
-  w.P = (gram_dom || v0) ? at<float>(mem, L.P) : nullptr;
-  w.v0 = v0 ? 1 : 0;
-  w.D = v0 ? at<float>(mem, L.D) : nullptr;
+  const bool f64 = precision == OMP_PREC_FP64;
+  w.P = L.P ? at<float>(mem, L.P) : nullptr;
+  w.v0 = (v0 || f64) ? 1 : 0;
+  w.D = L.D ? at<float>(mem, L.D) : nullptr;
+  w.P64 = f64 ? at<double>(mem, L.P64) : nullptr;
+  w.D64 = f64 ? at<double>(mem, L.D64) : nullptr;
+  w.V64 = f64 ? at<double>(mem, L.V64) : nullptr;
+  w.u64 = f64 ? at<double>(mem, L.u64) : nullptr;
   w.pchunks = L.pchunks;
   w.Pk = L.pchunks > 1 ? at<float>(mem, L.Pk) : nullptr;
   w.flag_ties = ties ? 1 : 0;
@@ -328,14 +345,15 @@ void omp_opts_default(omp_opts_t *opts) {
 }
 
 size_t omp_dict_size(int64_t M, int64_t N, int32_t precision) {
-  if (!dims_ok(M, N) || (precision != OMP_PREC_FP32 && precision != OMP_PREC_BF16)) return 0;
+  if (!dims_ok(M, N) || (precision != OMP_PREC_FP32 && precision != OMP_PREC_BF16 && precision != OMP_PREC_FP64))
+    return 0;
   return dict_bytes(M, N, precision);
 }
 
 int omp_dict_init(omp_dict_t *dict, const float *A, int64_t M, int64_t N, int64_t lda, int32_t precision,
                   void *mem, size_t bytes, void *stream) {
   if (!dict || !A || !dims_ok(M, N) || lda < M) return OMP_EINVAL;
-  if (precision != OMP_PREC_FP32 && precision != OMP_PREC_BF16) return OMP_EINVAL;
+  if (precision != OMP_PREC_FP32 && precision != OMP_PREC_BF16 && precision != OMP_PREC_FP64) return OMP_EINVAL;
   if (!aligned(A, 4)) return OMP_EINVAL;
   const size_t need = dict_bytes(M, N, precision);
   if (!mem || bytes < need || !aligned(mem, ALIGN)) return OMP_EWORKSPACE;
@@ -344,7 +362,7 @@ int omp_dict_init(omp_dict_t *dict, const float *A, int64_t M, int64_t N, int64_
   hipStream_t st = static_cast<hipStream_t>(stream);
   const DictView d = dict_view(mem, M, N, precision);
   hipError_t e = launch_dict_prep(A, lda, d, st);
-  if (e == hipSuccess) e = launch_gram(d, st);
+  if (e == hipSuccess) e = precision == OMP_PREC_FP64 ? launch_gram64(d, st) : launch_gram(d, st);
   if (e != hipSuccess) return device_error(e);
   dict->magic = DICT_MAGIC;
   dict->precision = precision;
@@ -373,7 +391,7 @@ size_t omp_workspace_size(int64_t M, int64_t N, int64_t B, int32_t S, const omp_
 size_t bomp::solve_bytes(int64_t M, int64_t N, int64_t B, int32_t S, const omp_opts_t *opts) {
   const int prec = opts ? opts->precision : OMP_PREC_FP32;
   if (!dims_ok(M, N) || B < 0 || B > ((int64_t)1 << 26) || S < 1 || S > OMP_MAX_S) return 0;
-  if (prec != OMP_PREC_FP32 && prec != OMP_PREC_BF16) return 0;
+  if (prec != OMP_PREC_FP32 && prec != OMP_PREC_BF16 && prec != OMP_PREC_FP64) return 0;
   const int cfg = opts ? opts->tile_config : 0;
   if (cfg < 0 || cfg > MAX_TILE_CFG) return 0;
   const bool v0 = opts && opts->v0 == 1;
@@ -392,7 +410,7 @@ int solve_impl(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y
   // ---- validation (host only) ----
   if (!opts) return OMP_EINVAL;
   const int prec = opts->precision;
-  if (prec != OMP_PREC_FP32 && prec != OMP_PREC_BF16) return OMP_EINVAL;
+  if (prec != OMP_PREC_FP32 && prec != OMP_PREC_BF16 && prec != OMP_PREC_FP64) return OMP_EINVAL;
   const int cfg = opts->tile_config;
   if (cfg < 0 || cfg > MAX_TILE_CFG) return OMP_EINVAL;
   if (opts->gram_on_the_fly != 0 && opts->gram_on_the_fly != 1) return OMP_EINVAL;
@@ -401,8 +419,9 @@ int solve_impl(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y
   if (opts->gram_domain == 1 && prec != OMP_PREC_FP32) return OMP_EINVAL;
   if (opts->flag_near_ties != 0 && opts->flag_near_ties != 1) return OMP_EINVAL;
   if (opts->v0 != 0 && opts->v0 != 1) return OMP_EINVAL;
-  const bool v0 = opts->v0 == 1;
-  if (v0 && (prec != OMP_PREC_FP32 || opts->gram_domain == 1 || opts->gram_on_the_fly || opts->refactor))
+  const bool f64 = prec == OMP_PREC_FP64;  // the FP64 form runs Algorithm v0 in FP64
+  const bool v0 = opts->v0 == 1 || f64;
+  if (v0 && (prec == OMP_PREC_BF16 || opts->gram_domain == 1 || opts->gram_on_the_fly || opts->refactor))
     return OMP_EINVAL;
   const bool gdom = !v0 && gram_domain_form(opts->gram_domain, prec, M, N);
   const bool ties = opts->flag_near_ties == 1;
@@ -439,7 +458,8 @@ int solve_impl(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y
       void *dmem = static_cast<char *>(workspace) + wneed;
       d = dict_view(dmem, M, N, prec);
       e = timer.run(OMP_PHASE_DICT, [&] { return launch_dict_prep(A, lda, d, cs); });
-      if (e == hipSuccess) e = timer.run(OMP_PHASE_DICT, [&] { return launch_gram(d, cs); });
+      if (e == hipSuccess)
+        e = timer.run(OMP_PHASE_DICT, [&] { return f64 ? launch_gram64(d, cs) : launch_gram(d, cs); });
       if (e != hipSuccess) return e;
     }
     WorkView w = work_view(workspace, M, N, B, S, prec, cfg, gdom, ties, v0);
@@ -448,13 +468,22 @@ int solve_impl(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y
     e = timer.run(OMP_PHASE_INIT, [&] {
       return launch_init(Y, ldy, opts->S_per_signal, opts->eps_per_signal, eps, d, w, prec, cs);
     });
-    if ((gdom || v0) && e == hipSuccess) e = timer.run(OMP_PHASE_INIT, [&] { return launch_project(d, w, cs); });
-    if (v0) {
+    if (f64) {
+      // FP64 form: Algorithm v0 in FP64
+      if (e == hipSuccess) e = timer.run(OMP_PHASE_INIT, [&] { return launch_project64(d, w, cs); });
+      if (e == hipSuccess) e = timer.run(OMP_PHASE_INIT, [&] { return launch_v0_first64(d, w, cs); });
+      for (int it = 0; it < S && e == hipSuccess; ++it)
+        e = timer.run(OMP_PHASE_UPDATE, [&] { return launch_v0_step64(d, w, cs); });
+      if (e == hipSuccess) e = timer.run(OMP_PHASE_OUTPUT, [&] { return launch_v0_coef64(w, cs); });
+    } else if (v0) {
       // Algorithm v0: one kernel per step, the coefficients x = F u at the end
+      if (e == hipSuccess) e = timer.run(OMP_PHASE_INIT, [&] { return launch_project(d, w, cs); });
       if (e == hipSuccess) e = timer.run(OMP_PHASE_INIT, [&] { return launch_v0_first(d, w, cs); });
       for (int it = 0; it < S && e == hipSuccess; ++it)
         e = timer.run(OMP_PHASE_UPDATE, [&] { return launch_v0_step(d, w, cs); });
       if (e == hipSuccess) e = timer.run(OMP_PHASE_OUTPUT, [&] { return launch_v0_coef(w, cs); });
+    } else if (gdom && e == hipSuccess) {
+      e = timer.run(OMP_PHASE_INIT, [&] { return launch_project(d, w, cs); });
     }
     for (int it = 0; it < S && e == hipSuccess && !v0; ++it) {
       if (gdom) {

@@ -53,6 +53,8 @@ struct DictView {
   uint16_t *A16;   // [Np][Mp] BF16 (round to nearest even) copy of A, or nullptr
   float *aerr;     // [Np]   ||a_n - bf16(a_n)|| / ||a_n|| (BF16 form), 0 for zero atoms
   float *aerr_max; // [1]    max_n aerr[n] (BF16 form)
+  double *G64;     // [Np][Np] Gram matrix in FP64 (FP64 form), or nullptr
+  double *inv_nu64;// [Np]   1/||a_n|| in FP64 (FP64 form), or nullptr
 };
 
 size_t dict_bytes(int64_t M, int64_t N, int precision);
@@ -96,6 +98,11 @@ struct WorkView {
   int flag_ties;  // 1: near-tie flagging (the select stages keep the second best atom too)
   int v0;         // 1: Algorithm v0 (inverse Cholesky factor F in V, D = A^T Q, correlations in P)
   float *D;       // [Bp][S][Np] v0: D's columns d_j = A^T q_j, each Np long (else nullptr)
+  // FP64 form (Algorithm v0 in FP64; else nullptr)
+  double *P64;    // [Bp][Np] correlations c = A^T r
+  double *D64;    // [Bp][S][Np] columns of D
+  double *V64;    // [Bp][vstride] inverse factor F, packed by columns
+  double *u64;    // [Bp][S] u = Q^T y
 };
 
 // Gram-domain select: the atoms are split into this many contiguous slices, one
@@ -232,6 +239,13 @@ hipError_t prepare_corr(const DictView &d, const WorkView &w, int precision);
 hipError_t launch_v0_first(const DictView &d, const WorkView &w, hipStream_t st);
 hipError_t launch_v0_step(const DictView &d, const WorkView &w, hipStream_t st);
 hipError_t launch_v0_coef(const WorkView &w, hipStream_t st);
+// FP64 form: G64 = A32 A32^T and P64 = Yp A32^T (exact products, FP64 sums), then
+// the v0 kernels in FP64.
+hipError_t launch_gram64(const DictView &d, hipStream_t st);
+hipError_t launch_project64(const DictView &d, const WorkView &w, hipStream_t st);
+hipError_t launch_v0_first64(const DictView &d, const WorkView &w, hipStream_t st);
+hipError_t launch_v0_step64(const DictView &d, const WorkView &w, hipStream_t st);
+hipError_t launch_v0_coef64(const WorkView &w, hipStream_t st);
 
 // Outputs: dense X, support, coefficients, status, residual norm.
 hipError_t launch_finalize(const DictView &d, const WorkView &w, float *X_out,

@@ -540,6 +540,13 @@ __global__ __launch_bounds__(64) void k_dict_prep(const float *__restrict__ A, i
   }
 }
 
+// 1/||a_n|| in FP64 from the FP64 squared norms (0 for zero and padding atoms).
+__global__ __launch_bounds__(256) void k_inv_nu64(const double *__restrict__ nu2, int64_t Np,
+                                                  double *__restrict__ inv) {
+  const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (n < Np) inv[n] = nu2[n] > 0.0 ? 1.0 / sqrt(nu2[n]) : 0.0;
+}
+
 // max_n aerr[n] over the dictionary (one block).
 __global__ __launch_bounds__(1024) void k_dict_aerr_max(const float *__restrict__ aerr, int64_t Np,
                                                         float *__restrict__ out) {
@@ -1447,6 +1454,258 @@ __global__ __launch_bounds__(64) void k_v0_coef(WorkView w) {
 }
 
 // ---------------------------------------------------------------------------
+// FP64 form (OMP_PREC_FP64): Algorithm v0 of Section 2.3 with every quantity in
+// FP64 -- the projection P = A^T y and the Gram matrix (exact products of the FP32
+// inputs, FP64 sums), the correlations c, the columns of D, the inverse factor F,
+// u and x. The paper notes that double precision halves the speed of its v0 code;
+// this form is the library's accurate mode (picks decided by FP64 scores, no FP32
+// cancellation in the solves).
+// ---------------------------------------------------------------------------
+
+// C[r][c] = sum_m X[r][m] Z[c][m] in FP64 from FP32 operands (rows of X and Z are Mp
+// floats, Mp a multiple of 32); 64 x 64 tiles, 256 threads, 4 x 4 outputs each.
+constexpr int G64_T = 64, G64_K = 32;
+__global__ __launch_bounds__(256) void k_gemm64(const float *__restrict__ X, const float *__restrict__ Z, int64_t Mp,
+                                                int ntc, double *__restrict__ C, int64_t ldc) {
+  __shared__ double Xs[G64_K][G64_T + 1];
+  __shared__ double Zs[G64_K][G64_T + 1];
+  const int tr = blockIdx.x / ntc, tc = blockIdx.x % ntc;
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const float *Xb = X + (int64_t)tr * G64_T * Mp;
+  const float *Zb = Z + (int64_t)tc * G64_T * Mp;
+  double acc[4][4] = {};
+  for (int64_t k0 = 0; k0 < Mp; k0 += G64_K) {
+    // 64 rows x 32 floats per operand: 512 float4, two per thread
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int f = tid + 256 * q;
+      const int r = f >> 3, c4 = f & 7;
+      const float4 xv = *reinterpret_cast<const float4 *>(Xb + (int64_t)r * Mp + k0 + 4 * c4);
+      const float4 zv = *reinterpret_cast<const float4 *>(Zb + (int64_t)r * Mp + k0 + 4 * c4);
+      Xs[4 * c4 + 0][r] = xv.x; Xs[4 * c4 + 1][r] = xv.y; Xs[4 * c4 + 2][r] = xv.z; Xs[4 * c4 + 3][r] = xv.w;
+      Zs[4 * c4 + 0][r] = zv.x; Zs[4 * c4 + 1][r] = zv.y; Zs[4 * c4 + 2][r] = zv.z; Zs[4 * c4 + 3][r] = zv.w;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int k = 0; k < G64_K; ++k) {
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = Xs[k][ty * 4 + i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Zs[k][tx * 4 + j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      C[((int64_t)tr * G64_T + ty * 4 + i) * ldc + (int64_t)tc * G64_T + tx * 4 + j] = acc[i][j];
+}
+
+// A candidate atom in FP64: score |c_n| / ||a_n|| (negative: none) and its index;
+// the larger score wins, ties to the lower index.
+struct Pick64 {
+  double s;
+  int n;
+};
+__device__ inline bool pick_better(double s, int n, double bs, int bn) { return s > bs || (s == bs && n < bn); }
+
+// Merge the top two (b1 > b2) of another set of distinct atoms into (a1 > a2).
+__device__ inline void pick_merge(Pick64 &a1, Pick64 &a2, const Pick64 &b1, const Pick64 &b2) {
+  if (pick_better(b1.s, b1.n, a1.s, a1.n)) {
+    a2 = pick_better(a1.s, a1.n, b2.s, b2.n) ? a1 : b2;
+    a1 = b1;
+  } else if (pick_better(b1.s, b1.n, a2.s, a2.n)) {
+    a2 = b1;
+  }
+}
+
+// Block-wide best and second best of the threads' (best, second) pairs, stored as the
+// signal's two (score, index) pairs of doubles in w.part. red: LDS [2 V0_THREADS / 64].
+__device__ inline void v0_store_pick64(const WorkView &w, int64_t b, Pick64 p1, Pick64 p2, Pick64 *red) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const Pick64 q1{__shfl_xor(p1.s, off), __shfl_xor(p1.n, off)};
+    const Pick64 q2{__shfl_xor(p2.s, off), __shfl_xor(p2.n, off)};
+    pick_merge(p1, p2, q1, q2);
+  }
+  const int tid = threadIdx.x;
+  if ((tid & 63) == 0) {
+    red[2 * (tid >> 6)] = p1;
+    red[2 * (tid >> 6) + 1] = p2;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    Pick64 b1 = red[0], b2 = red[1];
+    for (int i = 1; i < V0_THREADS / 64; ++i) pick_merge(b1, b2, red[2 * i], red[2 * i + 1]);
+    double *pk = reinterpret_cast<double *>(w.part) + 4 * b;
+    pk[0] = b1.s;
+    pk[1] = (double)b1.n;
+    pk[2] = b2.s;
+    pk[3] = (double)b2.n;
+  }
+  __syncthreads();
+}
+
+__device__ inline void pick_insert(double s, int n, Pick64 &p1, Pick64 &p2) {
+  if (pick_better(s, n, p1.s, p1.n)) {
+    p2 = p1;
+    p1 = Pick64{s, n};
+  } else if (pick_better(s, n, p2.s, p2.n)) {
+    p2 = Pick64{s, n};
+  }
+}
+
+__global__ __launch_bounds__(V0_THREADS) void k_v0_first64(DictView d, WorkView w) {
+  __shared__ Pick64 red[2 * V0_THREADS / 64];
+  const int64_t b = blockIdx.x;
+  const double *c = w.P64 + b * d.Np;
+  Pick64 p1{-1.0, 0x7fffffff}, p2{-1.0, 0x7fffffff};
+  for (int64_t n = threadIdx.x; n < d.Np; n += V0_THREADS) {
+    const double iv = d.inv_nu64[n];
+    if (iv > 0.0) pick_insert(fabs(c[n]) * iv, (int)n, p1, p2);
+  }
+  v0_store_pick64(w, b, p1, p2, red);
+}
+
+// One FP64 v0 step per live signal (the FP32 step's arithmetic in FP64).
+__global__ __launch_bounds__(V0_THREADS) void k_v0_step64(DictView d, WorkView w) {
+  extern __shared__ uint32_t v0s[];
+  __shared__ Pick64 red[2 * V0_THREADS / 64];
+  __shared__ double part4[V0_THREADS / 64];
+  const int64_t b = blockIdx.x;
+  const int tid = threadIdx.x;
+  int fl = w.flags[b];
+  if (fl & FLAG_DONE) return;
+  const int k = w.k[b];
+  const int S = w.S;
+  const int64_t Np = d.Np, mwords = Np / 32;
+  double *zs = reinterpret_cast<double *>(v0s);              // [S]
+  uint32_t *mk = v0s + 2 * S;                                 // [Np / 32]
+  const double rn = sqrt(w.pnorm[b * NSLICE_MAX]);
+  const float eps_b = w.epsb[b];
+  const double *pk = reinterpret_cast<const double *>(w.part) + 4 * b;
+  const double s1 = pk[0], s2 = pk[2];
+  if (rn <= (double)eps_b || !(s1 >= 0.0)) {
+    if (tid == 0) w.flags[b] = fl | FLAG_DONE | (rn <= (double)eps_b ? 0 : OMP_SIG_EXHAUSTED);
+    return;
+  }
+  const int nstar = (int)pk[1];
+  if (w.flag_ties && s2 >= 0.0 && s2 >= (1.0 - TIE_REL) * s1) fl |= OMP_SIG_NEARTIE;
+  double *Db = w.D64 + b * (int64_t)S * Np;
+  double *c = w.P64 + b * Np;
+  for (int j = tid; j < k; j += V0_THREADS) zs[j] = Db[(int64_t)j * Np + nstar];
+  for (int64_t t = tid; t < mwords; t += V0_THREADS) mk[t] = w.mask[b * mwords + t];
+  __syncthreads();
+  if (tid < 64) {
+    double zz = 0.0;
+    for (int j = tid; j < k; j += 64) zz += zs[j] * zs[j];
+    zz = wave_sum(zz);
+    if (tid == 0) part4[0] = zz;
+  }
+  __syncthreads();
+  const double nu2 = d.nu2[nstar];
+  const double d2 = nu2 - part4[0];
+  if (!(d2 > DEP_TOL2 * nu2)) {
+    if (tid == 0) w.flags[b] = fl | FLAG_DONE | OMP_SIG_DEPENDENT;
+    return;
+  }
+  const double g = 1.0 / sqrt(d2);
+  const double uk = g * c[nstar];
+  const double *Fb = w.V64 + b * w.vstride;
+  double *Fk = w.V64 + b * w.vstride + (int64_t)k * (k + 1) / 2;
+  for (int i = tid; i <= k; i += V0_THREADS) {
+    if (i == k) {
+      Fk[k] = g;
+    } else {
+      double acc = 0.0;
+      for (int j = i; j < k; ++j) acc += Fb[(int64_t)j * (j + 1) / 2 + i] * zs[j];
+      Fk[i] = -g * acc;
+    }
+  }
+  const double *Gr = d.G64 + (int64_t)nstar * Np;
+  double *Dk = Db + (int64_t)k * Np;
+  Pick64 p1{-1.0, 0x7fffffff}, p2{-1.0, 0x7fffffff};
+  for (int64_t n = tid; n < Np; n += V0_THREADS) {
+    double a = Gr[n];
+    int j = 0;
+    for (; j + 4 <= k; j += 4) {
+      const double e0 = Db[(int64_t)j * Np + n], e1 = Db[(int64_t)(j + 1) * Np + n];
+      const double e2 = Db[(int64_t)(j + 2) * Np + n], e3 = Db[(int64_t)(j + 3) * Np + n];
+      a = fma(-zs[j], e0, a);
+      a = fma(-zs[j + 1], e1, a);
+      a = fma(-zs[j + 2], e2, a);
+      a = fma(-zs[j + 3], e3, a);
+    }
+    for (; j < k; ++j) a = fma(-zs[j], Db[(int64_t)j * Np + n], a);
+    a *= g;
+    Dk[n] = a;
+    const bool taken = n == nstar || ((mk[n >> 5] >> (n & 31)) & 1u);
+    const double cn = taken ? 0.0 : fma(-uk, a, c[n]);
+    c[n] = cn;
+    const double iv = d.inv_nu64[n];
+    if (!taken && iv > 0.0) pick_insert(fabs(cn) * iv, (int)n, p1, p2);
+  }
+  v0_store_pick64(w, b, p1, p2, red);
+  const int K = k + 1;
+  double r2 = rn * rn - uk * uk;
+  const double y2 = w.pdelta[b * NSLICE_MAX];
+  const double floor2 = 64.0 * (double)(K + 1) * (1.0 / 9007199254740992.0) * y2;
+  const double e2 = (double)eps_b * (double)eps_b;
+  if (!(r2 > floor2) || fabs(r2 - e2) <= floor2) {
+    const double *Fu = w.V64 + b * w.vstride;
+    for (int i = tid; i < K; i += V0_THREADS) {
+      double acc = 0.0;
+      for (int j = i; j < K; ++j) acc += Fu[(int64_t)j * (j + 1) / 2 + i] * (j == k ? uk : w.u64[b * S + j]);
+      zs[i] = acc;
+    }
+    __syncthreads();
+    const float *yb = w.Yp + b * w.Mp;
+    double acc = 0.0;
+    for (int64_t m = tid; m < d.M; m += V0_THREADS) {
+      double rm = (double)yb[m];
+      for (int j = 0; j < K; ++j) {
+        const int sj = j == k ? nstar : w.sup[b * S + j];
+        rm -= zs[j] * (double)d.A32[(int64_t)sj * d.Mp + m];
+      }
+      acc += rm * rm;
+    }
+    acc = wave_sum(acc);
+    if ((tid & 63) == 0) part4[tid >> 6] = acc;
+    __syncthreads();
+    r2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < V0_THREADS / 64; ++i) r2 += part4[i];
+  }
+  if (tid == 0) {
+    w.pnorm[b * NSLICE_MAX] = r2;
+    w.sup[b * S + k] = nstar;
+    w.u64[b * S + k] = uk;
+    w.mask[b * mwords + nstar / 32] = mk[nstar / 32] | (1u << (nstar & 31));
+    w.k[b] = K;
+    w.flags[b] = fl | (K >= w.Sb[b] ? FLAG_DONE : 0);
+  }
+}
+
+// x = F u in FP64, rounded once to the FP32 coefficient outputs.
+__global__ __launch_bounds__(64) void k_v0_coef64(WorkView w) {
+  const int64_t b = blockIdx.x;
+  const int k = w.k[b];
+  const int S = w.S;
+  const double *F = w.V64 + b * w.vstride;
+  for (int i = threadIdx.x; i < k; i += 64) {
+    double acc = 0.0;
+    for (int j = i; j < k; ++j) acc += F[(int64_t)j * (j + 1) / 2 + i] * w.u64[b * S + j];
+    w.xh[b * S + i] = (float)acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Residual: r = y - sum_j x_j a_{s_j} on one slice of M for every signal whose
 // coefficients changed in this iteration, and that slice's ||r||^2 (FP64).
 // Block of 256 lanes; an item (signal, slice) takes LP lanes, 64 / LP items per
@@ -1734,6 +1993,45 @@ hipError_t launch_v0_step(const DictView &d, const WorkView &w, hipStream_t st) 
 hipError_t launch_v0_coef(const WorkView &w, hipStream_t st) {
   if (w.B == 0) return hipSuccess;
   hipLaunchKernelGGL(k_v0_coef, dim3((unsigned)w.B), dim3(64), 0, st, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram64(const DictView &d, hipStream_t st) {
+  if (!d.G64 || !d.inv_nu64 || d.Np % G64_T || d.Mp % G64_K) return hipErrorInvalidValue;
+  const int nt = (int)(d.Np / G64_T);
+  hipLaunchKernelGGL(k_gemm64, dim3((unsigned)(nt * nt)), dim3(256), 0, st, d.A32, d.A32, d.Mp, nt, d.G64, d.Np);
+  hipLaunchKernelGGL(k_inv_nu64, dim3((unsigned)((d.Np + 255) / 256)), dim3(256), 0, st, d.nu2, d.Np, d.inv_nu64);
+  return hipGetLastError();
+}
+
+hipError_t launch_project64(const DictView &d, const WorkView &w, hipStream_t st) {
+  if (!w.P64 || w.Bp % G64_T || d.Np % G64_T || w.Mp != d.Mp || d.Mp % G64_K || w.Np != d.Np)
+    return hipErrorInvalidValue;
+  const int ntr = (int)(w.Bp / G64_T), ntc = (int)(d.Np / G64_T);
+  hipLaunchKernelGGL(k_gemm64, dim3((unsigned)(ntr * ntc)), dim3(256), 0, st, w.Yp, d.A32, d.Mp, ntc, w.P64, d.Np);
+  return hipGetLastError();
+}
+
+hipError_t launch_v0_first64(const DictView &d, const WorkView &w, hipStream_t st) {
+  if (w.B == 0) return hipSuccess;
+  if (!w.P64 || !d.inv_nu64 || w.Np != d.Np) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_v0_first64, dim3((unsigned)w.B), dim3(V0_THREADS), 0, st, d, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_v0_step64(const DictView &d, const WorkView &w, hipStream_t st) {
+  if (w.B == 0) return hipSuccess;
+  if (!w.P64 || !w.D64 || !w.V64 || !w.u64 || !d.G64 || !d.inv_nu64 || w.Np != d.Np) return hipErrorInvalidValue;
+  const size_t lds = (size_t)(2 * w.S + d.Np / 32) * 4;
+  hipError_t e = allow_lds(k_v0_step64, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_v0_step64, dim3((unsigned)w.B), dim3(V0_THREADS), lds, st, d, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_v0_coef64(const WorkView &w, hipStream_t st) {
+  if (w.B == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_v0_coef64, dim3((unsigned)w.B), dim3(64), 0, st, w);
   return hipGetLastError();
 }
 
