@@ -19,8 +19,10 @@ early stop (synthetic stand-in for the paper's unnamed application data).
 
 The same line also carries the measurements beside the benchmark step: plain
 FP32, the paper's ablations on these kernels (batching, Gram precomputation,
-progressive Cholesky), the Gram-domain form on the tall face-recognition shape,
-uneven batches, the learned proposal and the oracle on the host (CPU baseline);
+progressive Cholesky; inverse Cholesky against re-factorisation), the paper's
+Algorithm v0 and the FP64 form, the Gram-domain form on the tall
+face-recognition shape, uneven batches, the learned proposal and the oracle on
+the host (CPU baseline, with every signal it solved checked against the GPU);
 --no-* flags skip them. Two other modes print their own JSON line instead:
 --sweep (the paper's parameter sweep as a speed map), --sweep-tall (every form on
 square and tall dictionaries), --apps (the shapes of its application table) and
@@ -418,6 +420,70 @@ def run_gram_domain(steps=3, warmup=1):
     return line
 
 
+def v0_bytes_per_launch(N, S, B, elem):
+    """Algorithmic bytes of one v0 step launch, averaged over the S steps: per signal at
+    support size k, the k columns of D read and the new one written ((k + 1) N), the Gram
+    row G[n*, :] (N) and the correlations read and written (2 N), elem bytes each."""
+    Np = -(-N // 256) * 256
+    return B * elem * Np * sum(k + 4 for k in range(S)) / S
+
+
+def run_v0_forms(w_main, steps=3, warmup=1):
+    """Algorithm v0 of the paper (FP32, opts.v0) and the FP64 form (v0 in FP64) beside
+    the residual-vector FP32 form and its re-factorising variant (ablation A3 of the
+    paper: inverse Cholesky against re-factorisation), on the benchmark workload and on
+    the 256 x 1024 workload. Graph-replayed calls; supports compared with the FP32 form;
+    one more direct call per form gives the v0 step kernel's launch time."""
+    import torch
+    from paper_2407_06434_amd import omp, workloads
+    dev = torch.device("cuda:0")
+    out_all = {}
+    for w in (w_main, workloads.batched_256x1024()):
+        A = torch.from_numpy(w.A).to(dev)
+        Y = torch.from_numpy(w.Y).to(dev)
+        res = {}
+        for name, prec, flags in (("fp32", "fp32", {}), ("fp32_refactor", "fp32", {"refactor": True}),
+                                  ("v0_fp32", "fp32", {"v0": True}), ("fp64", "fp64", {})):
+            d = omp.Dictionary(A, prec)
+            out = None
+            for _ in range(warmup):
+                out = omp.solve(A, Y, w.S, w.eps, precision=prec, dictionary=d, out=out, dense=False, **flags)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                out = omp.solve(A, Y, w.S, w.eps, precision=prec, dictionary=d, out=out, dense=False, **flags)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            r = dict(value=round(w.B / dt, 1), ms_per_call=round(1e3 * dt, 3), support=out.support.cpu().numpy())
+            if name in ("v0_fp32", "fp64"):
+                tim = {}
+                omp.solve(A, Y, w.S, w.eps, precision=prec, dictionary=d, dense=False, timing=tim, **flags)
+                ms, n = tim["update"]
+                avg = ms / max(n, 1)
+                byt = v0_bytes_per_launch(w.N, w.S, w.B, 8 if prec == "fp64" else 4)
+                r["k_v0_step"] = dict(bound="hbm", avg_launch_ms=round(avg, 5), launches=n,
+                                      algorithmic_per_launch=float(f"{byt:.5e}"),
+                                      achieved_GBps=round(byt / (avg * 1e-3) / 1e9, 1),
+                                      frac=round(byt / (avg * 1e-3) / 1e9 / PEAK["hbm"], 4))
+                r["projection_and_first_pick_ms"] = round(tim["init"][0], 4)
+            res[name] = r
+            del d
+            torch.cuda.empty_cache()
+        ref = res["fp32"]["support"]
+        line = {}
+        for name, r in res.items():
+            same = sum(set(a.tolist()) == set(b.tolist()) for a, b in zip(r.pop("support"), ref))
+            line[name] = dict(r, same_supports_as_fp32=f"{same}/{w.B}")
+        line["v0_speedup_vs_fp32"] = round(line["v0_fp32"]["value"] / line["fp32"]["value"], 3)
+        line["fp64_speed_vs_fp32"] = round(line["fp64"]["value"] / line["fp32"]["value"], 3)
+        line["fp64_speed_vs_v0_fp32"] = round(line["fp64"]["value"] / line["v0_fp32"]["value"], 3)
+        line["ablation_inverse_cholesky"] = {
+            "v0_fp32": line["v0_fp32"]["value"], "refactorised_each_step_fp32": line["fp32_refactor"]["value"],
+            "speedup": round(line["v0_fp32"]["value"] / line["fp32_refactor"]["value"], 2)}
+        out_all[f"{w.name}_{w.M}x{w.N}_S{w.S}_B{w.B}"] = line
+    return out_all
+
+
 # The paper's realistic-application shapes (Section 4.2) and its v0 GPU figures
 # there (another GPU, precision unstated): context, not a ratio taken here.
 APPS = (("image_patches_256x1024", 256, 1024, 32, 5000, 183904.0),
@@ -613,6 +679,8 @@ def main():
                     help="run only the Gram-domain measurement on the face-recognition shape and print it")
     ap.add_argument("--no-gram-domain", action="store_true",
                     help="skip the Gram-domain measurement on the tall face-recognition shape")
+    ap.add_argument("--no-v0", action="store_true",
+                    help="skip Algorithm v0 (FP32) and the FP64 form on the benchmark and 256x1024 workloads")
     ap.add_argument("--no-ablations", action="store_true",
                     help="skip the ablation runs (per-signal loop, Gram rows from atoms, re-factorisation)")
     ap.add_argument("--learned-train", type=int, default=262144, help="training signals for the learned proposal")
@@ -728,6 +796,10 @@ def main():
             }
             log(f"{key}: {line[key]}")
 
+    if not args.no_v0:
+        v0 = run_v0_forms(w)
+        line["v0_and_fp64"] = v0
+        log(f"v0 and fp64 forms: {v0}")
     if not args.no_gram_domain:
         gd = run_gram_domain()
         line["gram_domain"] = gd
