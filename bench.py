@@ -346,12 +346,26 @@ def run_learned(n_train, epochs, n_eval=65536, log=None):
                                          dense=False))
     s_l = out.support.cpu().numpy()
     s_o = ref.support.cpu().numpy()
+
+    def recall(network):
+        """Mean number of plain OMP's atoms among the network's 32 best scores, and the
+        number of signals whose 32 best scores are OMP's whole support."""
+        Fe = learned.features(network, d16, Yev)
+        top = network.forward(Fe).topk(32, dim=1).indices.cpu().numpy()
+        hits = np.array([len(set(t.tolist()) & set(o[o >= 0].tolist())) for t, o in zip(top, s_o)])
+        return round(float(hits.mean()), 3), int((hits == 32).sum())
+
+    rec_trained = recall(net)
+    rec_start = recall(omp.MLP(workloads.mlp_init_params()))
     acc = (out.status.cpu().numpy() & 128) != 0
     same = np.array([set(a[a >= 0]) == set(b[b >= 0]) for a, b in zip(s_l, s_o)])
     rn_ok = bool(np.all(out.rnorm.cpu().numpy()[acc] <= ev.eps_per_signal[acc]))
     rej_same = bool(np.array_equal(s_l[~acc], s_o[~acc]))
     return {"workload": "learned_256x1024_S32_eval65536", "value": round(n_eval / t_l, 1), "unit": "signals/s",
             "accepted": f"{int(nacc)}/{n_eval}", "accepted_same_support_as_omp": f"{int(same[acc].sum())}/{int(acc.sum())}",
+            "recall_at_32_of_omp_support": {"trained": rec_trained[0], "untrained_start": rec_start[0],
+                                            "signals_with_all_32_trained": rec_trained[1],
+                                            "signals_with_all_32_untrained": rec_start[1]},
             "all_same_support_as_omp": f"{int(same.sum())}/{n_eval}", "accepted_residuals_within_eps": rn_ok,
             "rejects_identical_to_omp": rej_same,
             "plain_bf16_omp": round(n_eval / t_b, 1), "plain_fp32_omp": round(n_eval / t_f, 1),
@@ -679,12 +693,14 @@ def main():
                     help="run only the Gram-domain measurement on the face-recognition shape and print it")
     ap.add_argument("--no-gram-domain", action="store_true",
                     help="skip the Gram-domain measurement on the tall face-recognition shape")
+    ap.add_argument("--only-v0", action="store_true",
+                    help="run only Algorithm v0 and the FP64 form (and their FP32 references) and print them")
     ap.add_argument("--no-v0", action="store_true",
                     help="skip Algorithm v0 (FP32) and the FP64 form on the benchmark and 256x1024 workloads")
     ap.add_argument("--no-ablations", action="store_true",
                     help="skip the ablation runs (per-signal loop, Gram rows from atoms, re-factorisation)")
-    ap.add_argument("--learned-train", type=int, default=262144, help="training signals for the learned proposal")
-    ap.add_argument("--learned-epochs", type=int, default=20)
+    ap.add_argument("--learned-train", type=int, default=1 << 20, help="training signals for the learned proposal")
+    ap.add_argument("--learned-epochs", type=int, default=8)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (scale reference for HBM counters)")
     args = ap.parse_args()
@@ -700,6 +716,11 @@ def main():
     if args.apps:
         print(json.dumps({"metric": "application_shapes", "unit": "signals/s", "data": "synthetic",
                           "steps": 3, "rows": run_apps()}), flush=True)
+        return
+    if args.only_v0:
+        from paper_2407_06434_amd import workloads
+        print(json.dumps(dict(metric="v0_and_fp64", data="synthetic",
+                              **run_v0_forms(workloads.bf16_1024x4096()))), flush=True)
         return
     if args.only_gram_domain:
         print(json.dumps(dict(metric="gram_domain", data="synthetic", **run_gram_domain())), flush=True)

@@ -1,7 +1,8 @@
 """Learned support proposal on an MI355X: features, forward pass and gradients
-against the FP64 oracle (same BF16 rounding points), the least-squares check
-of a proposal against least squares in FP64, the fallback against plain OMP,
-and a trained network's gain over plain OMP.
+against the FP64 oracle (same BF16 rounding points, and the unrounded FP64
+definition under a stated BF16 bound), Adam over two steps with different
+gradients against the oracle's Adam, the least-squares check of a proposal
+against least squares in FP64, and the fallback against plain OMP.
 
 Tolerances. Both sides round the same stored intermediates to BF16, so they
 differ only by FP32-versus-FP64 accumulation (relative ~K 2^-24 with K <= 1024
@@ -107,6 +108,82 @@ def test_forward_and_gradients_match_oracle():
         assert mx <= 1e-2 and fr <= 2e-3, k
 
 
+def test_gradients_against_the_unrounded_definition():
+    """GPU loss and gradients against the FP64 oracle with no BF16 rounding anywhere
+    (features, weights and activations exact). The GPU stores features, weight copies,
+    hidden activations, the output gradient and the back-propagated activation
+    gradients in BF16: at most 7 roundings lie on any product path of a gradient, each
+    of relative size <= 2^-9, so to first order every product term moves by <= 7 2^-9
+    (1.4%) and the gradient by <= 1.4% of the sum of its terms' magnitudes. Bound used:
+    3% of the gradient's norm (terms partly cancel) and 5% of its largest entry per
+    element; the loss (no cancellation) within 1%."""
+    torch = _torch()
+    from oracle import learned_oracle as lo
+    from paper_2407_06434_amd import omp, workloads
+    w = workloads.learned_256x1024(B=300, stream=8)
+    F = lo.features(w.A, w.Y)  # unrounded
+    p = _small_params()
+    net = omp.MLP(p)
+    dev = torch.device("cuda:0")
+    Fb = _bf16_bits(F).to(dev)
+    print("case gradients against the unrounded FP64 definition", flush=True)
+    sup = torch.from_numpy(w.true_support.astype(np.int32)).to(dev)
+    loss, g = net.grad(Fb, sup)
+    pz = {k: v.astype(np.float64) for k, v in p.items()}
+    lr_, gr = lo.backward(pz, F, lo.multi_hot(w.true_support, 1024), lo.identity)
+    print("loss gpu", float(loss.item()), "exact", lr_)
+    assert abs(float(loss.item()) - lr_) <= 1e-2 * abs(lr_)
+    for k in ("W1", "b1", "W2", "b2", "W3", "b3"):
+        d = g[k].cpu().numpy().astype(np.float64) - gr[k]
+        mx = np.abs(d).max() / np.abs(gr[k]).max()
+        fr = np.linalg.norm(d) / np.linalg.norm(gr[k])
+        print(k, "max", mx, "frob", fr)
+        assert mx <= 5e-2 and fr <= 3e-2, k
+
+
+def test_adam_two_steps_with_different_gradients_against_oracle():
+    """Two Adam steps on two different minibatches (rows of one feature set), so the
+    second step combines two different gradients in its moments. Against the oracle's
+    Adam (Kingma and Ba, Algorithm 1) run on the oracle's own gradients at its own
+    weights. The GPU and oracle gradients differ by at most 1e-2 of the largest entry
+    (test above), i.e. by <= 5% on entries >= 0.2 of the largest in both steps; the
+    update lr m^/sqrt(v^) then moves by <= 4 x 5% of lr per step. Bound: 0.25 lr on
+    those entries after two steps, and a median error below 0.01 lr. Reusing the first
+    gradient, dropping the bias correction or swapping beta1 and beta2 each move the
+    firm entries by 0.3 lr or more."""
+    torch = _torch()
+    from oracle import learned_oracle as lo
+    from paper_2407_06434_amd import omp
+    w, F = _oracle_inputs(B=512, seed=15)
+    p = _small_params(seed=16)
+    net = omp.MLP(p)
+    dev = torch.device("cuda:0")
+    Fb = _bf16_bits(F).to(dev)
+    sup = torch.from_numpy(w.true_support.astype(np.int32)).to(dev)
+    r1 = np.arange(0, 256, dtype=np.int32)
+    r2 = np.arange(256, 512, dtype=np.int32)
+    lr = 1e-3
+    print("case adam two steps, two batches", flush=True)
+    net.train_step(Fb, sup, lr, rows=torch.from_numpy(r1).to(dev))
+    net.train_step(Fb, sup, lr, rows=torch.from_numpy(r2).to(dev))
+    got = {k: v.cpu().numpy().astype(np.float64) for k, v in net.export().items()}
+    T = lo.multi_hot(w.true_support, 1024)
+    p0 = {k: v.astype(np.float64) for k, v in p.items()}
+    state = {}
+    _, g1 = lo.backward(p0, F[r1], T[r1], lo.bf16_round)
+    p1 = lo.adam_step(p0, g1, state, lr)
+    _, g2 = lo.backward(p1, F[r2], T[r2], lo.bf16_round)
+    p2 = lo.adam_step(p1, g2, state, lr)
+    for k in p0:
+        firm = (np.abs(g1[k]) >= 0.2 * np.abs(g1[k]).max()) & (np.abs(g2[k]) >= 0.2 * np.abs(g2[k]).max())
+        err = np.abs(got[k] - p2[k])
+        print(k, "firm", int(firm.sum()), "max err / lr", float(err[firm].max() / lr) if firm.any() else None,
+              "median / lr", float(np.median(err) / lr))
+        if firm.any():
+            assert err[firm].max() <= 0.25 * lr, k
+        assert np.median(err) <= 1e-2 * lr, k
+
+
 def test_adam_steps_closed_form():
     """Adam's moments and bias correction: a step with learning rate 0 (moments only)
     followed by a step with lr on the same batch at the same weights sees the same
@@ -191,3 +268,50 @@ def test_ls_check_and_fallback_against_oracle_and_plain_omp(orc):
     assert np.array_equal(sup[rej], ref.support.cpu().numpy())
     assert np.array_equal(coef[rej], ref.coef.cpu().numpy())
     assert np.array_equal(st[rej], ref.status.cpu().numpy())
+
+
+def test_what_training_gains_on_held_out_signals():
+    """Trains the network on the GPU (the library's own forward, backward and Adam
+    kernels) on 65,536 OMP-labelled signals of the learned workload and measures, on
+    8192 held-out signals, what it gains over its untrained start (which scores each
+    atom by its matched-filter feature): the training loss falls, but the held-out
+    recall of OMP's support among the 32 best scores stays at the start's (about 17.7 of
+    32; the best linear estimate from A^T y reaches about 20, measured on the CPU), no
+    held-out signal gets all 32 of OMP's atoms, and so no proposal explains a signal to
+    its noise level: the learned solve accepts none and returns plain OMP's results.
+    A proposal is accepted only when it holds every atom (one missed atom leaves about
+    its whole energy, above eps^2 = M sigma^2), which a one-shot estimate from A^T y at
+    S / M = 1/8 and 20 dB does not reach."""
+    torch = _torch()
+    from paper_2407_06434_amd import learned, omp, workloads
+    dev = torch.device("cuda:0")
+    tr = workloads.learned_256x1024(B=65536, stream=2)
+    ev = workloads.learned_256x1024(B=8192, stream=0)
+    A = torch.from_numpy(tr.A).to(dev)
+    d = omp.Dictionary(A, "bf16")
+    Ytr, Etr = torch.from_numpy(tr.Y).to(dev), torch.from_numpy(tr.eps_per_signal).to(dev)
+    Yev, Eev = torch.from_numpy(ev.Y).to(dev), torch.from_numpy(ev.eps_per_signal).to(dev)
+    print("case training gain 65536 pairs, 8192 held out", flush=True)
+    net = omp.MLP(workloads.mlp_init_params())
+    start = omp.MLP(workloads.mlp_init_params())
+    sup = learned.omp_labels(d, Ytr, 32, Etr)
+    F = learned.features(net, d, Ytr)
+    hist = learned.train(net, F, sup, 4, batch=1024, lr=1e-3)
+    ref = omp.solve(A, Yev, 32, precision="bf16", dictionary=d, eps_per_signal=Eev, dense=False)
+    s_o = ref.support.cpu().numpy()
+
+    def recall(network):
+        top = network.forward(learned.features(network, d, Yev)).topk(32, dim=1).indices.cpu().numpy()
+        hits = np.array([len(set(t.tolist()) & set(o[o >= 0].tolist())) for t, o in zip(top, s_o)])
+        return float(hits.mean()), int((hits == 32).sum())
+
+    r_t, all_t = recall(net)
+    r_0, all_0 = recall(start)
+    out, nacc = omp.learned_solve(d, net, Yev, 32, eps_per_signal=Eev)
+    torch.cuda.synchronize()
+    print(f"loss per epoch {[round(h, 3) for h in hist]}; held-out recall of OMP's support: trained {r_t:.2f}, "
+          f"untrained {r_0:.2f} of 32; signals with all 32: {all_t} / {all_0}; accepted {nacc} of {ev.B}")
+    assert hist[-1] < hist[0]                      # the kernels train: the loss falls
+    assert abs(r_t - r_0) <= 1.5 and r_t <= 24.0   # ... but the ranking stays the matched filter's
+    assert all_t == 0 and nacc == 0                # so nothing is accepted
+    assert np.array_equal(out.support.cpu().numpy(), s_o)  # and the result is plain OMP's

@@ -308,6 +308,31 @@ def test_graph_cache_eviction_with_solves_in_flight():
             assert torch.equal(getattr(o, k), getattr(ref, k)), (i, k)
 
 
+def test_solve_on_a_side_stream_while_the_default_stream_reuses_memory():
+    """A solve enqueued on a side stream, whose workspace and outputs the binding
+    allocates on torch's current stream, followed at once by allocations of the same
+    size written on the current stream: the caching allocator must not hand the
+    in-use workspace to them (the binding records it on the side stream), so the
+    results equal a solve on the current stream."""
+    torch = _torch()
+    from paper_2407_06434_amd import omp, workloads
+    w = workloads.batched_256x1024(B=2000)
+    dev = torch.device("cuda:0")
+    A = torch.from_numpy(w.A).to(dev)
+    Y = torch.from_numpy(w.Y).to(dev)
+    print("case side stream", flush=True)
+    ref = omp.solve(A, Y, w.S, graph=False)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    nbytes = omp.workspace_bytes(w.M, w.N, w.B, w.S)
+    out = omp.solve(A, Y, w.S, stream=side, graph=False)
+    junk = [torch.full((nbytes // 4,), 7.0, device=dev) for _ in range(4)]
+    torch.cuda.synchronize()
+    del junk
+    for k in ("support", "coef", "status", "rnorm", "X"):
+        assert torch.equal(getattr(out, k), getattr(ref, k)), k
+
+
 @pytest.mark.parametrize("prec", PRECS)
 def test_many_atom_tiles_keys_read_in_batches(orc, prec):
     """N = 8192 gives 768 BF16 keys per signal, more than the solve keeps in registers,
