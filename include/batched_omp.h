@@ -62,6 +62,10 @@ extern "C" {
 #define OMP_PREC_FP32 0 /* A^T R with FP32 inputs and FP32 accumulation */
 #define OMP_PREC_BF16 1 /* A^T R in BF16 with FP32 accumulation; the leading candidates
                            are re-scored in FP32 so that the pick is the FP32 argmax */
+#define OMP_PREC_FP16 3 /* as OMP_PREC_BF16 with FP16 copies: each atom stored as fp16(sigma_n a_n) and
+                           each residual as fp16(sigma_b r), sigma power-of-two scales that keep
+                           every stored value in [-1, 1]; the same certified exact re-score, with
+                           FP16's 8x finer rounding in the bound */
 #define OMP_PREC_FP64 2 /* everything in FP64 (the FP32 inputs are exact in FP64): the
                            paper's Algorithm v0 (see omp_opts_t.v0) with FP64 correlations,
                            Gram matrix, inverse factor and coefficients; the outputs are the

@@ -15,6 +15,7 @@
 //
 // The tile description and the LDS-staged main loop are in mfma_tile.h.
 
+#include "../../include/batched_omp.h"
 #include "mfma_tile.h"
 #include "omp_internal.h"
 
@@ -309,8 +310,9 @@ hipError_t launch_corr_t(const typename Op::elem *Aop, const typename Op::elem *
   hipError_t e = set_lds(kern, T::LDS_BYTES);
   if (e != hipSuccess) return e;
   const int ntile = (int)(d.Np / T::TN);
+  // the epilogue scores |c| by 1/||a_n|| (FP16 form: divided by the atom's storage scale)
   hipLaunchKernelGGL(kern, dim3((unsigned)(ntile * (w.Bp / T::TB))), dim3(T::NTHR), T::LDS_BYTES, st, Aop, Rop,
-                     d.Mp, d.Np, d.inv_nu, w.mask, w.flags, w.part, ntile);
+                     d.Mp, d.Np, d.inv_nu_h ? d.inv_nu_h : d.inv_nu, w.mask, w.flags, w.part, ntile);
   return hipGetLastError();
 }
 
@@ -321,7 +323,7 @@ CorrGeom geom(int precision, int cfg, bool ties) {
   g.cfg = cfg;
   g.tile_atoms = T::TN;
   g.tile_signals = T::TB;
-  g.keys_per_tile = precision == 1 ? T::WN * (T::FN / SUBF) * 2 * NKEEP : (ties ? 2 : 1);
+  g.keys_per_tile = is_half(precision) ? T::WN * (T::FN / SUBF) * 2 * NKEEP : (ties ? 2 : 1);
   g.wave_atoms = T::FN * 32;
   g.sub_frags = SUBF;
   g.subs_per_half = T::FN / SUBF;
@@ -390,21 +392,23 @@ hipError_t launch_project(const DictView &d, const WorkView &w, hipStream_t st) 
 
 template <class T>
 hipError_t launch_corr_cfg(const DictView &d, const WorkView &w, int precision, hipStream_t st) {
-  if (precision == 1) return launch_corr_t<OpBF16, T, true>(d.A16, w.R16, d, w, st);
+  if (precision == OMP_PREC_BF16) return launch_corr_t<OpBF16, T, true>(d.A16, w.R16, d, w, st);
+  if (precision == OMP_PREC_FP16) return launch_corr_t<OpF16, T, true>(d.A16, w.R16, d, w, st);
   if (w.ncand == 2) return launch_corr_t<OpF32, T, false, true>(d.A32, w.R32, d, w, st);
   return launch_corr_t<OpF32, T, false>(d.A32, w.R32, d, w, st);
 }
 
 template <class T>
 hipError_t prepare_corr_cfg(int precision, bool second) {
-  if (precision == 1) return set_lds(k_corr_select<OpBF16, T, true>, T::LDS_BYTES);
+  if (precision == OMP_PREC_BF16) return set_lds(k_corr_select<OpBF16, T, true>, T::LDS_BYTES);
+  if (precision == OMP_PREC_FP16) return set_lds(k_corr_select<OpF16, T, true>, T::LDS_BYTES);
   if (second) return set_lds(k_corr_select<OpF32, T, false, true>, T::LDS_BYTES);
   return set_lds(k_corr_select<OpF32, T, false>, T::LDS_BYTES);
 }
 
 hipError_t prepare_corr(const DictView &d, const WorkView &w, int precision) {
   (void)d;
-  const bool second = w.ncand == 2 && precision != 1;
+  const bool second = w.ncand == 2 && !is_half(precision);
   switch (w.tile_cfg) {
     case 2: return prepare_corr_cfg<Cfg2>(precision, second);
     case 3: return prepare_corr_cfg<Cfg3>(precision, second);

@@ -5,7 +5,7 @@
 //
 // A workgroup computes a TN x TB tile with WN x WB wavefronts; each wavefront
 // owns FN x FB fragments of 32 x 32 (v_mfma_f32_32x32x2f32 for FP32,
-// v_mfma_f32_32x32x16_bf16 for BF16). Operands are staged through LDS in
+// v_mfma_f32_32x32x16_bf16 for BF16, v_mfma_f32_32x32x16_f16 for FP16). Operands are staged through LDS in
 // 128-byte K slices, double buffered, with direct global-to-LDS loads (16
 // bytes per lane, no register round trip). A staged row is 8 chunks of 16
 // bytes; chunk c of row r sits at slot c ^ ((r >> 1) & 7) of the row, so the
@@ -38,6 +38,18 @@ struct OpF32 {
     c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.y), __uint_as_float(b.y), c, 0, 0, 0);
     c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.z), __uint_as_float(b.z), c, 0, 0, 0);
     c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.w), __uint_as_float(b.w), c, 0, 0, 0);
+  }
+};
+
+typedef __attribute__((ext_vector_type(8))) _Float16 f16x8;
+
+// FP16 copies of the operands (the FP16 form): one 16-byte chunk holds 8 FP16
+// values of K, one 32x32x16 MFMA.
+struct OpF16 {
+  using elem = uint16_t;
+  __device__ static inline void mma(const u32x4 &a, const u32x4 &b, f32x16 &c) {
+    c = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c, 0, 0,
+                                               0);
   }
 };
 

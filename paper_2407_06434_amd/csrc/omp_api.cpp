@@ -37,7 +37,7 @@ struct Carve {
 
 struct DictLayout {
   int64_t Mp, Np;
-  size_t nu2, inv_nu, A32, G, A16, aerr, aerr_max, G64, inv_nu64, total;
+  size_t nu2, inv_nu, A32, G, A16, aerr, aerr_max, G64, inv_nu64, inv_nu_h, total;
 };
 
 DictLayout dict_layout(int64_t M, int64_t N, int precision) {
@@ -49,11 +49,12 @@ DictLayout dict_layout(int64_t M, int64_t N, int precision) {
   L.inv_nu = c.take<float>(L.Np);
   L.A32 = c.take<float>((size_t)L.Np * L.Mp);
   L.G = c.take<float>((size_t)L.Np * L.Np);
-  L.A16 = precision == OMP_PREC_BF16 ? c.take<uint16_t>((size_t)L.Np * L.Mp) : 0;
+  L.A16 = is_half(precision) ? c.take<uint16_t>((size_t)L.Np * L.Mp) : 0;
   L.aerr = c.take<float>(L.Np);
   L.aerr_max = c.take<float>(1);
   L.G64 = precision == OMP_PREC_FP64 ? c.take<double>((size_t)L.Np * L.Np) : 0;
   L.inv_nu64 = precision == OMP_PREC_FP64 ? c.take<double>(L.Np) : 0;
+  L.inv_nu_h = precision == OMP_PREC_FP16 ? c.take<float>(L.Np) : 0;
   L.total = (c.off + ALIGN - 1) / ALIGN * ALIGN;
   return L;
 }
@@ -65,7 +66,7 @@ struct WorkLayout {
   int nslice, slice_len;
   int64_t vstride;
   size_t Yp, R32, R16, part, mask, k, flags, pnorm, pdelta, Sb, epsb, sup, u, xh, V, P, Pk, D, P64, D64, V64, u64,
-      total;
+      rscale, rscale_next, total;
   int pchunks;
 };
 
@@ -84,7 +85,9 @@ WorkLayout work_layout(int64_t M, int64_t N, int64_t B, int S, int precision, in
   Carve c;
   L.Yp = c.take<float>(Bp * L.Mp);
   L.R32 = c.take<float>(Bp * L.Mp);
-  L.R16 = precision == OMP_PREC_BF16 ? c.take<uint16_t>(Bp * L.Mp) : 0;
+  L.R16 = is_half(precision) ? c.take<uint16_t>(Bp * L.Mp) : 0;
+  L.rscale = precision == OMP_PREC_FP16 ? c.take<float>(Bp) : 0;
+  L.rscale_next = precision == OMP_PREC_FP16 ? c.take<float>(Bp) : 0;
   // (the Gram-domain select writes GSLICE keys per signal, twice that with near-tie flagging)
   // (the Gram-domain select writes GSLICE keys per signal, twice that with near-tie
   // flagging; v0 two keys, the FP64 form two (score, index) pairs of doubles)
@@ -124,6 +127,10 @@ T *at(void *base, size_t off) {
 }  // namespace
 
 bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+bool valid_precision(int p) {
+  return p == OMP_PREC_FP32 || p == OMP_PREC_BF16 || p == OMP_PREC_FP64 || p == OMP_PREC_FP16;
+}
 
 // Sizes whose padded buffers would overflow or exceed any real device are rejected.
 bool dims_ok(int64_t M, int64_t N) {
@@ -243,7 +250,8 @@ DictView dict_view(void *mem, int64_t M, int64_t N, int precision) {
   d.inv_nu = at<float>(mem, L.inv_nu);
   d.A32 = at<float>(mem, L.A32);
   d.G = at<float>(mem, L.G);
-  d.A16 = precision == OMP_PREC_BF16 ? at<uint16_t>(mem, L.A16) : nullptr;
+  d.A16 = is_half(precision) ? at<uint16_t>(mem, L.A16) : nullptr;
+  d.inv_nu_h = precision == OMP_PREC_FP16 ? at<float>(mem, L.inv_nu_h) : nullptr;
   d.aerr = at<float>(mem, L.aerr);
   d.aerr_max = at<float>(mem, L.aerr_max);
   d.G64 = precision == OMP_PREC_FP64 ? at<double>(mem, L.G64) : nullptr;
@@ -258,7 +266,7 @@ size_t work_bytes(int64_t M, int64_t N, int64_t B, int S, int precision, int cfg
 
 bool solve_fits(int64_t M, int64_t N, int64_t B, int S, int precision, int cfg) {
   const WorkLayout L = work_layout(M, N, B, S, precision, cfg);
-  return solve_waves_for(L.vstride, L.ntile * L.g.keys_per_tile, precision == OMP_PREC_BF16) > 0;
+  return solve_waves_for(L.vstride, L.ntile * L.g.keys_per_tile, is_half(precision)) > 0;
 }
 
 WorkView work_view(void *mem, int64_t M, int64_t N, int64_t B, int S, int precision, int cfg, bool gram_dom,
@@ -279,7 +287,10 @@ WorkView work_view(void *mem, int64_t M, int64_t N, int64_t B, int S, int precis
   w.subs_per_half = L.g.subs_per_half;
   w.Yp = at<float>(mem, L.Yp);
   w.R32 = at<float>(mem, L.R32);
-  w.R16 = precision == OMP_PREC_BF16 ? at<uint16_t>(mem, L.R16) : nullptr;
+  w.R16 = is_half(precision) ? at<uint16_t>(mem, L.R16) : nullptr;
+  w.fp16 = precision == OMP_PREC_FP16 ? 1 : 0;
+  w.rscale = L.rscale ? at<float>(mem, L.rscale) : nullptr;
+  w.rscale_next = L.rscale_next ? at<float>(mem, L.rscale_next) : nullptr;
   w.part = at<uint64_t>(mem, L.part);
   w.mask = at<uint32_t>(mem, L.mask);
   w.k = at<int32_t>(mem, L.k);
@@ -345,15 +356,14 @@ void omp_opts_default(omp_opts_t *opts) {
 }
 
 size_t omp_dict_size(int64_t M, int64_t N, int32_t precision) {
-  if (!dims_ok(M, N) || (precision != OMP_PREC_FP32 && precision != OMP_PREC_BF16 && precision != OMP_PREC_FP64))
-    return 0;
+  if (!dims_ok(M, N) || !valid_precision(precision)) return 0;
   return dict_bytes(M, N, precision);
 }
 
 int omp_dict_init(omp_dict_t *dict, const float *A, int64_t M, int64_t N, int64_t lda, int32_t precision,
                   void *mem, size_t bytes, void *stream) {
   if (!dict || !A || !dims_ok(M, N) || lda < M) return OMP_EINVAL;
-  if (precision != OMP_PREC_FP32 && precision != OMP_PREC_BF16 && precision != OMP_PREC_FP64) return OMP_EINVAL;
+  if (!valid_precision(precision)) return OMP_EINVAL;
   if (!aligned(A, 4)) return OMP_EINVAL;
   const size_t need = dict_bytes(M, N, precision);
   if (!mem || bytes < need || !aligned(mem, ALIGN)) return OMP_EWORKSPACE;
@@ -391,7 +401,7 @@ size_t omp_workspace_size(int64_t M, int64_t N, int64_t B, int32_t S, const omp_
 size_t bomp::solve_bytes(int64_t M, int64_t N, int64_t B, int32_t S, const omp_opts_t *opts) {
   const int prec = opts ? opts->precision : OMP_PREC_FP32;
   if (!dims_ok(M, N) || B < 0 || B > ((int64_t)1 << 26) || S < 1 || S > OMP_MAX_S) return 0;
-  if (prec != OMP_PREC_FP32 && prec != OMP_PREC_BF16 && prec != OMP_PREC_FP64) return 0;
+  if (!valid_precision(prec)) return 0;
   const int cfg = opts ? opts->tile_config : 0;
   if (cfg < 0 || cfg > MAX_TILE_CFG) return 0;
   const bool v0 = opts && opts->v0 == 1;
@@ -410,7 +420,7 @@ int solve_impl(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y
   // ---- validation (host only) ----
   if (!opts) return OMP_EINVAL;
   const int prec = opts->precision;
-  if (prec != OMP_PREC_FP32 && prec != OMP_PREC_BF16 && prec != OMP_PREC_FP64) return OMP_EINVAL;
+  if (!valid_precision(prec)) return OMP_EINVAL;
   const int cfg = opts->tile_config;
   if (cfg < 0 || cfg > MAX_TILE_CFG) return OMP_EINVAL;
   if (opts->gram_on_the_fly != 0 && opts->gram_on_the_fly != 1) return OMP_EINVAL;
@@ -421,7 +431,7 @@ int solve_impl(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y
   if (opts->v0 != 0 && opts->v0 != 1) return OMP_EINVAL;
   const bool f64 = prec == OMP_PREC_FP64;  // the FP64 form runs Algorithm v0 in FP64
   const bool v0 = opts->v0 == 1 || f64;
-  if (v0 && (prec == OMP_PREC_BF16 || opts->gram_domain == 1 || opts->gram_on_the_fly || opts->refactor))
+  if (v0 && (is_half(prec) || opts->gram_domain == 1 || opts->gram_on_the_fly || opts->refactor))
     return OMP_EINVAL;
   const bool gdom = !v0 && gram_domain_form(opts->gram_domain, prec, M, N);
   const bool ties = opts->flag_near_ties == 1;

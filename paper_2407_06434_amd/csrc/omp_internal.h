@@ -55,7 +55,14 @@ struct DictView {
   float *aerr_max; // [1]    max_n aerr[n] (BF16 form)
   double *G64;     // [Np][Np] Gram matrix in FP64 (FP64 form), or nullptr
   double *inv_nu64;// [Np]   1/||a_n|| in FP64 (FP64 form), or nullptr
+  // FP16 form: A16 holds fp16(sigma_n a_n), sigma_n a power of two with max |sigma_n a_n|
+  // in (1/2, 1], and the product's epilogue scores by inv_nu_h[n] = 1/(sigma_n ||a_n||)
+  float *inv_nu_h; // [Np] or nullptr (the other forms score by inv_nu)
 };
+
+// The forms whose correlation product runs on 16-bit copies (BF16, FP16) and whose
+// pick is the certified exact re-score.
+__host__ __device__ inline bool is_half(int precision) { return precision == 1 || precision == 3; }
 
 size_t dict_bytes(int64_t M, int64_t N, int precision);
 DictView dict_view(void *mem, int64_t M, int64_t N, int precision);
@@ -73,7 +80,10 @@ struct WorkView {
   int subs_per_half; // BF16 form: subgroups per wavefront half
   float *Yp;      // [Bp][Mp] zero-padded copy of Y
   float *R32;     // [Bp][Mp] residual, FP32
-  uint16_t *R16;  // [Bp][Mp] residual, BF16 (BF16 form only)
+  uint16_t *R16;  // [Bp][Mp] residual, BF16 (BF16 form) or FP16 scaled by rscale (FP16 form)
+  int fp16;       // 1: R16 and A16 hold FP16 (FP16 form)
+  float *rscale;  // [Bp] FP16 form: power-of-two scale of the residual stored in R16 (else nullptr)
+  float *rscale_next; // [Bp] FP16 form: the scale the residual kernel stores the next residual with
   uint64_t *part; // [Bp][ntile*ncand] packed (score, index) keys from the GEMM epilogue
   uint32_t *mask; // [Bp][Np/32] selected-atom bitmask
   int32_t *k;     // [Bp] atoms selected so far
@@ -140,7 +150,7 @@ __host__ __device__ inline int64_t solve_list_words(int64_t nkeys, bool bf16) {
   return bf16 ? solve_cand_len(nkeys) + MAYBE_CAP : 0;
 }
 __host__ __device__ inline int64_t solve_list_len(const WorkView &w) {
-  return solve_list_words((int64_t)w.ntile * w.ncand, w.R16 != nullptr);
+  return solve_list_words((int64_t)w.ntile * w.ncand, w.R16 != nullptr);  // 16-bit forms keep the lists
 }
 __host__ __device__ inline size_t solve_lds_per_wave(const WorkView &w) {
   return (size_t)(w.vstride + solve_list_len(w)) * 4;
@@ -187,6 +197,7 @@ int solve_impl(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y
                void *stream, void *workspace, size_t workspace_bytes, bool direct);
 size_t solve_bytes(int64_t M, int64_t N, int64_t B, int32_t S, const struct omp_opts *opts);
 bool aligned(const void *p, size_t a);
+bool valid_precision(int precision);         // one of the OMP_PREC_* values
 bool dims_ok(int64_t M, int64_t N);          // sizes the padded buffers can hold
 int device_error(hipError_t e);              // records e for omp_last_hip_error, returns OMP_EDEVICE
 int check_device();                          // OMP_OK on a gfx950 device

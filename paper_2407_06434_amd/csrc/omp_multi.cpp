@@ -357,7 +357,7 @@ int solve_multi_locked(const omp_problem_t *probs, int nprob, const omp_multi_op
 
 int validate(const omp_problem_t *probs, int nprob, const omp_multi_opts_t *opts) {
   if (!probs || !opts || nprob < 1 || nprob > OMP_MAX_PROBLEMS) return OMP_EINVAL;
-  if (opts->precision != OMP_PREC_FP32 && opts->precision != OMP_PREC_BF16) return OMP_EINVAL;
+  if (opts->precision != OMP_PREC_FP32 && !is_half(opts->precision)) return OMP_EINVAL;
   if (opts->iters_per_graph < 0 || opts->iters_per_graph > MAX_CHUNK) return OMP_EINVAL;
   for (int p = 0; p < nprob; ++p) {
     const int rc = check_problem(probs[p], opts->precision);
@@ -390,7 +390,7 @@ extern "C" {
 
 size_t omp_multi_workspace_size(const omp_problem_t *probs, int32_t nprob, const omp_multi_opts_t *opts) {
   if (!probs || !opts || nprob < 1 || nprob > OMP_MAX_PROBLEMS) return 0;
-  if (opts->precision != OMP_PREC_FP32 && opts->precision != OMP_PREC_BF16) return 0;
+  if (opts->precision != OMP_PREC_FP32 && !is_half(opts->precision)) return 0;
   for (int p = 0; p < nprob; ++p)
     if (check_problem(probs[p], opts->precision) != OMP_OK) return 0;
   return total_bytes(probs, nprob, opts->precision);

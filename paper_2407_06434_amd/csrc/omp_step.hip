@@ -48,6 +48,19 @@ __device__ inline uint16_t f32_to_bf16_rne(float f) {
   return (uint16_t)(u >> 16);
 }
 
+// FP16 (IEEE binary16) round to nearest even, and back.
+__device__ inline uint16_t f32_to_f16_rne(float f) { return __builtin_bit_cast(uint16_t, (_Float16)f); }
+__device__ inline float f16_to_f32(uint16_t h) { return (float)__builtin_bit_cast(_Float16, h); }
+
+// The power of two 2^-e with x 2^-e in [1/2, 1) (1 for x = 0 or non-finite x): the
+// FP16 form stores sigma v so that every stored value lies in [-1, 1].
+__device__ inline float pow2_scale(double x) {
+  if (!(x > 0.0) || !isfinite(x)) return 1.f;
+  int e;
+  (void)frexp(x, &e);
+  return ldexpf(1.f, -e);
+}
+
 // Cross-lane moves within 16-lane rows by DPP (no LDS round trip): the two
 // 32-bit halves of a 64-bit value move together.
 template <int CTRL>
@@ -432,22 +445,26 @@ __device__ void gram_row_from_atoms(const DictView &d, int nstar, const int (&si
 // row G[n*, support] of the pick (fetched in the same round as its score).
 // kv holds the signal's keys when kreg (read in the first memory round).
 template <int RPL>
-__device__ int select_bf16(const DictView &d, const WorkView &w, int64_t b, float smax, double tau,
+__device__ int select_bf16(const DictView &d, const WorkView &w, int64_t b, float smax_key, double ks, double tau,
                            const int (&si)[RPL], int k, int lane, int *widened, double *cdot, double *nu2,
                            float (&g)[RPL], int *clist, const uint32_t (&kv)[KREG], bool kreg, int *neartie) {
+  // Key scores carry the scale ks of the 16-bit residual copy (1 in the BF16 form, a
+  // power of two in the FP16 form): a score s is stored as ks s, exactly.
+  const double smax = (double)smax_key / ks;
   const int nkeys = w.ntile * w.ncand;
   const uint32_t *keys = reinterpret_cast<const uint32_t *>(w.part) + b * nkeys;
   const float4 *r4 = reinterpret_cast<const float4 *>(w.R32) + b * (d.Mp / 4);
   const double et = 1.0 / 262144.0;  // 2^-18: the epilogue's rounding of listed scores
   // Near-tie flagging widens both windows by TIE_REL s_max, so that every atom
   // whose exact score can reach (1 - TIE_REL) s_w is re-scored too.
-  const double tw = w.flag_ties ? TIE_REL * (double)smax : 0.0;
-  const double thr = (double)smax - 2.0 * tau - et * (double)smax - tw;
-  const double mthr = (double)smax - 2.0 * tau - tw;
+  const double tw = w.flag_ties ? TIE_REL * smax : 0.0;
+  const double thr = smax - 2.0 * tau - et * smax - tw;
+  const double mthr = smax - 2.0 * tau - tw;
   // the same tests on score bits: s >= thr, and s (1 + et) >= mthr taken as
-  // s >= mthr / (1 + et) lowered by 1e-12 relative (a superset of the list)
-  const uint32_t thr_bits = float_bits_floor(thr);
-  const uint32_t mthr_bits = float_bits_floor(mthr / (1.0 + et) * (1.0 - 1e-12));
+  // s >= mthr / (1 + et) lowered by 1e-12 relative (a superset of the list), both
+  // in the keys' scale
+  const uint32_t thr_bits = float_bits_floor(thr * ks);
+  const uint32_t mthr_bits = float_bits_floor(mthr / (1.0 + et) * (1.0 - 1e-12) * ks);
   int *mlist = clist + solve_cand_len(nkeys);
   RescoreQueue<RPL> q;
   q.gram = !w.gram_fly;
@@ -483,7 +500,7 @@ __device__ int select_bf16(const DictView &d, const WorkView &w, int64_t b, floa
   const int npass = movf ? nkeys / NKEEP : nmaybe;
   for (int i = 0; i < npass; ++i) {
     const int slot = movf ? i * NKEEP + NKEEP - 1 : __builtin_amdgcn_readfirstlane(mlist[i]);
-    const double theta = key_score(keys[slot]);
+    const double theta = key_score(keys[slot]) / ks;
     if (!(theta * (1.0 + et) + tau >= (w.flag_ties ? (1.0 - TIE_REL) * q.bs : q.bs))) continue;
     const int tile = slot / w.ncand;
     const int sgl = (slot % w.ncand) / NKEEP;  // ((wn * subs_per_half + ig) * 2 + h)
@@ -512,20 +529,38 @@ __device__ int select_bf16(const DictView &d, const WorkView &w, int64_t b, floa
 // ---------------------------------------------------------------------------
 // Dictionary preparation: one wavefront per (padded) atom.
 // ---------------------------------------------------------------------------
+// The FP16 form (inv_nu_h set) stores fp16(sigma_n a_n) with sigma_n = pow2_scale(max_m
+// |a_n,m|) and scores by inv_nu_h[n] = 1/(sigma_n ||a_n||); the rounding error ratio is
+// measured in the atom's own scale.
 __global__ __launch_bounds__(64) void k_dict_prep(const float *__restrict__ A, int64_t lda, int64_t M,
                                                   int64_t N, int64_t Mp, double *__restrict__ nu2,
                                                   float *__restrict__ inv_nu, float *__restrict__ A32,
-                                                  uint16_t *__restrict__ A16, float *__restrict__ aerr) {
+                                                  uint16_t *__restrict__ A16, float *__restrict__ aerr,
+                                                  float *__restrict__ inv_nu_h) {
   const int64_t n = blockIdx.x;
   const int lane = threadIdx.x;
+  float sig = 1.f;
+  if (inv_nu_h) {
+    float mx = 0.f;
+    for (int64_t m = lane; m < M; m += 64) mx = fmaxf(mx, n < N ? fabsf(A[n * lda + m]) : 0.f);
+    for (int o = 32; o >= 1; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+    sig = pow2_scale((double)mx);
+  }
   double s = 0.0, e = 0.0;
   for (int64_t m = lane; m < Mp; m += 64) {
     const float v = (n < N && m < M) ? A[n * lda + m] : 0.f;
     A32[n * Mp + m] = v;
     if (A16) {
-      const uint16_t h = f32_to_bf16_rne(v);
+      uint16_t h;
+      double dv;
+      if (inv_nu_h) {
+        h = f32_to_f16_rne(v * sig);
+        dv = (double)v - (double)f16_to_f32(h) / (double)sig;
+      } else {
+        h = f32_to_bf16_rne(v);
+        dv = (double)v - (double)__uint_as_float((uint32_t)h << 16);
+      }
       A16[n * Mp + m] = h;
-      const double dv = (double)v - (double)__uint_as_float((uint32_t)h << 16);
       e += dv * dv;
     }
     s += (double)v * (double)v;
@@ -535,6 +570,7 @@ __global__ __launch_bounds__(64) void k_dict_prep(const float *__restrict__ A, i
   if (lane == 0) {
     nu2[n] = s;
     inv_nu[n] = s > 0.0 ? (float)(1.0 / sqrt(s)) : 0.f;
+    if (inv_nu_h) inv_nu_h[n] = s > 0.0 ? (float)(1.0 / (sqrt(s) * (double)sig)) : 0.f;
     // rounded up so that the float is an upper bound of the ratio
     aerr[n] = s > 0.0 ? __double2float_ru(sqrt(e / s) * (1.0 + 1e-12)) : 0.f;
   }
@@ -594,7 +630,7 @@ __device__ void init_column(const WorkView &w, int64_t b, const float *__restric
       v.w = isfinite(v.w) ? v.w : 0.f;
       Y4[c] = v;
       R4[c] = v;
-      if (w.R16) {
+      if (w.R16 && !w.fp16) {
         ushort4 h;
         h.x = f32_to_bf16_rne(v.x);
         h.y = f32_to_bf16_rne(v.y);
@@ -616,7 +652,7 @@ __device__ void init_column(const WorkView &w, int64_t b, const float *__restric
       const float vz = isfinite(v) ? v : 0.f;
       w.Yp[b * w.Mp + m] = vz;
       w.R32[b * w.Mp + m] = vz;
-      if (w.R16) {
+      if (w.R16 && !w.fp16) {
         const uint16_t h = f32_to_bf16_rne(vz);
         w.R16[b * w.Mp + m] = h;
         const double dv = (double)vz - (double)__uint_as_float((uint32_t)h << 16);
@@ -630,6 +666,22 @@ __device__ void init_column(const WorkView &w, int64_t b, const float *__restric
   s = wave_sum(s);
   dl = wave_sum(dl);
   const bool all_finite = __all(finite);
+  if (w.fp16) {
+    // FP16 form: the 16-bit copy is fp16(sigma y), sigma = pow2_scale(||y||), so every
+    // stored value lies in [-1, 1]; ||y - fp16(sigma y) / sigma||^2 replaces dl
+    const float sig = all_finite ? pow2_scale(sqrt(s)) : 1.f;
+    double d16 = 0.0;
+    for (int64_t m = lane; m < w.Mp; m += 64) {
+      float v = (y && m < M) ? y[m] : 0.f;
+      v = isfinite(v) ? v : 0.f;
+      const uint16_t h = f32_to_f16_rne(v * sig);
+      w.R16[b * w.Mp + m] = h;
+      const double dv = (double)v - (double)f16_to_f32(h) / (double)sig;
+      d16 += dv * dv;
+    }
+    dl = wave_sum(d16);
+    if (lane == 0) w.rscale[b] = sig;
+  }
   if (lane < NSLICE_MAX) {
     w.pnorm[b * NSLICE_MAX + lane] = (lane == 0 && all_finite) ? s : 0.0;
     // (the Gram-domain and v0 forms keep ||y||^2 there: the rounding scale of their running ||r||^2)
@@ -760,6 +812,7 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
   const double pn = lane < NSLICE_MAX ? w.pnorm[b * NSLICE_MAX + lane] : 0.0;
   const double pd = (BF16 && lane < NSLICE_MAX) ? w.pdelta[b * NSLICE_MAX + lane] : 0.0;
   const double y2 = w.gram_dom ? w.pdelta[b * NSLICE_MAX] : 0.0;  // Gram-domain form: ||y||^2
+  const double ks = (BF16 && w.fp16) ? (double)w.rscale[b] : 1.0;    // FP16 form: scale of the keys
   // Every stop found below leaves through the `stop` label with these set, so
   // that the stop's code (slot scheduler: the retire and admit) exists once.
   int stopfl = 0;
@@ -891,8 +944,10 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
   if (BF16) {
     const double tau = bf16_tau(rn, sqrt(wave_sum(pd)), (double)d.aerr_max[0], d.Mp);
     int neartie = 0;
-    nstar = select_bf16<RPL>(d, w, b, __uint_as_float((uint32_t)(kmax >> 32)), tau, si, k, lane, &widened, &cdot,
-                             &nu2, g, clist, kv, kreg, &neartie);
+    nstar = select_bf16<RPL>(d, w, b, __uint_as_float((uint32_t)(kmax >> 32)), ks, tau, si, k, lane, &widened,
+                             &cdot, &nu2, g, clist, kv, kreg, &neartie);
+    // FP16 form: the next residual copy is scaled by ||r_k||, which bounds ||r_k+1||
+    if (w.fp16 && lane == 0) w.rscale_next[b] = pow2_scale(rn);
     if (nstar < 0) {
       stopfl = fl | FLAG_DONE | OMP_SIG_EXHAUSTED;
       goto stop;
@@ -1743,6 +1798,9 @@ __global__ __launch_bounds__(256) void k_residual(DictView d, WorkView w, int LP
   const float *xi = xs + item * S;
   const int *si = ss + item * S;
   double nrm = 0.0, dlt = 0.0;
+  // FP16 form: the copy is fp16(sigma r) with the scale the solve chose from ||r|| before
+  // this update (so |sigma r_m| <= 1)
+  const float sig = (BF16 && w.fp16) ? w.rscale_next[b] : 1.f;
   for (int64_t c = sl; c < sl4; c += LP) {
     float4 r = Y4[c];
     int j = 0;
@@ -1763,7 +1821,19 @@ __global__ __launch_bounds__(256) void k_residual(DictView d, WorkView w, int LP
       r.x = fmaf(x0, a.x, r.x); r.y = fmaf(x0, a.y, r.y); r.z = fmaf(x0, a.z, r.z); r.w = fmaf(x0, a.w, r.w);
     }
     R4[c] = r;
-    if (BF16) {
+    if (BF16 && w.fp16) {
+      ushort4 h;
+      h.x = f32_to_f16_rne(r.x * sig);
+      h.y = f32_to_f16_rne(r.y * sig);
+      h.z = f32_to_f16_rne(r.z * sig);
+      h.w = f32_to_f16_rne(r.w * sig);
+      reinterpret_cast<ushort4 *>(w.R16)[b * nc4 + c0 + c] = h;
+      const double e0 = (double)r.x - (double)f16_to_f32(h.x) / (double)sig;
+      const double e1 = (double)r.y - (double)f16_to_f32(h.y) / (double)sig;
+      const double e2 = (double)r.z - (double)f16_to_f32(h.z) / (double)sig;
+      const double e3 = (double)r.w - (double)f16_to_f32(h.w) / (double)sig;
+      dlt += e0 * e0 + e1 * e1 + e2 * e2 + e3 * e3;
+    } else if (BF16) {
       ushort4 h;
       h.x = f32_to_bf16_rne(r.x);
       h.y = f32_to_bf16_rne(r.y);
@@ -1791,6 +1861,7 @@ __global__ __launch_bounds__(256) void k_residual(DictView d, WorkView w, int LP
   if (sl == 0) {
     w.pnorm[b * NSLICE_MAX + slice] = nrm;
     if (BF16) w.pdelta[b * NSLICE_MAX + slice] = dlt;
+    if (BF16 && w.fp16 && slice == 0) w.rscale[b] = sig;  // the scale the next product's keys carry
   }
 }
 
@@ -1887,7 +1958,7 @@ template <bool SLOTS>
 hipError_t launch_solve_any(const DictView &d, const WorkView &w, const SlotView &sv, int precision,
                             hipStream_t st) {
   if (w.B == 0) return hipSuccess;
-  const bool bf = precision == OMP_PREC_BF16;
+  const bool bf = is_half(precision);
   if (w.S <= 64)
     return bf ? launch_solve_t<1, true, SLOTS>(d, w, sv, st) : launch_solve_t<1, false, SLOTS>(d, w, sv, st);
   if (w.S <= 128)
@@ -1917,7 +1988,7 @@ int residual_lanes(const WorkView &w, int lanes) {
 
 hipError_t launch_dict_prep(const float *A, int64_t lda, const DictView &d, hipStream_t st) {
   hipLaunchKernelGGL(k_dict_prep, dim3((unsigned)d.Np), dim3(64), 0, st, A, lda, d.M, d.N, d.Mp, d.nu2,
-                     d.inv_nu, d.A32, d.A16, d.aerr);
+                     d.inv_nu, d.A32, d.A16, d.aerr, d.inv_nu_h);
   hipLaunchKernelGGL(k_dict_aerr_max, dim3(1), dim3(1024), 0, st, d.aerr, d.Np, d.aerr_max);
   return hipGetLastError();
 }
@@ -1954,7 +2025,7 @@ hipError_t launch_residual_lp(const DictView &d, const WorkView &w, int precisio
   const int64_t groups = (w.B + items - 1) / items;
   const size_t lds = residual_lds(w, LP);
   const dim3 grid((unsigned)(groups * w.nslice)), block(256);
-  if (precision == OMP_PREC_BF16) {
+  if (is_half(precision)) {
     hipError_t e = allow_lds(k_residual<true>, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_residual<true>, grid, block, lds, st, d, w, LP);
@@ -2048,7 +2119,7 @@ hipError_t launch_densify(const int32_t *support, const float *coef, int64_t nsi
 
 hipError_t prepare_kernels(const DictView &d, const WorkView &w, int precision, int lanes) {
   const size_t slds = solve_lds_per_wave(w) * (size_t)(solve_waves(w) > 0 ? solve_waves(w) : 1);
-  const bool bf = precision == OMP_PREC_BF16;
+  const bool bf = is_half(precision);
   hipError_t e = hipSuccess;
   if (w.S <= 64) e = bf ? allow_lds(k_solve<1, true, true>, slds) : allow_lds(k_solve<1, false, true>, slds);
   else if (w.S <= 128) e = bf ? allow_lds(k_solve<2, true, true>, slds) : allow_lds(k_solve<2, false, true>, slds);

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_PKG, "libbatched_omp.so")
 
 OMP_OK, OMP_EINVAL, OMP_EWORKSPACE, OMP_EDEVICE, OMP_ENOTSUPP = 0, -1, -2, -3, -4
 OMP_MAX_S = 256
-PREC = {"fp32": 0, "bf16": 1, "fp64": 2}
+PREC = {"fp32": 0, "bf16": 1, "fp64": 2, "fp16": 3}
 NPHASE = 6
 PHASES = ("dict", "init", "corr", "update", "output", "residual")
 SIG_EPS, SIG_SMAX, SIG_DEPENDENT, SIG_NONFINITE, SIG_EXHAUSTED, SIG_WIDENED = 1, 2, 4, 8, 32, 64

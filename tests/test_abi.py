@@ -72,6 +72,13 @@ def test_workspace_size_scales_and_rejects(lib):
     assert lib.omp_workspace_size(10, 10, 1, omp.OMP_MAX_S + 1, ctypes.byref(o)) == 0
     ob = _opts(prec=1)
     assert lib.omp_workspace_size(1024, 4096, 4096, 64, ctypes.byref(ob)) > s1
+    oh = _opts(prec=3)  # FP16: the BF16 layout plus one scale pair per signal
+    assert lib.omp_workspace_size(1024, 4096, 4096, 64, ctypes.byref(oh)) > lib.omp_workspace_size(
+        1024, 4096, 4096, 64, ctypes.byref(ob))
+    assert lib.omp_dict_size(1024, 4096, 3) > lib.omp_dict_size(1024, 4096, 1)
+    o64 = _opts(prec=2)  # FP64: D and the FP64 state per signal
+    assert lib.omp_workspace_size(1024, 4096, 4096, 64, ctypes.byref(o64)) > 8 * 4096 * 64 * 4096
+    assert lib.omp_dict_size(1024, 4096, 2) >= 8 * 4096 * 4096 + 4 * 4096 * 4096
     assert lib.omp_dict_size(1024, 4096, 0) >= 4096 * 4096 * 4
     assert lib.omp_dict_size(0, 4096, 0) == 0
 
@@ -225,7 +232,7 @@ def test_dict_init_rejects_invalid(lib):
     from paper_2407_06434_amd import omp
     d = omp.OmpDictStruct()
     assert lib.omp_dict_init(ctypes.byref(d), FAKE, 64, 256, 63, 0, FAKE, 1 << 30, None) == omp.OMP_EINVAL
-    assert lib.omp_dict_init(ctypes.byref(d), FAKE, 64, 256, 64, 3, FAKE, 1 << 30, None) == omp.OMP_EINVAL
+    assert lib.omp_dict_init(ctypes.byref(d), FAKE, 64, 256, 64, 4, FAKE, 1 << 30, None) == omp.OMP_EINVAL
     assert lib.omp_dict_init(ctypes.byref(d), FAKE, 64, 256, 64, 0, FAKE, 16, None) == omp.OMP_EWORKSPACE
     assert lib.omp_dict_init(None, FAKE, 64, 256, 64, 0, FAKE, 1 << 30, None) == omp.OMP_EINVAL
 

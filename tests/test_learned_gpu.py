@@ -260,6 +260,16 @@ def test_ls_check_and_fallback_against_oracle_and_plain_omp(orc):
     scale = np.maximum(np.abs(X[acc]), 1e-2 * np.abs(X[acc]).max(axis=1, keepdims=True))
     assert np.all(np.abs(coef[acc] - X[acc]) <= 1e-4 * scale)
     assert np.allclose(out.rnorm.cpu().numpy()[acc], rn[acc], rtol=1e-4, atol=1e-6)
+    # accepted supports against plain OMP's on the same signals: acceptance checks the
+    # residual only, so a different support is possible; counted here (these signals are
+    # built on P with small noise, where OMP recovers P)
+    acc_idx = torch.from_numpy(np.nonzero(acc)[0]).to(dev)
+    plain = omp.solve(A, Yt[acc_idx].contiguous(), 32, precision="bf16", dictionary=d,
+                      eps_per_signal=Et[acc_idx].contiguous(), dense=False)
+    ps = plain.support.cpu().numpy()
+    differ = sum(set(a.tolist()) != set(Pset.tolist()) for a in ps)
+    print("accepted supports that differ from plain OMP's:", differ, "of", int(acc.sum()))
+    assert differ <= 0.05 * acc.sum()
     # rejects: identical to a plain BF16 OMP solve of the same signals
     rej = np.nonzero(~acc)[0]
     ref = omp.solve(A, Yt[torch.from_numpy(rej).to(dev)].contiguous(), 32, precision="bf16", dictionary=d,
@@ -272,31 +282,34 @@ def test_ls_check_and_fallback_against_oracle_and_plain_omp(orc):
 
 def test_what_training_gains_on_held_out_signals():
     """Trains the network on the GPU (the library's own forward, backward and Adam
-    kernels) on 65,536 OMP-labelled signals of the learned workload and measures, on
-    8192 held-out signals, what it gains over its untrained start (which scores each
-    atom by its matched-filter feature): the training loss falls, but the held-out
-    recall of OMP's support among the 32 best scores stays at the start's (about 17.7 of
-    32; the best linear estimate from A^T y reaches about 20, measured on the CPU), no
-    held-out signal gets all 32 of OMP's atoms, and so no proposal explains a signal to
-    its noise level: the learned solve accepts none and returns plain OMP's results.
-    A proposal is accepted only when it holds every atom (one missed atom leaves about
-    its whole energy, above eps^2 = M sigma^2), which a one-shot estimate from A^T y at
-    S / M = 1/8 and 20 dB does not reach."""
+    kernels) on 2^20 OMP-labelled signals of the learned workload for 8 epochs and
+    measures, on 16,384 held-out signals, what it gains over its untrained start (which
+    scores each atom by its matched-filter feature): the held-out recall of OMP's
+    support among the 32 best scores rises (measured: 18.3 against 17.0 of 32 on the
+    benchmark's evaluation set; with 2^16 pairs it does not rise), but no held-out
+    signal gets all 32 of OMP's atoms, so no proposal explains a signal to its noise
+    level and the learned solve accepts none, returning plain OMP's results. A
+    proposal is accepted only when it holds every atom (one missed atom leaves about
+    its whole energy, above eps^2 = M sigma^2); one-shot estimates from A^T y at
+    S / M = 1/8 and 20 dB stay far from that (the best linear one, ridge regression,
+    reaches about 20 of 32, measured on the CPU)."""
     torch = _torch()
     from paper_2407_06434_amd import learned, omp, workloads
     dev = torch.device("cuda:0")
-    tr = workloads.learned_256x1024(B=65536, stream=2)
-    ev = workloads.learned_256x1024(B=8192, stream=0)
+    tr = workloads.learned_256x1024(B=1 << 20, stream=2)
+    ev = workloads.learned_256x1024(B=16384, stream=0)
     A = torch.from_numpy(tr.A).to(dev)
     d = omp.Dictionary(A, "bf16")
     Ytr, Etr = torch.from_numpy(tr.Y).to(dev), torch.from_numpy(tr.eps_per_signal).to(dev)
     Yev, Eev = torch.from_numpy(ev.Y).to(dev), torch.from_numpy(ev.eps_per_signal).to(dev)
-    print("case training gain 65536 pairs, 8192 held out", flush=True)
+    del tr
+    print("case training gain 2^20 pairs, 16384 held out", flush=True)
     net = omp.MLP(workloads.mlp_init_params())
     start = omp.MLP(workloads.mlp_init_params())
     sup = learned.omp_labels(d, Ytr, 32, Etr)
     F = learned.features(net, d, Ytr)
-    hist = learned.train(net, F, sup, 4, batch=1024, lr=1e-3)
+    hist = learned.train(net, F, sup, 8, batch=1024, lr=1e-3)
+    del F, Ytr
     ref = omp.solve(A, Yev, 32, precision="bf16", dictionary=d, eps_per_signal=Eev, dense=False)
     s_o = ref.support.cpu().numpy()
 
@@ -311,7 +324,7 @@ def test_what_training_gains_on_held_out_signals():
     torch.cuda.synchronize()
     print(f"loss per epoch {[round(h, 3) for h in hist]}; held-out recall of OMP's support: trained {r_t:.2f}, "
           f"untrained {r_0:.2f} of 32; signals with all 32: {all_t} / {all_0}; accepted {nacc} of {ev.B}")
-    assert hist[-1] < hist[0]                      # the kernels train: the loss falls
-    assert abs(r_t - r_0) <= 1.5 and r_t <= 24.0   # ... but the ranking stays the matched filter's
-    assert all_t == 0 and nacc == 0                # so nothing is accepted
+    assert hist[-1] < hist[0]      # the kernels train: the loss falls
+    assert r_t >= r_0 + 0.5        # and the held-out ranking improves on the matched filter
+    assert all_t == 0 and nacc == 0  # but never to a whole support, so nothing is accepted
     assert np.array_equal(out.support.cpu().numpy(), s_o)  # and the result is plain OMP's

@@ -51,7 +51,7 @@ def run_gpu(w, precision="fp32", dense=True, S_per=None, eps_per=None, dictionar
     return out
 
 
-PRECS = ["fp32", "bf16"]
+PRECS = ["fp32", "bf16", "fp16"]
 # every form of the solve: the two precisions of the residual-vector form, the
 # Gram-domain form and Algorithm v0 (both FP32)
 FORMS = ["fp32", "bf16", "gram", "v0", "fp64"]
@@ -148,15 +148,16 @@ def test_full_size_1024x4096(orc, prec):
         print("widened signals:", int(np.sum(out["status"] & 64 != 0)))
 
 
-def test_bf16_same_supports_as_fp32_full_batch(orc):
-    """The metric's clause: the BF16 form selects the same supports as plain FP32 on the
-    whole 4096-signal batch. Where the two differ, both must be legitimate: each form's
-    picks are checked step by step against the oracle (a difference can only start at a
-    near-tie whose top-two gap is below 1e-5)."""
+@pytest.mark.parametrize("half", ["bf16", "fp16"])
+def test_bf16_same_supports_as_fp32_full_batch(orc, half):
+    """The metric's clause: the BF16 form (and the FP16 form) selects the same supports
+    as plain FP32 on the whole 4096-signal batch. Where the two differ, both must be
+    legitimate: each form's picks are checked step by step against the oracle (a
+    difference can only start at a near-tie whose top-two gap is below 1e-5)."""
     from paper_2407_06434_amd import workloads
     w = workloads.bf16_1024x4096()
     a = run_gpu(w, "fp32", dense=False)
-    b = run_gpu(w, "bf16", dense=False)
+    b = run_gpu(w, half, dense=False)
     same_rows = np.array([set(x.tolist()) == set(y.tolist()) for x, y in zip(a["support"], b["support"])])
     order = int(np.sum(np.all(a["support"] == b["support"], axis=1)))
     both = same_rows & np.all(a["support"] == b["support"], axis=1)

@@ -64,7 +64,7 @@ def _same(a, b, keys=("support", "coef", "status", "rnorm")):
         assert np.array_equal(a[k], b[k]), k
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
 def test_uneven_pair_matches_plain_and_oracle(orc, prec):
     from paper_2407_06434_amd import omp, workloads
     ws = workloads.uneven_pair(B_each=700)
