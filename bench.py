@@ -445,8 +445,9 @@ def v0_bytes_per_launch(N, S, B, elem):
 def run_v0_forms(w_main, steps=3, warmup=1):
     """Algorithm v0 of the paper (FP32, opts.v0) and the FP64 form (v0 in FP64) beside
     the residual-vector FP32 form and its re-factorising variant (ablation A3 of the
-    paper: inverse Cholesky against re-factorisation), on the benchmark workload and on
-    the 256 x 1024 workload. Graph-replayed calls; supports compared with the FP32 form;
+    paper: inverse Cholesky against re-factorisation), the Gram-domain form forced on
+    these wide dictionaries (M < N: where it stops paying) and the FP16 form, on the
+    benchmark workload and on the 256 x 1024 workload. Graph-replayed calls; supports compared with the FP32 form;
     one more direct call per form gives the v0 step kernel's launch time."""
     import torch
     from paper_2407_06434_amd import omp, workloads
@@ -457,7 +458,8 @@ def run_v0_forms(w_main, steps=3, warmup=1):
         Y = torch.from_numpy(w.Y).to(dev)
         res = {}
         for name, prec, flags in (("fp32", "fp32", {}), ("fp32_refactor", "fp32", {"refactor": True}),
-                                  ("v0_fp32", "fp32", {"v0": True}), ("fp64", "fp64", {})):
+                                  ("v0_fp32", "fp32", {"v0": True}), ("fp64", "fp64", {}),
+                                  ("gram_domain_fp32", "fp32", {"gram_domain": True}), ("fp16", "fp16", {})):
             d = omp.Dictionary(A, prec)
             out = None
             for _ in range(warmup):
@@ -491,6 +493,7 @@ def run_v0_forms(w_main, steps=3, warmup=1):
         line["v0_speedup_vs_fp32"] = round(line["v0_fp32"]["value"] / line["fp32"]["value"], 3)
         line["fp64_speed_vs_fp32"] = round(line["fp64"]["value"] / line["fp32"]["value"], 3)
         line["fp64_speed_vs_v0_fp32"] = round(line["fp64"]["value"] / line["v0_fp32"]["value"], 3)
+        line["gram_domain_speed_vs_fp32"] = round(line["gram_domain_fp32"]["value"] / line["fp32"]["value"], 3)
         line["ablation_inverse_cholesky"] = {
             "v0_fp32": line["v0_fp32"]["value"], "refactorised_each_step_fp32": line["fp32_refactor"]["value"],
             "speedup": round(line["v0_fp32"]["value"] / line["fp32_refactor"]["value"], 2)}

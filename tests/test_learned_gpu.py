@@ -261,15 +261,18 @@ def test_ls_check_and_fallback_against_oracle_and_plain_omp(orc):
     assert np.all(np.abs(coef[acc] - X[acc]) <= 1e-4 * scale)
     assert np.allclose(out.rnorm.cpu().numpy()[acc], rn[acc], rtol=1e-4, atol=1e-6)
     # accepted supports against plain OMP's on the same signals: acceptance checks the
-    # residual only, so a different support is possible; counted here (these signals are
-    # built on P with small noise, where OMP recovers P)
+    # residual only, so a support other than OMP's can be accepted. Here P is the true
+    # support; where OMP misses it (OMP's greedy picks fail on some 32-sparse signals in
+    # 256 dimensions) the accepted proposal fits y at least as well as OMP's support.
     acc_idx = torch.from_numpy(np.nonzero(acc)[0]).to(dev)
     plain = omp.solve(A, Yt[acc_idx].contiguous(), 32, precision="bf16", dictionary=d,
                       eps_per_signal=Et[acc_idx].contiguous(), dense=False)
     ps = plain.support.cpu().numpy()
-    differ = sum(set(a.tolist()) != set(Pset.tolist()) for a in ps)
-    print("accepted supports that differ from plain OMP's:", differ, "of", int(acc.sum()))
-    assert differ <= 0.05 * acc.sum()
+    differ = np.array([set(a.tolist()) != set(Pset.tolist()) for a in ps])
+    print("accepted supports that differ from plain OMP's:", int(differ.sum()), "of", int(acc.sum()))
+    prn = plain.rnorm.cpu().numpy()
+    arn = out.rnorm.cpu().numpy()[acc]
+    assert np.all(arn[differ] <= prn[differ] * (1 + 1e-4))
     # rejects: identical to a plain BF16 OMP solve of the same signals
     rej = np.nonzero(~acc)[0]
     ref = omp.solve(A, Yt[torch.from_numpy(rej).to(dev)].contiguous(), 32, precision="bf16", dictionary=d,
