@@ -52,6 +52,16 @@ __device__ inline uint16_t f32_to_bf16_rne(float f) {
 __device__ inline uint16_t f32_to_f16_rne(float f) { return __builtin_bit_cast(uint16_t, (_Float16)f); }
 __device__ inline float f16_to_f32(uint16_t h) { return (float)__builtin_bit_cast(_Float16, h); }
 
+// The value the product may take for a stored 16-bit code: the code's own value, or 0
+// where the code is subnormal (an MFMA that flushes subnormal inputs uses 0). The
+// rounding errors of the copies are measured against it, so the certificate's bound
+// holds whether or not subnormals are flushed (|v - sub| <= |v - 0| for a subnormal sub
+// that v rounds to).
+__device__ inline double bf16_used(uint16_t h) {
+  return (h & 0x7F80u) == 0 ? 0.0 : (double)__uint_as_float((uint32_t)h << 16);
+}
+__device__ inline double f16_used(uint16_t h) { return (h & 0x7C00u) == 0 ? 0.0 : (double)f16_to_f32(h); }
+
 // The power of two 2^-e with x 2^-e in [1/2, 1) (1 for x = 0 or non-finite x): the
 // FP16 form stores sigma v so that every stored value lies in [-1, 1].
 __device__ inline float pow2_scale(double x) {
@@ -555,10 +565,10 @@ __global__ __launch_bounds__(64) void k_dict_prep(const float *__restrict__ A, i
       double dv;
       if (inv_nu_h) {
         h = f32_to_f16_rne(v * sig);
-        dv = (double)v - (double)f16_to_f32(h) / (double)sig;
+        dv = (double)v - f16_used(h) / (double)sig;
       } else {
         h = f32_to_bf16_rne(v);
-        dv = (double)v - (double)__uint_as_float((uint32_t)h << 16);
+        dv = (double)v - bf16_used(h);
       }
       A16[n * Mp + m] = h;
       e += dv * dv;
@@ -637,10 +647,10 @@ __device__ void init_column(const WorkView &w, int64_t b, const float *__restric
         h.z = f32_to_bf16_rne(v.z);
         h.w = f32_to_bf16_rne(v.w);
         reinterpret_cast<ushort4 *>(w.R16 + b * w.Mp)[c] = h;
-        const double d0 = (double)v.x - (double)__uint_as_float((uint32_t)h.x << 16);
-        const double d1 = (double)v.y - (double)__uint_as_float((uint32_t)h.y << 16);
-        const double d2 = (double)v.z - (double)__uint_as_float((uint32_t)h.z << 16);
-        const double d3 = (double)v.w - (double)__uint_as_float((uint32_t)h.w << 16);
+        const double d0 = (double)v.x - bf16_used(h.x);
+        const double d1 = (double)v.y - bf16_used(h.y);
+        const double d2 = (double)v.z - bf16_used(h.z);
+        const double d3 = (double)v.w - bf16_used(h.w);
         dl += d0 * d0 + d1 * d1 + d2 * d2 + d3 * d3;
       }
       s += (double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z + (double)v.w * v.w;
@@ -655,7 +665,7 @@ __device__ void init_column(const WorkView &w, int64_t b, const float *__restric
       if (w.R16 && !w.fp16) {
         const uint16_t h = f32_to_bf16_rne(vz);
         w.R16[b * w.Mp + m] = h;
-        const double dv = (double)vz - (double)__uint_as_float((uint32_t)h << 16);
+        const double dv = (double)vz - bf16_used(h);
         dl += dv * dv;
       }
       s += (double)vz * (double)vz;
@@ -676,7 +686,7 @@ __device__ void init_column(const WorkView &w, int64_t b, const float *__restric
       v = isfinite(v) ? v : 0.f;
       const uint16_t h = f32_to_f16_rne(v * sig);
       w.R16[b * w.Mp + m] = h;
-      const double dv = (double)v - (double)f16_to_f32(h) / (double)sig;
+      const double dv = (double)v - f16_used(h) / (double)sig;
       d16 += dv * dv;
     }
     dl = wave_sum(d16);
@@ -1828,10 +1838,10 @@ __global__ __launch_bounds__(256) void k_residual(DictView d, WorkView w, int LP
       h.z = f32_to_f16_rne(r.z * sig);
       h.w = f32_to_f16_rne(r.w * sig);
       reinterpret_cast<ushort4 *>(w.R16)[b * nc4 + c0 + c] = h;
-      const double e0 = (double)r.x - (double)f16_to_f32(h.x) / (double)sig;
-      const double e1 = (double)r.y - (double)f16_to_f32(h.y) / (double)sig;
-      const double e2 = (double)r.z - (double)f16_to_f32(h.z) / (double)sig;
-      const double e3 = (double)r.w - (double)f16_to_f32(h.w) / (double)sig;
+      const double e0 = (double)r.x - f16_used(h.x) / (double)sig;
+      const double e1 = (double)r.y - f16_used(h.y) / (double)sig;
+      const double e2 = (double)r.z - f16_used(h.z) / (double)sig;
+      const double e3 = (double)r.w - f16_used(h.w) / (double)sig;
       dlt += e0 * e0 + e1 * e1 + e2 * e2 + e3 * e3;
     } else if (BF16) {
       ushort4 h;
@@ -1840,10 +1850,10 @@ __global__ __launch_bounds__(256) void k_residual(DictView d, WorkView w, int LP
       h.z = f32_to_bf16_rne(r.z);
       h.w = f32_to_bf16_rne(r.w);
       reinterpret_cast<ushort4 *>(w.R16)[b * nc4 + c0 + c] = h;
-      const double e0 = (double)r.x - (double)__uint_as_float((uint32_t)h.x << 16);
-      const double e1 = (double)r.y - (double)__uint_as_float((uint32_t)h.y << 16);
-      const double e2 = (double)r.z - (double)__uint_as_float((uint32_t)h.z << 16);
-      const double e3 = (double)r.w - (double)__uint_as_float((uint32_t)h.w << 16);
+      const double e0 = (double)r.x - bf16_used(h.x);
+      const double e1 = (double)r.y - bf16_used(h.y);
+      const double e2 = (double)r.z - bf16_used(h.z);
+      const double e3 = (double)r.w - bf16_used(h.w);
       dlt += e0 * e0 + e1 * e1 + e2 * e2 + e3 * e3;
     }
     nrm += (double)r.x * r.x + (double)r.y * r.y + (double)r.z * r.z + (double)r.w * r.w;
