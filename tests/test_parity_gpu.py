@@ -780,3 +780,54 @@ def test_gram_domain_automatic_choice(M, N):
     for k in ("support", "coef", "status", "rnorm"):
         assert torch.equal(getattr(auto, k), getattr(want, k)), k
 
+
+
+@pytest.mark.parametrize("form", FORMS + ["fp16"])
+def test_metamorphic_relations_hold_bit_for_bit(form):
+    """Relations that the method satisfies exactly and that scaling by powers of two and
+    relabelling keep exact in floating point as well, so every form must reproduce them
+    bit for bit: scaling atom n by 2^e_n leaves the supports unchanged and divides its
+    coefficient by 2^e_n (the paper's normalisation remark); scaling every signal by 2^e
+    scales the coefficients and residual norms by 2^e; permuting the atoms permutes the
+    supports (each correlation, Gram entry and projection is computed the same way
+    whatever the atom's position). Status bits are compared without the BF16/FP16 forms'
+    widening bit, which depends on how atoms fall into key subgroups."""
+    torch = _torch()
+    from paper_2407_06434_amd import omp, workloads
+    prec, kw = ("fp16", {}) if form == "fp16" else _form(form)
+    w = workloads.custom(96, 320, 160, 12, seed=29, k_true=12)
+    g = np.random.default_rng(30)
+    dev = torch.device("cuda:0")
+
+    def run(A, Y):
+        r = omp.solve(torch.from_numpy(np.ascontiguousarray(A)).to(dev), torch.from_numpy(np.ascontiguousarray(Y)).to(dev),
+                      w.S, precision=prec, dense=False, **kw)
+        torch.cuda.synchronize()
+        return {k: v.cpu().numpy() for k, v in r._asdict().items() if v is not None}
+
+    print(f"case metamorphic relations {form}", flush=True)
+    base = run(w.A, w.Y)
+    mask = ~np.int32(omp.SIG_WIDENED)
+    # column scaling by powers of two
+    e = g.integers(-3, 4, size=w.N)
+    sc = run(w.A * np.ldexp(1.0, e)[:, None].astype(np.float32), w.Y)
+    assert np.array_equal(sc["support"], base["support"])
+    sup = base["support"]
+    want = np.where(sup >= 0, base["coef"] * np.ldexp(1.0, -e[np.maximum(sup, 0)]), 0.0).astype(np.float32)
+    assert np.array_equal(sc["coef"], want)
+    assert np.array_equal(sc["rnorm"], base["rnorm"])
+    assert np.array_equal(sc["status"] & mask, base["status"] & mask)
+    # signal scaling by a power of two
+    sy = run(w.A, w.Y * np.float32(8.0))
+    assert np.array_equal(sy["support"], base["support"])
+    assert np.array_equal(sy["coef"], base["coef"] * np.float32(8.0))
+    assert np.array_equal(sy["rnorm"], base["rnorm"] * np.float32(8.0))
+    # atom permutation
+    perm = g.permutation(w.N)
+    inv = np.argsort(perm)
+    pa = run(w.A[perm], w.Y)
+    mapped = np.where(pa["support"] >= 0, perm[np.maximum(pa["support"], 0)], -1)
+    assert np.array_equal(mapped, base["support"])
+    assert np.array_equal(pa["coef"], base["coef"])
+    assert np.array_equal(pa["status"] & mask, base["status"] & mask)
+    del inv
