@@ -113,6 +113,19 @@ __device__ inline void xcd_tile(int b, int nta, int ntb, int *tn, int *tb) {
 //   atoms marked invalid (bit 31 set; s >= 0 leaves that bit free), so the third
 //   key still bounds every atom of the subgroup that is not listed.
 // ---------------------------------------------------------------------------
+// LDS of the correlation kernel: the main loop's two operand buffers, then (BF16
+// and FP16 select) 1/||a|| of the tile's TN atoms and the TN/32 selected-atom
+// mask words of each of its TB signals.
+template <class T>
+struct SelectLds {
+  static constexpr int MAIN_CHUNKS = 2 * T::STAGE;
+  static constexpr int IV_CHUNKS = T::TN / 4;      // TN floats
+  static constexpr int MASK_CPS = T::TN / 128;     // 16-byte chunks of mask words per signal
+  static constexpr int MASK_CHUNKS = T::TB * MASK_CPS;
+  static constexpr size_t BYTES = (size_t)(MAIN_CHUNKS + IV_CHUNKS + MASK_CHUNKS) * 16;
+  static_assert(IV_CHUNKS <= 64 && T::TN % 128 == 0 && MASK_CHUNKS % 64 == 0, "one load per 64 chunks");
+};
+
 template <class Op, class T, bool TOP2, bool SECOND = false>
 __global__ __launch_bounds__(T::NTHR) void k_corr_select(
     const typename Op::elem *__restrict__ Aop, const typename Op::elem *__restrict__ Rop, int64_t Mp,
@@ -133,26 +146,44 @@ __global__ __launch_bounds__(T::NTHR) void k_corr_select(
   const int64_t rs = Mp / EPC;
   const u32x4 *P = reinterpret_cast<const u32x4 *>(Aop) + (int64_t)tn * T::TN * rs;
   const u32x4 *Q = reinterpret_cast<const u32x4 *>(Rop) + b0 * rs;
-  f32x16 acc[T::FN][T::FB];
-  mainloop<Op, T>(P, rs, Q, rs, (int)(rs / T::CH), lds, acc);
-
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wn = wave % T::WN, wb = wave / T::WN;
   const int h = lane >> 5;
   const int64_t mwords = Np / 32;
   const int64_t nw0 = (int64_t)tn * T::TN + wn * T::FN * 32;  // first atom of this wavefront's rows
 
+  // BF16 / FP16 select: the epilogue's inputs that do not depend on the product,
+  // 1/||a|| of the tile's atoms and the tile's selected-atom mask words of every
+  // signal, are loaded into LDS behind the operand buffers before the main loop
+  // (they land with its first slice), so the epilogue reads them from LDS.
+  u32x4 *const ex = lds + SelectLds<T>::MAIN_CHUNKS;
+  if (TOP2) {
+    using X = SelectLds<T>;
+    if (wave == 0 && lane < X::IV_CHUNKS)
+      dma16(inv_nu + (int64_t)tn * T::TN + 4 * lane, (lds_void_t *)ex);
+    for (int c0 = wave * 64; c0 < X::MASK_CHUNKS; c0 += T::NW * 64) {
+      const int c = c0 + lane, t = c / X::MASK_CPS, part16 = c % X::MASK_CPS;
+      dma16(mask + (b0 + t) * mwords + (int64_t)tn * (T::TN / 32) + 4 * part16,
+            (lds_void_t *)(ex + X::IV_CHUNKS + c0));
+    }
+  }
+  f32x16 acc[T::FN][T::FB];
+  mainloop<Op, T>(P, rs, Q, rs, (int)(rs / T::CH), lds, acc);
+
   if (TOP2) {
     constexpr int SUBF = T::FN >= 2 ? 2 : 1;  // fragments per subgroup
     constexpr int SPH = T::FN / SUBF;         // subgroups per lane
     constexpr int KPT = T::WN * SPH * 2 * NKEEP;
+    const float *ivl = reinterpret_cast<const float *>(ex);                            // [TN]
+    const uint32_t *mwl = reinterpret_cast<const uint32_t *>(ex + SelectLds<T>::IV_CHUNKS);  // [TB][TN / 32]
+    const int a0 = wn * T::FN * 32;  // first atom of this wavefront's rows within the tile
     // 1/||a|| of the lane's rows (the same for every signal column).
     float iv[T::FN][16];
 #pragma unroll
     for (int i = 0; i < T::FN; ++i)
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
-        const float4 v = *reinterpret_cast<const float4 *>(inv_nu + nw0 + i * 32 + 8 * g + 4 * h);
+        const float4 v = *reinterpret_cast<const float4 *>(ivl + a0 + i * 32 + 8 * g + 4 * h);
         iv[i][4 * g + 0] = v.x;
         iv[i][4 * g + 1] = v.y;
         iv[i][4 * g + 2] = v.z;
@@ -173,13 +204,12 @@ __global__ __launch_bounds__(T::NTHR) void k_corr_select(
 #pragma unroll
     for (int j = 0; j < T::FB; ++j) {
       const int jt = wb * T::FB * 32 + j * 32 + (lane & 31);  // signal within the tile
-      const int64_t b = b0 + jt;
       // selected-atom bits of this signal for the wavefront's FN * 32 atoms
       uint32_t mw[T::FN];
       {
-        const uint32_t *mrow = mask + b * mwords + (nw0 >> 5);
+        const uint32_t *mrow = mwl + jt * (T::TN / 32) + (a0 >> 5);
         if (T::FN == 4) {
-          const uint4 v = *reinterpret_cast<const uint4 *>(mrow);
+          const uint4 v = *reinterpret_cast<const uint4 *>(mrow);  // 16-byte aligned: TN / 32 words per signal
           mw[0] = v.x;
           mw[T::FN > 1 ? 1 : 0] = v.y;
           mw[T::FN > 2 ? 2 : 0] = v.z;
@@ -218,15 +248,19 @@ __global__ __launch_bounds__(T::NTHR) void k_corr_select(
           const int row = 8 * (r >> 2) + 4 * h + (r & 3);
           const int64_t n = nw0 + (ig * SUBF + ii) * 32 + row;
           const uint32_t word = ii ? w1 : w0;
-          const bool valid = (all_rows_ok || inv_nu[n] > 0.f) && !((word >> row) & 1u);
+          const bool valid = (all_rows_ok || ivl[n - (int64_t)tn * T::TN] > 0.f) && !((word >> row) & 1u);
           stage[jt * KPT + ((wn * SPH + ig) * 2 + h) * NKEEP + q] = valid ? ks[q] : (ks[q] | 0x80000000u);
         }
       }
     }
     __syncthreads();
+    // one signal's KPT keys are 16-byte chunks of `part` (KPT is a multiple of 4)
+    static_assert(KPT % 4 == 0, "keys are written in 16-byte chunks");
+    constexpr int CPR = KPT / 4;
     uint32_t *dst = reinterpret_cast<uint32_t *>(part) + b0 * ((int64_t)ntile * KPT) + (int64_t)tn * KPT;
-    for (int t = threadIdx.x; t < T::TB * KPT; t += T::NTHR)
-      dst[(int64_t)(t / KPT) * ntile * KPT + t % KPT] = stage[t];
+    const u32x4 *stg = reinterpret_cast<const u32x4 *>(stage);
+    for (int t = threadIdx.x; t < T::TB * CPR; t += T::NTHR)
+      reinterpret_cast<u32x4 *>(dst + (int64_t)(t / CPR) * ntile * KPT)[t % CPR] = stg[t];
     return;
   }
 
@@ -307,11 +341,12 @@ template <class Op, class T, bool TOP2, bool SECOND = false>
 hipError_t launch_corr_t(const typename Op::elem *Aop, const typename Op::elem *Rop, const DictView &d,
                          const WorkView &w, hipStream_t st) {
   auto kern = k_corr_select<Op, T, TOP2, SECOND>;
-  hipError_t e = set_lds(kern, T::LDS_BYTES);
+  const size_t lds_bytes = TOP2 ? SelectLds<T>::BYTES : T::LDS_BYTES;
+  hipError_t e = set_lds(kern, lds_bytes);
   if (e != hipSuccess) return e;
   const int ntile = (int)(d.Np / T::TN);
   // the epilogue scores |c| by 1/||a_n|| (FP16 form: divided by the atom's storage scale)
-  hipLaunchKernelGGL(kern, dim3((unsigned)(ntile * (w.Bp / T::TB))), dim3(T::NTHR), T::LDS_BYTES, st, Aop, Rop,
+  hipLaunchKernelGGL(kern, dim3((unsigned)(ntile * (w.Bp / T::TB))), dim3(T::NTHR), lds_bytes, st, Aop, Rop,
                      d.Mp, d.Np, d.inv_nu_h ? d.inv_nu_h : d.inv_nu, w.mask, w.flags, w.part, ntile);
   return hipGetLastError();
 }
@@ -400,8 +435,8 @@ hipError_t launch_corr_cfg(const DictView &d, const WorkView &w, int precision, 
 
 template <class T>
 hipError_t prepare_corr_cfg(int precision, bool second) {
-  if (precision == OMP_PREC_BF16) return set_lds(k_corr_select<OpBF16, T, true>, T::LDS_BYTES);
-  if (precision == OMP_PREC_FP16) return set_lds(k_corr_select<OpF16, T, true>, T::LDS_BYTES);
+  if (precision == OMP_PREC_BF16) return set_lds(k_corr_select<OpBF16, T, true>, SelectLds<T>::BYTES);
+  if (precision == OMP_PREC_FP16) return set_lds(k_corr_select<OpF16, T, true>, SelectLds<T>::BYTES);
   if (second) return set_lds(k_corr_select<OpF32, T, false, true>, T::LDS_BYTES);
   return set_lds(k_corr_select<OpF32, T, false>, T::LDS_BYTES);
 }

@@ -83,13 +83,42 @@ struct Tile {
 // Slot of chunk c in staged row r.
 __device__ inline int lds_slot(int r, int c) { return c ^ ((r >> 1) & 7); }
 
+// One global-to-LDS load of 16 bytes per lane: lane l's 16 bytes from `g` land
+// in LDS chunk l after the wave-uniform address `l` (M0 holds that address).
+// Written as inline asm on purpose: the compiler counts its own LDS-DMA builtin
+// as an LDS access that may complete out of order, and then answers every later
+// LDS read with a full lgkmcnt(0) wait, which serialises the fragment reads of
+// the main loop against the MFMAs. Hidden from the compiler, these loads are
+// waited for explicitly (vmcnt) before the barrier that publishes them. M0 is
+// saved and restored around the load (the compiler may hold a value there); the
+// only register the asm writes is that scalar save slot, no load destination.
+__device__ inline void dma16(const void *g, lds_void_t *l) {
+  const uint32_t la = __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)l);
+  uint32_t saved;
+  asm volatile(
+      "s_mov_b32 %0, m0\n\t"
+      "s_mov_b32 m0, %2\n\t"
+      "s_nop 0\n\t"
+      "global_load_lds_dwordx4 %1, off\n\t"
+      "s_nop 0\n\t"
+      "s_mov_b32 m0, %0"
+      : "=&s"(saved)
+      : "v"(g), "s"(la)
+      : "memory");
+}
+
 // Main loop: acc += P_tile * Q_tile^T over `nslices` K slices of 128 bytes.
 // P points at the tile's first row, rows `prs` chunks apart; likewise Q.
 // Wavefront w stages rows 8 (i NW + w) .. +7 of every slice with its load i: a
 // load writes 64 consecutive LDS chunks (lane l -> chunk l), so lane l fetches
-// row 8 (i NW + w) + l/8, chunk lds_slot(row, l mod 8). The loads of slice s+1
-// are issued right after the barrier that opens slice s and land while slice s
-// is multiplied. Ends with a barrier, so the caller may reuse the LDS.
+// row 8 (i NW + w) + l/8, chunk lds_slot(row, l mod 8). Two LDS buffers: the
+// loads of slice s+2 are issued right after the barrier that ends slice s (its
+// buffer is then free). Fragments are double-buffered in registers: the LDS
+// reads of step q+1 are issued before the MFMAs of step q, and the slice barrier
+// sits between the two halves of a slice's last step, so the MFMA pipe keeps
+// working while the wavefronts meet. Loads the caller issued with dma16 before
+// the call have landed once the first barrier has passed. Ends with a barrier,
+// so the caller may reuse the LDS.
 template <class Op, class T>
 __device__ inline void mainloop(const u32x4 *__restrict__ P, int64_t prs, const u32x4 *__restrict__ Q,
                                 int64_t qrs, int nslices, u32x4 *lds, f32x16 (&acc)[T::FN][T::FB]) {
@@ -97,11 +126,19 @@ __device__ inline void mainloop(const u32x4 *__restrict__ P, int64_t prs, const 
   const int lane = tid & 63, wave = tid >> 6;
   const int wn = wave % T::WN, wb = wave / T::WN;
   const int h = lane >> 5, r32 = lane & 31;
+  constexpr int QS = T::CH / 2;         // MFMA steps per slice (32 bytes of K each)
+  constexpr int NM = T::FN * T::FB;     // MFMAs (fragment pairs) per step
+  constexpr int SPLIT = NM / 2;         // last step: MFMAs issued before the barrier
 
 #pragma unroll
   for (int i = 0; i < T::FN; ++i)
 #pragma unroll
     for (int j = 0; j < T::FB; ++j) acc[i][j] = f32x16{};
+  if (nslices <= 0) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    return;
+  }
 
   // Source of this lane's chunk for each of its loads, at slice 0.
   const u32x4 *src[T::LPW];
@@ -111,10 +148,12 @@ __device__ inline void mainloop(const u32x4 *__restrict__ P, int64_t prs, const 
     const int c = lds_slot(row, lane & 7);  // the slot map is an involution
     src[i] = row < T::TN ? P + (int64_t)row * prs + c : Q + (int64_t)(row - T::TN) * qrs + c;
   }
+  auto issue = [&](int s, int buf) {
 #pragma unroll
-  for (int i = 0; i < T::LPW; ++i)
-    __builtin_amdgcn_global_load_lds(reinterpret_cast<const void *>(src[i]),
-                                     (lds_void_t *)(lds + (i * T::NW + wave) * 64), 16, 0, 0);
+    for (int i = 0; i < T::LPW; ++i)
+      dma16(reinterpret_cast<const void *>(src[i] + (int64_t)s * T::CH),
+            (lds_void_t *)(lds + buf * T::STAGE + (i * T::NW + wave) * 64));
+  };
 
   // LDS offsets (chunks) of this lane's fragment rows and their slot swizzles.
   int aoff[T::FN], asw[T::FN], boff[T::FB], bsw[T::FB];
@@ -130,30 +169,50 @@ __device__ inline void mainloop(const u32x4 *__restrict__ P, int64_t prs, const 
     boff[j] = row * T::CH;
     bsw[j] = (row >> 1) & 7;
   }
-
-  for (int s = 0; s < nslices; ++s) {
-    const int buf = s & 1;
-    __builtin_amdgcn_s_waitcnt(0);  // this wavefront's loads of slice s have landed ...
-    __syncthreads();                // ... and everyone's; slice s-1 is no longer read
-    if (s + 1 < nslices) {
-#pragma unroll
-      for (int i = 0; i < T::LPW; ++i)
-        __builtin_amdgcn_global_load_lds(reinterpret_cast<const void *>(src[i] + (int64_t)(s + 1) * T::CH),
-                                         (lds_void_t *)(lds + (buf ^ 1) * T::STAGE + (i * T::NW + wave) * 64),
-                                         16, 0, 0);
-    }
+  u32x4 af[2][T::FN], bf[2][T::FB];
+  auto rd = [&](int buf, int q, int set) {
     const u32x4 *L = lds + buf * T::STAGE;
 #pragma unroll
-    for (int q = 0; q < T::CH / 2; ++q) {
-      u32x4 af[T::FN], bf[T::FB];
+    for (int i = 0; i < T::FN; ++i) af[set][i] = L[aoff[i] + ((2 * q + h) ^ asw[i])];
 #pragma unroll
-      for (int i = 0; i < T::FN; ++i) af[i] = L[aoff[i] + ((2 * q + h) ^ asw[i])];
+    for (int j = 0; j < T::FB; ++j) bf[set][j] = L[boff[j] + ((2 * q + h) ^ bsw[j])];
+  };
+
+  issue(0, 0);
+  __builtin_amdgcn_s_waitcnt(0);  // this wavefront's loads of slice 0 have landed ...
+  __syncthreads();                // ... and everyone's
+  if (nslices > 1) issue(1, 1);
+  rd(0, 0, 0);
+  for (int s = 0; s < nslices; ++s) {
+    const int buf = s & 1;
 #pragma unroll
-      for (int j = 0; j < T::FB; ++j) bf[j] = L[boff[j] + ((2 * q + h) ^ bsw[j])];
+    for (int q = 0; q < QS; ++q) {
+      const int cur = q & 1;
+      if (q + 1 < QS) {
+        rd(buf, q + 1, cur ^ 1);
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int i = 0; i < T::FN; ++i)
+        for (int t = 0; t < NM; ++t) Op::mma(af[cur][t / T::FB], bf[cur][t % T::FB], acc[t / T::FB][t % T::FB]);
+        __builtin_amdgcn_sched_barrier(0);
+      } else {
 #pragma unroll
-        for (int j = 0; j < T::FB; ++j) Op::mma(af[i], bf[j], acc[i][j]);
+        for (int t = 0; t < SPLIT; ++t) Op::mma(af[cur][t / T::FB], bf[cur][t % T::FB], acc[t / T::FB][t % T::FB]);
+        __builtin_amdgcn_sched_barrier(0);
+        if (s + 1 < nslices) {
+          // Slice s+1 (the only one in flight) must have landed everywhere, and
+          // every wavefront has read all of slice s (its last fragments are in
+          // registers), so slice s+2 may overwrite buffer s & 1.
+          __builtin_amdgcn_s_waitcnt(0);
+          __syncthreads();
+          rd(buf ^ 1, 0, cur ^ 1);
+          __builtin_amdgcn_sched_barrier(0);
+          if (s + 2 < nslices) issue(s + 2, buf);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int t = SPLIT; t < NM; ++t) Op::mma(af[cur][t / T::FB], bf[cur][t % T::FB], acc[t / T::FB][t % T::FB]);
+        __builtin_amdgcn_sched_barrier(0);
+      }
     }
   }
   __syncthreads();
