@@ -146,12 +146,6 @@ __global__ __launch_bounds__(T::NTHR) void k_corr_select(
   const int64_t rs = Mp / EPC;
   const u32x4 *P = reinterpret_cast<const u32x4 *>(Aop) + (int64_t)tn * T::TN * rs;
   const u32x4 *Q = reinterpret_cast<const u32x4 *>(Rop) + b0 * rs;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wn = wave % T::WN, wb = wave / T::WN;
-  const int h = lane >> 5;
-  const int64_t mwords = Np / 32;
-  const int64_t nw0 = (int64_t)tn * T::TN + wn * T::FN * 32;  // first atom of this wavefront's rows
-
   // BF16 / FP16 select: the epilogue's inputs that do not depend on the product,
   // 1/||a|| of the tile's atoms and the tile's selected-atom mask words of every
   // signal, are loaded into LDS behind the operand buffers before the main loop
@@ -159,16 +153,22 @@ __global__ __launch_bounds__(T::NTHR) void k_corr_select(
   u32x4 *const ex = lds + SelectLds<T>::MAIN_CHUNKS;
   if (TOP2) {
     using X = SelectLds<T>;
-    if (wave == 0 && lane < X::IV_CHUNKS)
-      dma16(inv_nu + (int64_t)tn * T::TN + 4 * lane, (lds_void_t *)ex);
-    for (int c0 = wave * 64; c0 < X::MASK_CHUNKS; c0 += T::NW * 64) {
-      const int c = c0 + lane, t = c / X::MASK_CPS, part16 = c % X::MASK_CPS;
-      dma16(mask + (b0 + t) * mwords + (int64_t)tn * (T::TN / 32) + 4 * part16,
+    const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (wv == 0 && l < X::IV_CHUNKS) dma16(inv_nu + (int64_t)tn * T::TN + 4 * l, (lds_void_t *)ex);
+    for (int c0 = wv * 64; c0 < X::MASK_CHUNKS; c0 += T::NW * 64) {
+      const int c = c0 + l, t = c / X::MASK_CPS, part16 = c % X::MASK_CPS;
+      dma16(mask + (b0 + t) * (Np / 32) + (int64_t)tn * (T::TN / 32) + 4 * part16,
             (lds_void_t *)(ex + X::IV_CHUNKS + c0));
     }
   }
   f32x16 acc[T::FN][T::FB];
   mainloop<Op, T>(P, rs, Q, rs, (int)(rs / T::CH), lds, acc);
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wn = wave % T::WN, wb = wave / T::WN;
+  const int h = lane >> 5;
+  const int64_t mwords = Np / 32;
+  const int64_t nw0 = (int64_t)tn * T::TN + wn * T::FN * 32;  // first atom of this wavefront's rows
 
   if (TOP2) {
     constexpr int SUBF = T::FN >= 2 ? 2 : 1;  // fragments per subgroup

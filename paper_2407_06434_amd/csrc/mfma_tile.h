@@ -7,7 +7,8 @@
 // owns FN x FB fragments of 32 x 32 (v_mfma_f32_32x32x2f32 for FP32,
 // v_mfma_f32_32x32x16_bf16 for BF16, v_mfma_f32_32x32x16_f16 for FP16). Operands are staged through LDS in
 // 128-byte K slices, double buffered, with direct global-to-LDS loads (16
-// bytes per lane, no register round trip). A staged row is 8 chunks of 16
+// bytes per lane, no register round trip); the 16-bit products also double-buffer
+// their fragments in registers (mainloop_pipelined). A staged row is 8 chunks of 16
 // bytes; chunk c of row r sits at slot c ^ ((r >> 1) & 7) of the row, so the
 // 16 lanes of one LDS read phase (16 consecutive rows, one chunk) hit 16
 // distinct 4-bank groups. Lane l of a fragment reads row (l mod 32) at chunk
@@ -107,11 +108,11 @@ __device__ inline void dma16(const void *g, lds_void_t *l) {
       : "memory");
 }
 
-// Main loop: acc += P_tile * Q_tile^T over `nslices` K slices of 128 bytes.
-// P points at the tile's first row, rows `prs` chunks apart; likewise Q.
-// Wavefront w stages rows 8 (i NW + w) .. +7 of every slice with its load i: a
-// load writes 64 consecutive LDS chunks (lane l -> chunk l), so lane l fetches
-// row 8 (i NW + w) + l/8, chunk lds_slot(row, l mod 8). Two LDS buffers: the
+// Pipelined main loop (16-bit operands): acc += P_tile * Q_tile^T over `nslices`
+// K slices of 128 bytes. P points at the tile's first row, rows `prs` chunks
+// apart; likewise Q. Wavefront w stages rows 8 (i NW + w) .. +7 of every slice
+// with its load i: a load writes 64 consecutive LDS chunks (lane l -> chunk l),
+// so lane l fetches row 8 (i NW + w) + l/8, chunk lds_slot(row, l mod 8). Two LDS buffers: the
 // loads of slice s+2 are issued right after the barrier that ends slice s (its
 // buffer is then free). Fragments are double-buffered in registers: the LDS
 // reads of step q+1 are issued before the MFMAs of step q, and the slice barrier
@@ -120,8 +121,8 @@ __device__ inline void dma16(const void *g, lds_void_t *l) {
 // the call have landed once the first barrier has passed. Ends with a barrier,
 // so the caller may reuse the LDS.
 template <class Op, class T>
-__device__ inline void mainloop(const u32x4 *__restrict__ P, int64_t prs, const u32x4 *__restrict__ Q,
-                                int64_t qrs, int nslices, u32x4 *lds, f32x16 (&acc)[T::FN][T::FB]) {
+__device__ inline void mainloop_pipelined(const u32x4 *__restrict__ P, int64_t prs, const u32x4 *__restrict__ Q,
+                                          int64_t qrs, int nslices, u32x4 *lds, f32x16 (&acc)[T::FN][T::FB]) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wn = wave % T::WN, wb = wave / T::WN;
@@ -216,6 +217,95 @@ __device__ inline void mainloop(const u32x4 *__restrict__ P, int64_t prs, const 
     }
   }
   __syncthreads();
+}
+
+// Serial main loop (FP32 operands): acc += P_tile * Q_tile^T over `nslices` K
+// slices of 128 bytes. P points at the tile's first row, rows `prs` chunks apart; likewise Q.
+// Wavefront w stages rows 8 (i NW + w) .. +7 of every slice with its load i: a
+// load writes 64 consecutive LDS chunks (lane l -> chunk l), so lane l fetches
+// row 8 (i NW + w) + l/8, chunk lds_slot(row, l mod 8). The loads of slice s+1
+// are issued right after the barrier that opens slice s and land while slice s
+// is multiplied. Each step's fragments are read and then multiplied. The FP32
+// product is bound by its MFMAs (four per 16-byte chunk), and there this loop
+// is faster than the pipelined one above. Ends with a barrier, so the caller may
+// reuse the LDS.
+template <class Op, class T>
+__device__ inline void mainloop_serial(const u32x4 *__restrict__ P, int64_t prs, const u32x4 *__restrict__ Q,
+                                       int64_t qrs, int nslices, u32x4 *lds, f32x16 (&acc)[T::FN][T::FB]) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wn = wave % T::WN, wb = wave / T::WN;
+  const int h = lane >> 5, r32 = lane & 31;
+
+#pragma unroll
+  for (int i = 0; i < T::FN; ++i)
+#pragma unroll
+    for (int j = 0; j < T::FB; ++j) acc[i][j] = f32x16{};
+
+  // Source of this lane's chunk for each of its loads, at slice 0.
+  const u32x4 *src[T::LPW];
+#pragma unroll
+  for (int i = 0; i < T::LPW; ++i) {
+    const int row = (i * T::NW + wave) * 8 + (lane >> 3);
+    const int c = lds_slot(row, lane & 7);  // the slot map is an involution
+    src[i] = row < T::TN ? P + (int64_t)row * prs + c : Q + (int64_t)(row - T::TN) * qrs + c;
+  }
+#pragma unroll
+  for (int i = 0; i < T::LPW; ++i)
+    __builtin_amdgcn_global_load_lds(reinterpret_cast<const void *>(src[i]),
+                                     (lds_void_t *)(lds + (i * T::NW + wave) * 64), 16, 0, 0);
+
+  // LDS offsets (chunks) of this lane's fragment rows and their slot swizzles.
+  int aoff[T::FN], asw[T::FN], boff[T::FB], bsw[T::FB];
+#pragma unroll
+  for (int i = 0; i < T::FN; ++i) {
+    const int row = wn * T::FN * 32 + i * 32 + r32;
+    aoff[i] = row * T::CH;
+    asw[i] = (row >> 1) & 7;
+  }
+#pragma unroll
+  for (int j = 0; j < T::FB; ++j) {
+    const int row = T::TN + wb * T::FB * 32 + j * 32 + r32;
+    boff[j] = row * T::CH;
+    bsw[j] = (row >> 1) & 7;
+  }
+
+  for (int s = 0; s < nslices; ++s) {
+    const int buf = s & 1;
+    __builtin_amdgcn_s_waitcnt(0);  // this wavefront's loads of slice s have landed ...
+    __syncthreads();                // ... and everyone's; slice s-1 is no longer read
+    if (s + 1 < nslices) {
+#pragma unroll
+      for (int i = 0; i < T::LPW; ++i)
+        __builtin_amdgcn_global_load_lds(reinterpret_cast<const void *>(src[i] + (int64_t)(s + 1) * T::CH),
+                                         (lds_void_t *)(lds + (buf ^ 1) * T::STAGE + (i * T::NW + wave) * 64),
+                                         16, 0, 0);
+    }
+    const u32x4 *L = lds + buf * T::STAGE;
+#pragma unroll
+    for (int q = 0; q < T::CH / 2; ++q) {
+      u32x4 af[T::FN], bf[T::FB];
+#pragma unroll
+      for (int i = 0; i < T::FN; ++i) af[i] = L[aoff[i] + ((2 * q + h) ^ asw[i])];
+#pragma unroll
+      for (int j = 0; j < T::FB; ++j) bf[j] = L[boff[j] + ((2 * q + h) ^ bsw[j])];
+#pragma unroll
+      for (int i = 0; i < T::FN; ++i)
+#pragma unroll
+        for (int j = 0; j < T::FB; ++j) Op::mma(af[i], bf[j], acc[i][j]);
+    }
+  }
+  __syncthreads();
+}
+
+// The main loop of every product: pipelined for 16-bit operands, serial for FP32.
+template <class Op, class T>
+__device__ inline void mainloop(const u32x4 *__restrict__ P, int64_t prs, const u32x4 *__restrict__ Q,
+                                int64_t qrs, int nslices, u32x4 *lds, f32x16 (&acc)[T::FN][T::FB]) {
+  if constexpr (sizeof(typename Op::elem) == 4)
+    mainloop_serial<Op, T>(P, prs, Q, qrs, nslices, lds, acc);
+  else
+    mainloop_pipelined<Op, T>(P, prs, Q, qrs, nslices, lds, acc);
 }
 
 // Row of a 32x32 MFMA result held by (lane, register r): the column is lane % 32.

@@ -248,30 +248,22 @@ __device__ inline void wave_lds_sync() {
 // Queue of atoms to re-score against r, flushed two at a time (all values
 // wave-uniform; a pick has about two candidates on the benchmark workload).
 // A flush fetches, in one round with the dot products, each candidate's
-// ||a_n||^2 and Gram row G[n, support] (lane holds rows i = lane + 64 p), so
-// that whichever candidate wins, the solve needs no further memory round.
-// Keeps the best exact score, its atom, its signed a^T r, ||a||^2 and Gram row.
-template <int RPL>
+// ||a_n||^2. Keeps the best exact score, its atom, its signed a^T r and
+// ||a||^2. The winner's Gram row is read after the pick: fetching every
+// candidate's row in the re-score round instead saves that round but reads
+// about twice the Gram lines, and measured 2.7% slower on the benchmark step.
 struct RescoreQueue {
   int n0 = -1, n1 = -1;
   double bs = -1.0;
   double bs2 = -1.0;  // best exact score of any other atom (near-tie flagging)
   double bar = 0.0, bnu2 = 0.0;
   int bn = 0x7fffffff;
-  float bg[RPL];
-  bool gram = true;  // false: the winner's Gram row is computed after the pick
   template <int NA>
   __device__ __attribute__((always_inline)) void rescore(const DictView &d, const float4 *r4, const int (&n)[NA],
-                                                         const int (&si)[RPL], int k, int lane) {
+                                                         int lane) {
     double nu2[NA];
-    float gc[NA][RPL];
 #pragma unroll
-    for (int i = 0; i < NA; ++i) {
-      nu2[i] = n[i] >= 0 ? d.nu2[n[i]] : 1.0;
-#pragma unroll
-      for (int p = 0; p < RPL; ++p)
-        gc[i][p] = (gram && n[i] >= 0 && lane + 64 * p < k) ? d.G[(int64_t)n[i] * d.Np + si[p]] : 0.f;
-    }
+    for (int i = 0; i < NA; ++i) nu2[i] = n[i] >= 0 ? d.nu2[n[i]] : 1.0;
     double ar[NA];
     atom_dots<NA, 2>(d, n, r4, lane, ar);
 #pragma unroll
@@ -284,32 +276,28 @@ struct RescoreQueue {
         bn = n[i];
         bar = ar[i];
         bnu2 = nu2[i];
-#pragma unroll
-        for (int p = 0; p < RPL; ++p) bg[p] = gc[i][p];
       } else if (n[i] != bn && sc > bs2) {
         bs2 = sc;
       }
     }
   }
-  __device__ __attribute__((always_inline)) void flush(const DictView &d, const float4 *r4, const int (&si)[RPL],
-                                                       int k, int lane) {
+  __device__ __attribute__((always_inline)) void flush(const DictView &d, const float4 *r4, int lane) {
     if (n0 < 0) return;
     if (n1 < 0) {  // a single atom: half the loads and dot products
       const int n[1] = {n0};
-      rescore<1>(d, r4, n, si, k, lane);
+      rescore<1>(d, r4, n, lane);
     } else {
       const int n[2] = {n0, n1};
-      rescore<2>(d, r4, n, si, k, lane);
+      rescore<2>(d, r4, n, lane);
     }
     n0 = n1 = -1;
   }
-  __device__ __attribute__((always_inline)) void push(int atom, const DictView &d, const float4 *r4,
-                                                      const int (&si)[RPL], int k, int lane) {
+  __device__ __attribute__((always_inline)) void push(int atom, const DictView &d, const float4 *r4, int lane) {
     if (n0 < 0) {
       n0 = atom;
     } else {
       n1 = atom;
-      flush(d, r4, si, k, lane);
+      flush(d, r4, lane);
     }
   }
 };
@@ -451,13 +439,12 @@ __device__ void gram_row_from_atoms(const DictView &d, int nstar, const int (&si
 //      can open: they are listed while the keys are scanned for step 1 and
 //      tested against s_w afterwards.
 // The result is the exact argmax of s over the selectable atoms, ties to the
-// lowest index; *cdot, *nu2 and g receive a_n*^T r, ||a_n*||^2 and the Gram
-// row G[n*, support] of the pick (fetched in the same round as its score).
-// kv holds the signal's keys when kreg (read in the first memory round).
-template <int RPL>
+// lowest index; *cdot and *nu2 receive a_n*^T r and ||a_n*||^2 of the pick
+// (fetched in the same round as its score). kv holds the signal's keys when
+// kreg (read in the first memory round).
 __device__ int select_bf16(const DictView &d, const WorkView &w, int64_t b, float smax_key, double ks, double tau,
-                           const int (&si)[RPL], int k, int lane, int *widened, double *cdot, double *nu2,
-                           float (&g)[RPL], int *clist, const uint32_t (&kv)[KREG], bool kreg, int *neartie) {
+                           int lane, int *widened, double *cdot, double *nu2, int *clist,
+                           const uint32_t (&kv)[KREG], bool kreg, int *neartie) {
   // Key scores carry the scale ks of the 16-bit residual copy (1 in the BF16 form, a
   // power of two in the FP16 form): a score s is stored as ks s, exactly.
   const double smax = (double)smax_key / ks;
@@ -476,8 +463,7 @@ __device__ int select_bf16(const DictView &d, const WorkView &w, int64_t b, floa
   const uint32_t thr_bits = float_bits_floor(thr * ks);
   const uint32_t mthr_bits = float_bits_floor(mthr / (1.0 + et) * (1.0 - 1e-12) * ks);
   int *mlist = clist + solve_cand_len(nkeys);
-  RescoreQueue<RPL> q;
-  q.gram = !w.gram_fly;
+  RescoreQueue q;
   // Candidates and possibly open subgroups, from the keys in registers or, for
   // more keys than that, read again KREG per lane at a time.
   int ncand = 0, nmaybe = 0;
@@ -498,9 +484,9 @@ __device__ int select_bf16(const DictView &d, const WorkView &w, int64_t b, floa
   wave_lds_sync();
   for (int i = 0; i < ncand; ++i) {
     const int e = __builtin_amdgcn_readfirstlane(clist[i]);
-    q.push(key_atom(w, e >> 5, e & 31), d, r4, si, k, lane);
+    q.push(key_atom(w, e >> 5, e & 31), d, r4, lane);
   }
-  q.flush(d, r4, si, k, lane);
+  q.flush(d, r4, lane);
 
   // The listed subgroups (all bounding keys if the list overflowed) against
   // the exact winner; an open subgroup is re-scored whole.
@@ -523,15 +509,13 @@ __device__ int select_bf16(const DictView &d, const WorkView &w, int64_t b, floa
         for (int e = 0; e < 4; ++e) {
           const int n = tile * w.tile_atoms + wn * w.wave_atoms + 32 * (ig * w.sub_frags + ii) + 8 * g4 + 4 * hh + e;
           if (d.inv_nu[n] <= 0.f || ((mk[n >> 5] >> (n & 31)) & 1u)) continue;
-          q.push(n, d, r4, si, k, lane);
+          q.push(n, d, r4, lane);
         }
-    q.flush(d, r4, si, k, lane);
+    q.flush(d, r4, lane);
   }
   *cdot = q.bar;
   *nu2 = q.bnu2;
   *neartie = (w.flag_ties && q.bs2 >= (1.0 - TIE_REL) * q.bs) ? 1 : 0;
-#pragma unroll
-  for (int p = 0; p < RPL; ++p) g[p] = q.bg[p];
   return q.bn == 0x7fffffff ? -1 : q.bn;
 }
 
@@ -943,9 +927,10 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
 
   // ... and the pick: the best key over all atom tiles (largest score, then
   // lowest index), or in the BF16 form the certified exact re-score of the
-  // candidates; cdot = a_n*^T r (exact products, FP64 sum). In the FP32 form
-  // the Gram row of the pick, g_i = G[n*, support_i] (lane holds rows
-  // i = lane + 64 p), and ||a_n*||^2 are fetched in this same round.
+  // candidates; cdot = a_n*^T r (exact products, FP64 sum). The Gram row of the
+  // pick, g_i = G[n*, support_i] (lane holds rows i = lane + 64 p), and
+  // ||a_n*||^2 are fetched in this same round in the FP32 form; in the BF16
+  // form the row is read once the re-score has decided the pick.
   int nstar;
   int widened = 0;
   double cdot = 0.0, nu2 = 0.0;
@@ -954,8 +939,8 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
   if (BF16) {
     const double tau = bf16_tau(rn, sqrt(wave_sum(pd)), (double)d.aerr_max[0], d.Mp);
     int neartie = 0;
-    nstar = select_bf16<RPL>(d, w, b, __uint_as_float((uint32_t)(kmax >> 32)), ks, tau, si, k, lane, &widened,
-                             &cdot, &nu2, g, clist, kv, kreg, &neartie);
+    nstar = select_bf16(d, w, b, __uint_as_float((uint32_t)(kmax >> 32)), ks, tau, lane, &widened, &cdot, &nu2,
+                        clist, kv, kreg, &neartie);
     // FP16 form: the next residual copy is scaled by ||r_k||, which bounds ||r_k+1||
     if (w.fp16 && lane == 0) w.rscale_next[b] = pow2_scale(rn);
     if (nstar < 0) {
@@ -978,7 +963,15 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
       cdot = ar[0];
     }
   }
-  if (w.gram_fly) gram_row_from_atoms<RPL>(d, nstar, si, k, lane, g);
+  if (w.gram_fly) {
+    gram_row_from_atoms<RPL>(d, nstar, si, k, lane, g);
+  } else if (BF16) {  // the pick's Gram row, now that the pick is known
+#pragma unroll
+    for (int p = 0; p < RPL; ++p) {
+      const int i = lane + 64 * p;
+      g[p] = i < k ? d.G[(int64_t)nstar * d.Np + si[p]] : 0.f;
+    }
+  }
   // beta = a_n*^T y = a_n*^T r + sum_j G[n*, s_j] x_j (r = y - A_{k-1} x_{k-1})
   double gx = 0.0;
 #pragma unroll
