@@ -227,6 +227,52 @@ __device__ __attribute__((always_inline)) inline void atom_dots(const DictView &
   for (int i = 0; i < NA; ++i) av[i] = wave_sum(av[i]);
 }
 
+// The residual's chunks a lane holds in registers when the solve reads r in
+// its first memory round (M <= 64 * 4 * RREG).
+constexpr int RREG = 4;
+
+// atom_dots with the vector already in registers: lane l holds chunks
+// l + 64 q (q < RREG) of v, zero past the end (requires M <= 64 * 4 * RREG).
+// The atoms' chunks are loaded CP at a time.
+template <int NA, int CP>
+__device__ __attribute__((always_inline)) inline void atom_dots_reg(const DictView &d, const int (&n)[NA],
+                                                                    const float4 (&vr)[RREG], int lane,
+                                                                    double (&av)[NA]) {
+  static_assert(RREG % CP == 0, "whole passes");
+  const int64_t nc4 = d.Mp / 4;
+  const float4 *A4 = reinterpret_cast<const float4 *>(d.A32);
+  int64_t row[NA];
+  bool use[NA];
+#pragma unroll
+  for (int i = 0; i < NA; ++i) {
+    use[i] = n[i] >= 0;
+    row[i] = (int64_t)(use[i] ? n[i] : 0) * nc4;
+    av[i] = 0.0;
+  }
+#pragma unroll
+  for (int q0 = 0; q0 < RREG; q0 += CP) {
+    float4 aa[NA][CP];
+    bool ok[CP];
+#pragma unroll
+    for (int q = 0; q < CP; ++q) {
+      const int64_t c = lane + 64 * (q0 + q);
+      ok[q] = c < nc4;
+      const int64_t cs = ok[q] ? c : 0;
+#pragma unroll
+      for (int i = 0; i < NA; ++i) aa[i][q] = A4[row[i] + cs];
+    }
+#pragma unroll
+    for (int i = 0; i < NA; ++i)
+#pragma unroll
+      for (int q = 0; q < CP; ++q) {
+        const double pa = dot4d(aa[i][q], vr[q0 + q]);
+        av[i] += (use[i] && ok[q]) ? pa : 0.0;
+      }
+  }
+#pragma unroll
+  for (int i = 0; i < NA; ++i) av[i] = wave_sum(av[i]);
+}
+
 typedef __attribute__((address_space(3))) void lds_void_t;
 
 // Asynchronous global-to-LDS loads (gfx950 global_load_lds): lane l's element
@@ -252,20 +298,26 @@ __device__ inline void wave_lds_sync() {
 // ||a||^2. The winner's Gram row is read after the pick: fetching every
 // candidate's row in the re-score round instead saves that round but reads
 // about twice the Gram lines, and measured 2.7% slower on the benchmark step.
+template <bool RR>
 struct RescoreQueue {
+  const float4 *r4;          // the residual in memory ...
+  const float4 (&rr)[RREG];  // ... and in registers (RR)
+  __device__ RescoreQueue(const float4 *r, const float4 (&regs)[RREG]) : r4(r), rr(regs) {}
   int n0 = -1, n1 = -1;
   double bs = -1.0;
   double bs2 = -1.0;  // best exact score of any other atom (near-tie flagging)
   double bar = 0.0, bnu2 = 0.0;
   int bn = 0x7fffffff;
   template <int NA>
-  __device__ __attribute__((always_inline)) void rescore(const DictView &d, const float4 *r4, const int (&n)[NA],
-                                                         int lane) {
+  __device__ __attribute__((always_inline)) void rescore(const DictView &d, const int (&n)[NA], int lane) {
     double nu2[NA];
 #pragma unroll
     for (int i = 0; i < NA; ++i) nu2[i] = n[i] >= 0 ? d.nu2[n[i]] : 1.0;
     double ar[NA];
-    atom_dots<NA, 2>(d, n, r4, lane, ar);
+    if constexpr (RR)
+      atom_dots_reg<NA, 2>(d, n, rr, lane, ar);
+    else
+      atom_dots<NA, 2>(d, n, r4, lane, ar);
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
       if (n[i] < 0) continue;
@@ -281,23 +333,23 @@ struct RescoreQueue {
       }
     }
   }
-  __device__ __attribute__((always_inline)) void flush(const DictView &d, const float4 *r4, int lane) {
+  __device__ __attribute__((always_inline)) void flush(const DictView &d, int lane) {
     if (n0 < 0) return;
     if (n1 < 0) {  // a single atom: half the loads and dot products
       const int n[1] = {n0};
-      rescore<1>(d, r4, n, lane);
+      rescore<1>(d, n, lane);
     } else {
       const int n[2] = {n0, n1};
-      rescore<2>(d, r4, n, lane);
+      rescore<2>(d, n, lane);
     }
     n0 = n1 = -1;
   }
-  __device__ __attribute__((always_inline)) void push(int atom, const DictView &d, const float4 *r4, int lane) {
+  __device__ __attribute__((always_inline)) void push(int atom, const DictView &d, int lane) {
     if (n0 < 0) {
       n0 = atom;
     } else {
       n1 = atom;
-      flush(d, r4, lane);
+      flush(d, lane);
     }
   }
 };
@@ -442,9 +494,10 @@ __device__ void gram_row_from_atoms(const DictView &d, int nstar, const int (&si
 // lowest index; *cdot and *nu2 receive a_n*^T r and ||a_n*||^2 of the pick
 // (fetched in the same round as its score). kv holds the signal's keys when
 // kreg (read in the first memory round).
+template <bool RR>
 __device__ int select_bf16(const DictView &d, const WorkView &w, int64_t b, float smax_key, double ks, double tau,
                            int lane, int *widened, double *cdot, double *nu2, int *clist,
-                           const uint32_t (&kv)[KREG], bool kreg, int *neartie) {
+                           const uint32_t (&kv)[KREG], bool kreg, const float4 (&rr)[RREG], int *neartie) {
   // Key scores carry the scale ks of the 16-bit residual copy (1 in the BF16 form, a
   // power of two in the FP16 form): a score s is stored as ks s, exactly.
   const double smax = (double)smax_key / ks;
@@ -463,7 +516,7 @@ __device__ int select_bf16(const DictView &d, const WorkView &w, int64_t b, floa
   const uint32_t thr_bits = float_bits_floor(thr * ks);
   const uint32_t mthr_bits = float_bits_floor(mthr / (1.0 + et) * (1.0 - 1e-12) * ks);
   int *mlist = clist + solve_cand_len(nkeys);
-  RescoreQueue q;
+  RescoreQueue<RR> q(r4, rr);
   // Candidates and possibly open subgroups, from the keys in registers or, for
   // more keys than that, read again KREG per lane at a time.
   int ncand = 0, nmaybe = 0;
@@ -484,9 +537,9 @@ __device__ int select_bf16(const DictView &d, const WorkView &w, int64_t b, floa
   wave_lds_sync();
   for (int i = 0; i < ncand; ++i) {
     const int e = __builtin_amdgcn_readfirstlane(clist[i]);
-    q.push(key_atom(w, e >> 5, e & 31), d, r4, lane);
+    q.push(key_atom(w, e >> 5, e & 31), d, lane);
   }
-  q.flush(d, r4, lane);
+  q.flush(d, lane);
 
   // The listed subgroups (all bounding keys if the list overflowed) against
   // the exact winner; an open subgroup is re-scored whole.
@@ -509,9 +562,9 @@ __device__ int select_bf16(const DictView &d, const WorkView &w, int64_t b, floa
         for (int e = 0; e < 4; ++e) {
           const int n = tile * w.tile_atoms + wn * w.wave_atoms + 32 * (ig * w.sub_frags + ii) + 8 * g4 + 4 * hh + e;
           if (d.inv_nu[n] <= 0.f || ((mk[n >> 5] >> (n & 31)) & 1u)) continue;
-          q.push(n, d, r4, lane);
+          q.push(n, d, lane);
         }
-    q.flush(d, r4, lane);
+    q.flush(d, lane);
   }
   *cdot = q.bar;
   *nu2 = q.bnu2;
@@ -786,7 +839,7 @@ __device__ inline void stop_signal(const WorkView &w, const SlotView &sv, int64_
   else if (lane == 0) w.flags[b] = fl;
 }
 
-template <int RPL, bool BF16, bool SLOTS>
+template <int RPL, bool BF16, bool SLOTS, bool RR>
 __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView w, SlotView sv) {
   extern __shared__ float smem[];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -825,6 +878,20 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
   // FP32 form: the largest valid 64-bit key (a valid key has a non-zero index
   // word). BF16 form: (score bits << 32) | 1 of the best valid 32-bit key.
   uint64_t kmax = 0;
+  // RR (M <= 1024, residual-vector forms): the residual is read in this round
+  // too, so the pick's exact scores need only the atoms.
+  const float4 *r4 = reinterpret_cast<const float4 *>(w.R32) + b * (d.Mp / 4);
+  float4 rr[RREG];
+#pragma unroll
+  for (int q = 0; q < RREG; ++q) {
+    if constexpr (RR) {
+      const int64_t c = lane + 64 * q;
+      const float4 v = r4[c < d.Mp / 4 ? c : 0];
+      rr[q] = c < d.Mp / 4 ? v : make_float4(0.f, 0.f, 0.f, 0.f);
+    } else {
+      rr[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  }
   // BF16 form: up to 64 KREG keys stay in registers for the pick
   uint32_t kv[KREG];
   const bool kreg = BF16 && nkeys <= 64 * KREG;
@@ -935,12 +1002,11 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
   int widened = 0;
   double cdot = 0.0, nu2 = 0.0;
   float g[RPL];
-  const float4 *r4 = reinterpret_cast<const float4 *>(w.R32) + b * (d.Mp / 4);
   if (BF16) {
     const double tau = bf16_tau(rn, sqrt(wave_sum(pd)), (double)d.aerr_max[0], d.Mp);
     int neartie = 0;
-    nstar = select_bf16(d, w, b, __uint_as_float((uint32_t)(kmax >> 32)), ks, tau, lane, &widened, &cdot, &nu2,
-                        clist, kv, kreg, &neartie);
+    nstar = select_bf16<RR>(d, w, b, __uint_as_float((uint32_t)(kmax >> 32)), ks, tau, lane, &widened, &cdot,
+                            &nu2, clist, kv, kreg, rr, &neartie);
     // FP16 form: the next residual copy is scaled by ||r_k||, which bounds ||r_k+1||
     if (w.fp16 && lane == 0) w.rscale_next[b] = pow2_scale(rn);
     if (nstar < 0) {
@@ -959,7 +1025,10 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
     if (!w.gram_dom) {  // the Gram-domain form keeps no residual vectors
       const int na[1] = {nstar};
       double ar[1];
-      atom_dots<1, 4>(d, na, r4, lane, ar);
+      if constexpr (RR)
+        atom_dots_reg<1, 4>(d, na, rr, lane, ar);
+      else
+        atom_dots<1, 4>(d, na, r4, lane, ar);
       cdot = ar[0];
     }
   }
@@ -1945,15 +2014,29 @@ __global__ __launch_bounds__(256) void k_densify(const int32_t *__restrict__ sup
   }
 }
 
+// The solve reads the residual into registers in its first memory round when
+// a lane's share fits (M <= 1024) and the form keeps residual vectors (not in
+// the slot scheduler's solve, whose retire-and-admit code would then leave
+// three wavefronts per SIMD instead of four).
+bool solve_rr(const DictView &d, const WorkView &w) { return !w.gram_dom && d.Mp <= 64 * 4 * RREG; }
+
 template <int RPL, bool BF16, bool SLOTS>
 hipError_t launch_solve_t(const DictView &d, const WorkView &w, const SlotView &sv, hipStream_t st) {
   const int nw = solve_waves(w);
   if (nw == 0) return hipErrorInvalidValue;  // rejected by the entry points' validation
   const size_t lds = solve_lds_per_wave(w) * nw;
-  hipError_t e = allow_lds(k_solve<RPL, BF16, SLOTS>, lds);
-  if (e != hipSuccess) return e;
   const unsigned blocks = (unsigned)((w.B + nw - 1) / nw);
-  hipLaunchKernelGGL((k_solve<RPL, BF16, SLOTS>), dim3(blocks), dim3(64 * nw), lds, st, d, w, sv);
+  if constexpr (!SLOTS) {
+    if (solve_rr(d, w)) {
+      hipError_t e = allow_lds(k_solve<RPL, BF16, false, true>, lds);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((k_solve<RPL, BF16, false, true>), dim3(blocks), dim3(64 * nw), lds, st, d, w, sv);
+      return hipGetLastError();
+    }
+  }
+  hipError_t e = allow_lds(k_solve<RPL, BF16, SLOTS, false>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_solve<RPL, BF16, SLOTS, false>), dim3(blocks), dim3(64 * nw), lds, st, d, w, sv);
   return hipGetLastError();
 }
 
@@ -2124,9 +2207,11 @@ hipError_t prepare_kernels(const DictView &d, const WorkView &w, int precision, 
   const size_t slds = solve_lds_per_wave(w) * (size_t)(solve_waves(w) > 0 ? solve_waves(w) : 1);
   const bool bf = is_half(precision);
   hipError_t e = hipSuccess;
-  if (w.S <= 64) e = bf ? allow_lds(k_solve<1, true, true>, slds) : allow_lds(k_solve<1, false, true>, slds);
-  else if (w.S <= 128) e = bf ? allow_lds(k_solve<2, true, true>, slds) : allow_lds(k_solve<2, false, true>, slds);
-  else e = bf ? allow_lds(k_solve<4, true, true>, slds) : allow_lds(k_solve<4, false, true>, slds);
+  if (w.S <= 64)
+    e = bf ? allow_lds(k_solve<1, true, true, false>, slds) : allow_lds(k_solve<1, false, true, false>, slds);
+  else if (w.S <= 128)
+    e = bf ? allow_lds(k_solve<2, true, true, false>, slds) : allow_lds(k_solve<2, false, true, false>, slds);
+  else e = bf ? allow_lds(k_solve<4, true, true, false>, slds) : allow_lds(k_solve<4, false, true, false>, slds);
   if (e != hipSuccess) return e;
   const size_t rlds = residual_lds(w, residual_lanes(w, lanes));
   e = bf ? allow_lds(k_residual<true>, rlds) : allow_lds(k_residual<false>, rlds);
