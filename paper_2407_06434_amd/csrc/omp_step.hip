@@ -1844,8 +1844,12 @@ __global__ __launch_bounds__(256) void k_residual(DictView d, WorkView w, int LP
   const int IPW = 64 / LP;
   const int items = 4 * IPW;
   const int S = w.S;
-  float *xs = reinterpret_cast<float *>(rsm);  // [items][S]: -x
-  int *ss = rsm + items * S;                   // [items][S]: support
+  // Rows of S + 1 words: the items of a wavefront read their j-th entries from
+  // distinct LDS banks (rows of S words would put them all in one bank for S a
+  // multiple of 64).
+  const int SP = S + 1;
+  float *xs = reinterpret_cast<float *>(rsm);  // [items][SP]: -x
+  int *ss = rsm + items * SP;                  // [items][SP]: support
   const int slice = blockIdx.x % w.nslice;
   const int64_t group = blockIdx.x / w.nslice;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1855,8 +1859,8 @@ __global__ __launch_bounds__(256) void k_residual(DictView d, WorkView w, int LP
   int kk = 0;
   if (b < w.B && (w.flags[b] & FLAG_NEWX)) kk = w.k[b];
   for (int j = sl; j < kk; j += LP) {
-    xs[item * S + j] = -w.xh[b * S + j];
-    ss[item * S + j] = w.sup[b * S + j];
+    xs[item * SP + j] = -w.xh[b * S + j];
+    ss[item * SP + j] = w.sup[b * S + j];
   }
   __syncthreads();
   if (kk == 0) return;  // after the only barrier
@@ -1867,8 +1871,8 @@ __global__ __launch_bounds__(256) void k_residual(DictView d, WorkView w, int LP
   const float4 *A4 = reinterpret_cast<const float4 *>(d.A32) + c0;
   const float4 *Y4 = reinterpret_cast<const float4 *>(w.Yp) + b * nc4 + c0;
   float4 *R4 = reinterpret_cast<float4 *>(w.R32) + b * nc4 + c0;
-  const float *xi = xs + item * S;
-  const int *si = ss + item * S;
+  const float *xi = xs + item * SP;
+  const int *si = ss + item * SP;
   double nrm = 0.0, dlt = 0.0;
   // FP16 form: the copy is fp16(sigma r) with the scale the solve chose from ||r|| before
   // this update (so |sigma r_m| <= 1)
@@ -2052,7 +2056,7 @@ hipError_t launch_solve_any(const DictView &d, const WorkView &w, const SlotView
   return bf ? launch_solve_t<4, true, SLOTS>(d, w, sv, st) : launch_solve_t<4, false, SLOTS>(d, w, sv, st);
 }
 
-size_t residual_lds(const WorkView &w, int LP) { return (size_t)4 * (64 / LP) * w.S * 8; }
+size_t residual_lds(const WorkView &w, int LP) { return (size_t)4 * (64 / LP) * (w.S + 1) * 8; }
 
 // Lanes per signal of the residual kernel: as requested, else by shape (one
 // lane per float4 of a slice, at most 16: on the 1024 x 4096 benchmark 16
