@@ -297,7 +297,7 @@ __device__ inline void wave_lds_sync() {
 // ||a_n||^2. Keeps the best exact score, its atom, its signed a^T r and
 // ||a||^2. The winner's Gram row is read after the pick: fetching every
 // candidate's row in the re-score round instead saves that round but reads
-// about twice the Gram lines, and measured 2.7% slower on the benchmark step.
+// about twice the Gram lines, and measured 2.3% slower on the benchmark step.
 template <bool RR>
 struct RescoreQueue {
   const float4 *r4;          // the residual in memory ...
@@ -839,6 +839,9 @@ __device__ inline void stop_signal(const WorkView &w, const SlotView &sv, int64_
   else if (lane == 0) w.flags[b] = fl;
 }
 
+// RPL: support rows per lane (S <= 64 RPL); BF16: the 16-bit forms' certified
+// pick; SLOTS: the slot scheduler's retire and admit; RR: the residual is held
+// in registers (M <= 1024).
 template <int RPL, bool BF16, bool SLOTS, bool RR>
 __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView w, SlotView sv) {
   extern __shared__ float smem[];
@@ -850,8 +853,8 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
   float *Vs = smem + (size_t)wv * (VS + solve_list_len(w));
   int *clist = reinterpret_cast<int *>(Vs + VS);  // BF16 pick: candidate list (one entry per key at most)
 
-  // ---- memory round 1: state, residual norms, keys, support, u (none of these
-  // addresses depends on another load)
+  // ---- memory round 1: state, residual norms, keys, support, u and (RR) the
+  // residual (none of these addresses depends on another load)
   int fl = w.flags[b];
   const int k = __builtin_amdgcn_readfirstlane(w.k[b]);  // wave-uniform: scalar loop bounds
   const float eps_b = w.epsb[b];  // read here, with the rest of memory round 1
