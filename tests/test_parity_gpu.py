@@ -100,6 +100,20 @@ def test_ragged_shapes(orc, M, N, B, S, prec):
     print(rep)
 
 
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("M,N,B,S", [(1025, 900, 33, 20), (2056, 1300, 24, 40)])
+def test_long_signals_residual_in_memory(orc, M, N, B, S, prec):
+    """Signals longer than 1024 samples, where the solve reads the residual from memory
+    during the pick instead of holding it in registers, and its exact scores take
+    several passes over M; residual-vector forms, every signal against the oracle."""
+    from paper_2407_06434_amd import workloads
+    w = workloads.custom(M, N, B, S, seed=M + 7 * N, k_true=S)
+    print(f"case long signals M={M} N={N} B={B} S={S} {prec}", flush=True)
+    rep = parity.check(w, run_gpu(w, prec, A_pad=2, Y_pad=3), orc)
+    print(rep)
+    assert rep["passed"] == w.B
+
+
 def ls_invariants(A, Y, sup, coef, chunk=256):
     """FP64 checks of every signal's GPU result on its own support: the coefficients
     against the least-squares solution on that support (QR of A_S in FP64), and the
