@@ -309,6 +309,51 @@ def pin_sklearn_crosscheck(orc, lib):
     np.testing.assert_allclose(o["x"], X.T, rtol=1e-9, atol=1e-11)
 
 
+def pin_forced_prefix(orc, lib):
+    """Forced-prefix replay (the mode the GPU parity checker uses): the first nprefix_b
+    picks are the forced atoms in order, whatever their scores, and the run then goes
+    on greedily; at every step s_pick is the picked atom's |a^T r| / ||a|| and s_best
+    and idx_best the largest such score over the atoms not yet picked and its atom,
+    with r the least-squares residual on the picks so far (numpy here); nprefix_b = 0
+    is the free run; a forced atom picked twice is refused."""
+    import pytest
+    g = np.random.default_rng(31)
+    M, N, S, B = 20, 50, 7, 6
+    A = _dict(M, N, 32, norms=(0.5, 2.0))
+    Y = g.standard_normal((B, M)).astype(np.float32)
+    free = orc.omp(A, Y, S, lib=lib)
+    npre = np.array([0, 1, 3, 7, 2, 5], np.int32)
+    pre = np.full((B, S), -1, np.int32)
+    for b in range(B):
+        pre[b, :npre[b]] = g.choice(N, int(npre[b]), replace=False)
+    o = orc.omp(A, Y, S, prefix=pre, nprefix=npre, lib=lib)
+    A64 = A.astype(np.float64)
+    nu = np.linalg.norm(A64, axis=1)
+    for b in range(B):
+        assert o["k"][b] == S
+        sup = o["support"][b, :S]
+        assert sup[:npre[b]].tolist() == pre[b, :npre[b]].tolist(), b
+        if npre[b] == 0:
+            assert sup.tolist() == free["support"][b, :S].tolist()
+        r = Y[b].astype(np.float64)
+        for j in range(S):
+            sc = np.abs(A64 @ r) / nu
+            sc[sup[:j]] = -1.0
+            best = int(np.argmax(sc))
+            assert abs(o["s_best"][b, j] - sc[best]) <= 1e-10 * sc[best], (b, j)
+            assert abs(o["s_pick"][b, j] - sc[sup[j]]) <= 1e-10 * sc[best], (b, j)
+            assert o["idx_best"][b, j] == best, (b, j)
+            if j >= npre[b]:
+                assert sup[j] == best, (b, j)
+            _, r = _lstsq(A, Y[b], sup[: j + 1])
+        x, _ = _lstsq(A, Y[b], sup)
+        np.testing.assert_allclose(o["coef"][b, :S], x, rtol=1e-9, atol=1e-12)
+    twice = pre.copy()
+    twice[3, 1] = twice[3, 0]
+    with pytest.raises(ValueError):
+        orc.omp(A, Y, S, prefix=twice, nprefix=npre, lib=lib)
+
+
 PINS = [pin_s1_matched_filter, pin_bruteforce_tiny, pin_greedy_choice, pin_exact_recovery_erc,
         pin_orthonormal_thresholding, pin_invariants, pin_metamorphic, pin_tie_break_lowest,
-        pin_stop_rules, pin_per_signal_caps_and_tolerances, pin_sklearn_crosscheck]
+        pin_stop_rules, pin_per_signal_caps_and_tolerances, pin_sklearn_crosscheck, pin_forced_prefix]

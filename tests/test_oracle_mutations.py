@@ -39,6 +39,10 @@ MUTATIONS = {
     "per_signal_eps_wrong_row": ("double eb = eps_arr ? (double)eps_arr[b] : eps;",
                                  "double eb = eps_arr ? (double)eps_arr[0] : eps;"),
     "per_signal_S_wrong_row": ("int Sb = S_arr ? S_arr[b] : S;", "int Sb = S_arr ? S_arr[b > 0 ? b - 1 : 0] : S;"),
+    "forced_pick_scored_as_best": ("      spick = fabs(dot_atom(A + (size_t)pick * (size_t)lda, r, M)) / nu[pick];",
+                                   "      spick = best;"),
+    "forced_prefix_ignored": ("    if (k < nprefix) {\n      pick = prefix[k];", "    if (k < 0) {\n      pick = prefix[k];"),
+    "forced_prefix_one_short": ("    if (k < nprefix) {\n      pick = prefix[k];", "    if (k + 1 < nprefix) {\n      pick = prefix[k];"),
 }
 
 
