@@ -135,17 +135,23 @@ __global__ __launch_bounds__(T::NTHR) void k_corr_select(
   int tn, tb;
   xcd_tile(blockIdx.x, ntile, gridDim.x / ntile, &tn, &tb);
   const int64_t b0 = (int64_t)tb * T::TB;
+  constexpr int EPC = 16 / sizeof(typename Op::elem);  // elements per 16-byte chunk
+  const int64_t rs = Mp / EPC;
+  const u32x4 *P = reinterpret_cast<const u32x4 *>(Aop) + (int64_t)tn * T::TN * rs;
+  const u32x4 *Q = reinterpret_cast<const u32x4 *>(Rop) + b0 * rs;
+  // 16-bit forms: the first K slice is staged before the liveness test below,
+  // so that its loads and the test's flag reads are in flight together.
+  if (TOP2) stage_first_slice<T>(P, rs, Q, rs, lds);
 
   // Skip the tile when every signal in it has stopped (keep-in-batch stopping,
   // Section 3.5: finished signals stay in place and are simply not advanced).
   int live = 0;
   for (int t = threadIdx.x; t < T::TB; t += T::NTHR) live |= !(flags[b0 + t] & FLAG_DONE);
-  if (!__syncthreads_or(live)) return;
+  if (!__syncthreads_or(live)) {
+    __builtin_amdgcn_s_waitcnt(0);  // no load may still be writing this workgroup's LDS
+    return;
+  }
 
-  constexpr int EPC = 16 / sizeof(typename Op::elem);  // elements per 16-byte chunk
-  const int64_t rs = Mp / EPC;
-  const u32x4 *P = reinterpret_cast<const u32x4 *>(Aop) + (int64_t)tn * T::TN * rs;
-  const u32x4 *Q = reinterpret_cast<const u32x4 *>(Rop) + b0 * rs;
   // BF16 / FP16 select: the epilogue's inputs that do not depend on the product,
   // 1/||a|| of the tile's atoms and the tile's selected-atom mask words of every
   // signal, are loaded into LDS behind the operand buffers before the main loop
@@ -162,7 +168,10 @@ __global__ __launch_bounds__(T::NTHR) void k_corr_select(
     }
   }
   f32x16 acc[T::FN][T::FB];
-  mainloop<Op, T>(P, rs, Q, rs, (int)(rs / T::CH), lds, acc);
+  if constexpr (TOP2)
+    mainloop_pipelined<Op, T, true>(P, rs, Q, rs, (int)(rs / T::CH), lds, acc);
+  else
+    mainloop<Op, T>(P, rs, Q, rs, (int)(rs / T::CH), lds, acc);
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wn = wave % T::WN, wb = wave / T::WN;

@@ -120,7 +120,30 @@ __device__ inline void dma16(const void *g, lds_void_t *l) {
 // working while the wavefronts meet. Loads the caller issued with dma16 before
 // the call have landed once the first barrier has passed. Ends with a barrier,
 // so the caller may reuse the LDS.
-template <class Op, class T>
+// Source of lane's chunk for load i of the calling wavefront at slice 0 (the
+// slot map is an involution, so the chunk that lands in slot l mod 8 is read).
+template <class T>
+__device__ inline const u32x4 *stage_src(const u32x4 *__restrict__ P, int64_t prs, const u32x4 *__restrict__ Q,
+                                         int64_t qrs, int i) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int row = (i * T::NW + wave) * 8 + (lane >> 3);
+  const int c = lds_slot(row, lane & 7);
+  return row < T::TN ? P + (int64_t)row * prs + c : Q + (int64_t)(row - T::TN) * qrs + c;
+}
+
+// The calling wavefront's loads of K slice 0 into LDS buffer 0 (a caller may
+// issue them early and then tell mainloop_pipelined so with FIRST_STAGED).
+template <class T>
+__device__ inline void stage_first_slice(const u32x4 *__restrict__ P, int64_t prs, const u32x4 *__restrict__ Q,
+                                         int64_t qrs, u32x4 *lds) {
+  const int wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < T::LPW; ++i)
+    dma16(reinterpret_cast<const void *>(stage_src<T>(P, prs, Q, qrs, i)),
+          (lds_void_t *)(lds + (i * T::NW + wave) * 64));
+}
+
+template <class Op, class T, bool FIRST_STAGED = false>
 __device__ inline void mainloop_pipelined(const u32x4 *__restrict__ P, int64_t prs, const u32x4 *__restrict__ Q,
                                           int64_t qrs, int nslices, u32x4 *lds, f32x16 (&acc)[T::FN][T::FB]) {
   const int tid = threadIdx.x;
@@ -144,11 +167,7 @@ __device__ inline void mainloop_pipelined(const u32x4 *__restrict__ P, int64_t p
   // Source of this lane's chunk for each of its loads, at slice 0.
   const u32x4 *src[T::LPW];
 #pragma unroll
-  for (int i = 0; i < T::LPW; ++i) {
-    const int row = (i * T::NW + wave) * 8 + (lane >> 3);
-    const int c = lds_slot(row, lane & 7);  // the slot map is an involution
-    src[i] = row < T::TN ? P + (int64_t)row * prs + c : Q + (int64_t)(row - T::TN) * qrs + c;
-  }
+  for (int i = 0; i < T::LPW; ++i) src[i] = stage_src<T>(P, prs, Q, qrs, i);
   auto issue = [&](int s, int buf) {
 #pragma unroll
     for (int i = 0; i < T::LPW; ++i)
@@ -179,7 +198,7 @@ __device__ inline void mainloop_pipelined(const u32x4 *__restrict__ P, int64_t p
     for (int j = 0; j < T::FB; ++j) bf[set][j] = L[boff[j] + ((2 * q + h) ^ bsw[j])];
   };
 
-  issue(0, 0);
+  if (!FIRST_STAGED) issue(0, 0);
   __builtin_amdgcn_s_waitcnt(0);  // this wavefront's loads of slice 0 have landed ...
   __syncthreads();                // ... and everyone's
   if (nslices > 1) issue(1, 1);
