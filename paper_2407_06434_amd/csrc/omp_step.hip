@@ -228,7 +228,7 @@ __device__ __attribute__((always_inline)) inline void atom_dots(const DictView &
 }
 
 // The residual's chunks a lane holds in registers when the solve reads r in
-// its first memory round (M <= 64 * 4 * RREG).
+// its first memory round (512 < M <= 64 * 4 * RREG).
 constexpr int RREG = 4;
 
 // atom_dots with the vector already in registers: lane l holds chunks
@@ -841,7 +841,7 @@ __device__ inline void stop_signal(const WorkView &w, const SlotView &sv, int64_
 
 // RPL: support rows per lane (S <= 64 RPL); BF16: the 16-bit forms' certified
 // pick; SLOTS: the slot scheduler's retire and admit; RR: the residual is held
-// in registers (M <= 1024).
+// in registers (512 < M <= 1024).
 template <int RPL, bool BF16, bool SLOTS, bool RR>
 __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView w, SlotView sv) {
   extern __shared__ float smem[];
@@ -881,8 +881,8 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
   // FP32 form: the largest valid 64-bit key (a valid key has a non-zero index
   // word). BF16 form: (score bits << 32) | 1 of the best valid 32-bit key.
   uint64_t kmax = 0;
-  // RR (M <= 1024, residual-vector forms): the residual is read in this round
-  // too, so the pick's exact scores need only the atoms.
+  // RR (512 < M <= 1024, residual-vector forms): the residual is read in this
+  // round too, so the pick's exact scores need only the atoms.
   const float4 *r4 = reinterpret_cast<const float4 *>(w.R32) + b * (d.Mp / 4);
   float4 rr[RREG];
 #pragma unroll
@@ -2022,10 +2022,15 @@ __global__ __launch_bounds__(256) void k_densify(const int32_t *__restrict__ sup
 }
 
 // The solve reads the residual into registers in its first memory round when
-// a lane's share fits (M <= 1024) and the form keeps residual vectors (not in
-// the slot scheduler's solve, whose retire-and-admit code would then leave
-// three wavefronts per SIMD instead of four).
-bool solve_rr(const DictView &d, const WorkView &w) { return !w.gram_dom && d.Mp <= 64 * 4 * RREG; }
+// a lane's share fills most of RREG chunks (512 < M <= 1024) and the form keeps
+// residual vectors. Shorter signals keep the memory path: with one or two
+// chunks per lane the register path's fixed four loads per operand cost more
+// than the round they save (2.3% slower at M = 64 and 256). Not in the slot
+// scheduler's solve either, whose retire-and-admit code would then leave three
+// wavefronts per SIMD instead of four.
+bool solve_rr(const DictView &d, const WorkView &w) {
+  return !w.gram_dom && d.Mp > 64 * 2 * RREG && d.Mp <= 64 * 4 * RREG;
+}
 
 template <int RPL, bool BF16, bool SLOTS>
 hipError_t launch_solve_t(const DictView &d, const WorkView &w, const SlotView &sv, hipStream_t st) {
