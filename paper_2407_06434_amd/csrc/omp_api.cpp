@@ -504,7 +504,9 @@ int solve_impl(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y
       }
       e = timer.run(OMP_PHASE_CORR, [&] { return launch_corr_select(d, w, prec, cs); });
       if (e == hipSuccess) e = timer.run(OMP_PHASE_UPDATE, [&] { return launch_solve(d, w, prec, cs); });
-      if (e == hipSuccess) e = timer.run(OMP_PHASE_RESIDUAL, [&] { return launch_residual(d, w, prec, cs); });
+      // after step it every signal holds at most it + 1 atoms
+      if (e == hipSuccess)
+        e = timer.run(OMP_PHASE_RESIDUAL, [&] { return launch_residual(d, w, prec, it + 1, cs); });
     }
     if (e == hipSuccess)
       e = timer.run(OMP_PHASE_OUTPUT, [&] {

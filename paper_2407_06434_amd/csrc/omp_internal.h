@@ -228,15 +228,16 @@ hipError_t launch_project(const DictView &d, const WorkView &w, hipStream_t st);
 hipError_t launch_gram_select(const DictView &d, const WorkView &w, hipStream_t st);
 // One OMP step per live signal: stop test, pick, Cholesky append, both solves.
 hipError_t launch_solve(const DictView &d, const WorkView &w, int precision, hipStream_t st);
-// Residual r = y - A_S x (and its BF16 copy and per-slice norms) for the signals just updated.
-hipError_t launch_residual(const DictView &d, const WorkView &w, int precision, hipStream_t st);
+// Residual r = y - A_S x (and its BF16 copy and per-slice norms) for the signals just updated;
+// kbound is an upper bound on every signal's support size (the number of steps taken so far).
+hipError_t launch_residual(const DictView &d, const WorkView &w, int precision, int kbound, hipStream_t st);
 // Slot scheduler: fill the slots with the first signals and reset the queue.
 hipError_t launch_init_slots(const WorkView &w, const SlotView &sv, hipStream_t st);
 // One OMP step per occupied slot; stopped signals are written out and replaced.
 hipError_t launch_solve_slots(const DictView &d, const WorkView &w, const SlotView &sv, int precision,
                               hipStream_t st);
 // Residual with an explicit number of lanes per signal (power of two, 1..64; 0 = by shape).
-hipError_t launch_residual_lp(const DictView &d, const WorkView &w, int precision, int lanes,
+hipError_t launch_residual_lp(const DictView &d, const WorkView &w, int precision, int lanes, int kbound,
                               hipStream_t st);
 // Dense X [nsig][N] from compact supports and coefficients.
 hipError_t launch_densify(const int32_t *support, const float *coef, int64_t nsig, int S, int64_t N,

@@ -160,7 +160,7 @@ hipError_t capture_chunk(DevState *ds, const std::vector<Plan> &plans, int preci
       hipStream_t sp = ds->streams[p];
       e = launch_corr_select(q.d, q.w, precision, sp);
       if (e == hipSuccess) e = launch_solve_slots(q.d, q.w, q.sv, precision, sp);
-      if (e == hipSuccess) e = launch_residual_lp(q.d, q.w, precision, q.lanes, sp);
+      if (e == hipSuccess) e = launch_residual_lp(q.d, q.w, precision, q.lanes, q.w.S, sp);  // slots: any k <= S
     }
   }
   for (int p = 1; p < np && e == hipSuccess; ++p) {

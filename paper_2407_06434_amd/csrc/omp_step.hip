@@ -1842,7 +1842,7 @@ __global__ __launch_bounds__(64) void k_v0_coef64(WorkView w) {
 // wavefront. Workgroup i handles slice i mod nslice.
 // ---------------------------------------------------------------------------
 template <bool BF16>
-__global__ __launch_bounds__(256) void k_residual(DictView d, WorkView w, int LP) {
+__global__ __launch_bounds__(256) void k_residual(DictView d, WorkView w, int LP, int kbound) {
   extern __shared__ int rsm[];
   const int IPW = 64 / LP;
   const int items = 4 * IPW;
@@ -1859,12 +1859,18 @@ __global__ __launch_bounds__(256) void k_residual(DictView d, WorkView w, int LP
   const int item = wave * IPW + lane / LP;
   const int sl = lane % LP;
   const int64_t b = group * items + item;
-  int kk = 0;
-  if (b < w.B && (w.flags[b] & FLAG_NEWX)) kk = w.k[b];
-  for (int j = sl; j < kk; j += LP) {
-    xs[item * SP + j] = -w.xh[b * S + j];
-    ss[item * SP + j] = w.sup[b * S + j];
+  // kbound >= k for every signal (the launch knows how many picks have been
+  // made at most), so the coefficients and support entries are read in the
+  // same memory round as the signal's state instead of after it.
+  const int64_t bc = b < w.B ? b : 0;  // padding items read signal 0 and do nothing
+  const int fl = w.flags[bc];
+  const int kraw = w.k[bc];
+  const int kb = kbound < S ? kbound : S;
+  for (int j = sl; j < kb; j += LP) {
+    xs[item * SP + j] = -w.xh[bc * S + j];
+    ss[item * SP + j] = w.sup[bc * S + j];
   }
+  const int kk = (b < w.B && (fl & FLAG_NEWX)) ? kraw : 0;
   __syncthreads();
   if (kk == 0) return;  // after the only barrier
 
@@ -2115,7 +2121,8 @@ hipError_t launch_init_slots(const WorkView &w, const SlotView &sv, hipStream_t 
   return hipGetLastError();
 }
 
-hipError_t launch_residual_lp(const DictView &d, const WorkView &w, int precision, int lanes, hipStream_t st) {
+hipError_t launch_residual_lp(const DictView &d, const WorkView &w, int precision, int lanes, int kbound,
+                              hipStream_t st) {
   if (w.B == 0) return hipSuccess;
   const int LP = residual_lanes(w, lanes);
   if (LP < 1 || LP > 64 || (LP & (LP - 1))) return hipErrorInvalidValue;
@@ -2126,11 +2133,11 @@ hipError_t launch_residual_lp(const DictView &d, const WorkView &w, int precisio
   if (is_half(precision)) {
     hipError_t e = allow_lds(k_residual<true>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_residual<true>, grid, block, lds, st, d, w, LP);
+    hipLaunchKernelGGL(k_residual<true>, grid, block, lds, st, d, w, LP, kbound);
   } else {
     hipError_t e = allow_lds(k_residual<false>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_residual<false>, grid, block, lds, st, d, w, LP);
+    hipLaunchKernelGGL(k_residual<false>, grid, block, lds, st, d, w, LP, kbound);
   }
   return hipGetLastError();
 }
@@ -2204,8 +2211,8 @@ hipError_t launch_v0_coef64(const WorkView &w, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_residual(const DictView &d, const WorkView &w, int precision, hipStream_t st) {
-  return launch_residual_lp(d, w, precision, 0, st);
+hipError_t launch_residual(const DictView &d, const WorkView &w, int precision, int kbound, hipStream_t st) {
+  return launch_residual_lp(d, w, precision, 0, kbound, st);
 }
 
 hipError_t launch_densify(const int32_t *support, const float *coef, int64_t nsig, int S, int64_t N,
