@@ -1264,6 +1264,9 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
   }
   return;
 stop:
+  // A stop after the factor's global-to-LDS loads were issued (no selectable
+  // atom left) must not leave them writing this block's LDS after it ends.
+  __builtin_amdgcn_s_waitcnt(0);
   stop_signal<SLOTS>(w, sv, b, stopfl, k, rn, lane);
 }
 
