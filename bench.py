@@ -116,6 +116,9 @@ def kernel_rooflines(w, precision, tim):
     entry("k_solve", "update", "hbm", solve_bytes_per_launch(w.M, w.S, w.B), 1e9, PEAK["hbm"], "GB/s")
     gb = residual_gather_bytes_per_launch(w.M, w.S, w.B)
     ms, n = tim["residual"]
+    if n == 0:  # a dictionary that fits every XCD's L2: the solve formed the residual
+        out["k_residual"] = dict(fused_into="k_solve", launches=0)
+        return out
     entry("k_residual", "residual", "hbm", residual_bytes_per_launch(w.M, w.N, w.S, w.B, bf16), 1e9,
           PEAK["hbm"], "GB/s",
           extra=dict(l2_gather_bytes_per_launch=float(f"{gb:.5e}"),

@@ -320,6 +320,7 @@ WorkView work_view(void *mem, int64_t M, int64_t N, int64_t B, int S, int precis
   w.pchunks = L.pchunks;
   w.Pk = L.pchunks > 1 ? at<float>(mem, L.Pk) : nullptr;
   w.flag_ties = ties ? 1 : 0;
+  w.fuse_res = 0;
   if (gram_dom) {  // one key (two with near-tie flagging) per (signal, atom slice) from the Gram-domain select
     w.ntile = GSLICE;
     w.ncand = ties ? 2 : 1;
@@ -475,6 +476,10 @@ int solve_impl(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y
     WorkView w = work_view(workspace, M, N, B, S, prec, cfg, gdom, ties, v0);
     w.gram_fly = opts->gram_on_the_fly;
     w.refactor = opts->refactor;
+    // A dictionary that fits every XCD's L2 (the residual kernel would use one
+    // slice of M): the solve forms the residual itself, one launch fewer per step.
+    w.fuse_res = (w.nslice == 1 && !gdom && !v0 && !f64) ? 1 : 0;
+    if (solve_rr(d, w)) w.fuse_res = 0;  // that variant keeps its registers for the residual it reads
     e = timer.run(OMP_PHASE_INIT, [&] {
       return launch_init(Y, ldy, opts->S_per_signal, opts->eps_per_signal, eps, d, w, prec, cs);
     });
@@ -505,7 +510,7 @@ int solve_impl(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y
       e = timer.run(OMP_PHASE_CORR, [&] { return launch_corr_select(d, w, prec, cs); });
       if (e == hipSuccess) e = timer.run(OMP_PHASE_UPDATE, [&] { return launch_solve(d, w, prec, cs); });
       // after step it every signal holds at most it + 1 atoms
-      if (e == hipSuccess)
+      if (e == hipSuccess && !w.fuse_res)
         e = timer.run(OMP_PHASE_RESIDUAL, [&] { return launch_residual(d, w, prec, it + 1, cs); });
     }
     if (e == hipSuccess)

@@ -39,6 +39,16 @@
 #include "omp_internal.h"
 
 namespace bomp {
+
+// The solve reads the residual into registers in its first memory round when
+// a lane's share fills most of its four 16-byte register chunks (512 < M <=
+// 1024) and the form keeps residual vectors. Shorter signals keep the memory path: with one or two
+// chunks per lane the register path's fixed four loads per operand cost more
+// than the round they save (2.3% slower at M = 64 and 256). Not in the slot
+// scheduler's solve either, whose retire-and-admit code would then leave three
+// wavefronts per SIMD instead of four.
+bool solve_rr(const DictView &d, const WorkView &w) { return !w.gram_dom && d.Mp > 512 && d.Mp <= 1024; }
+
 namespace {
 
 __device__ inline uint16_t f32_to_bf16_rne(float f) {
@@ -148,6 +158,33 @@ __device__ inline float readlane(float v, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
+// Element j (wave-uniform) of an array held one element per lane, rows
+// j = lane + 64 p: lane j mod 64 of every register is read first and the
+// register chosen by j / 64 afterwards, among the read (uniform) values. Unlike
+// readlane(pick(a, j >> 6), j & 63) this is exact where some lanes are inactive:
+// pick's per-lane select is not executed by inactive lanes, whose stale values
+// readlane would then return.
+template <int R>
+__device__ inline int lane_elem(const int (&a)[R], int j) {
+  int v = __builtin_amdgcn_readlane(a[0], j & 63);
+#pragma unroll
+  for (int i = 1; i < R; ++i) {
+    const int u = __builtin_amdgcn_readlane(a[i], j & 63);
+    v = (j >> 6) == i ? u : v;
+  }
+  return v;
+}
+template <int R>
+__device__ inline float lane_elem(const float (&a)[R], int j) {
+  float v = readlane(a[0], j & 63);
+#pragma unroll
+  for (int i = 1; i < R; ++i) {
+    const float u = readlane(a[i], j & 63);
+    v = (j >> 6) == i ? u : v;
+  }
+  return v;
+}
+
 // Current ||r|| of signal b from its per-slice partial sums of squares.
 __device__ inline double residual_norm(const WorkView &w, int64_t b) {
   double s = 0.0;
@@ -230,6 +267,7 @@ __device__ __attribute__((always_inline)) inline void atom_dots(const DictView &
 // The residual's chunks a lane holds in registers when the solve reads r in
 // its first memory round (512 < M <= 64 * 4 * RREG).
 constexpr int RREG = 4;
+static_assert(64 * 4 * RREG == 1024, "solve_rr selects the register path for M <= 1024");
 
 // atom_dots with the vector already in registers: lane l holds chunks
 // l + 64 q (q < RREG) of v, zero past the end (requires M <= 64 * 4 * RREG).
@@ -1225,6 +1263,65 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
     if (i < K) w.xh[b * S + i] = x[p];
   }
 
+  if (!SLOTS && !RR && w.fuse_res) {
+    // Residual fused into the solve (dictionaries small enough for every XCD's L2,
+    // where the residual kernel would not slice M): this wavefront forms
+    // r = y - A_K x for its own signal exactly as the residual kernel does (the
+    // same FMA order per element), its 16-bit copy, ||r||^2 and, in the 16-bit
+    // forms, the copy's error norm, and stores them where that kernel would.
+    const int64_t nc4 = d.Mp / 4;
+    const float4 *A4 = reinterpret_cast<const float4 *>(d.A32);
+    const float4 *Y4 = reinterpret_cast<const float4 *>(w.Yp) + b * nc4;
+    float4 *R4 = reinterpret_cast<float4 *>(w.R32) + b * nc4;
+    // FP16 form: the copy is fp16(sigma r) with the scale chosen from ||r_k|| above
+    const float sig = (BF16 && w.fp16) ? pow2_scale(rn) : 1.f;
+    double nrm = 0.0, dlt = 0.0;
+    for (int64_t c = lane; c < nc4; c += 64) {
+      float4 r = Y4[c];
+      for (int j = 0; j < K; ++j) {
+        // (lanes past nc4 are inactive in the last pass: lane_elem, not pick)
+        const int sj = j < k ? lane_elem(si, j) : nstar;
+        const float xj = -lane_elem(x, j);
+        const float4 a = A4[(int64_t)sj * nc4 + c];
+        r.x = fmaf(xj, a.x, r.x); r.y = fmaf(xj, a.y, r.y); r.z = fmaf(xj, a.z, r.z); r.w = fmaf(xj, a.w, r.w);
+      }
+      R4[c] = r;
+      if (BF16 && w.fp16) {
+        ushort4 h;
+        h.x = f32_to_f16_rne(r.x * sig);
+        h.y = f32_to_f16_rne(r.y * sig);
+        h.z = f32_to_f16_rne(r.z * sig);
+        h.w = f32_to_f16_rne(r.w * sig);
+        reinterpret_cast<ushort4 *>(w.R16)[b * nc4 + c] = h;
+        const double e0 = (double)r.x - f16_used(h.x) / (double)sig;
+        const double e1 = (double)r.y - f16_used(h.y) / (double)sig;
+        const double e2 = (double)r.z - f16_used(h.z) / (double)sig;
+        const double e3 = (double)r.w - f16_used(h.w) / (double)sig;
+        dlt += e0 * e0 + e1 * e1 + e2 * e2 + e3 * e3;
+      } else if (BF16) {
+        ushort4 h;
+        h.x = f32_to_bf16_rne(r.x);
+        h.y = f32_to_bf16_rne(r.y);
+        h.z = f32_to_bf16_rne(r.z);
+        h.w = f32_to_bf16_rne(r.w);
+        reinterpret_cast<ushort4 *>(w.R16)[b * nc4 + c] = h;
+        const double e0 = (double)r.x - bf16_used(h.x);
+        const double e1 = (double)r.y - bf16_used(h.y);
+        const double e2 = (double)r.z - bf16_used(h.z);
+        const double e3 = (double)r.w - bf16_used(h.w);
+        dlt += e0 * e0 + e1 * e1 + e2 * e2 + e3 * e3;
+      }
+      nrm += (double)r.x * r.x + (double)r.y * r.y + (double)r.z * r.z + (double)r.w * r.w;
+    }
+    nrm = wave_sum(nrm);
+    if (BF16) dlt = wave_sum(dlt);
+    if (lane == 0) {
+      w.pnorm[b * NSLICE_MAX] = nrm;  // one slice: entries 1 .. NSLICE_MAX-1 stay 0
+      if (BF16) w.pdelta[b * NSLICE_MAX] = dlt;
+      if (BF16 && w.fp16) w.rscale[b] = sig;
+    }
+  }
+
   if (w.gram_dom) {
     // Gram-domain form (no residual vectors): ||r_K||^2 = ||r_k||^2 - u_K^2, u_K
     // being y's component along the new orthonormal direction, kept in FP64
@@ -1243,8 +1340,9 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
       for (int64_t m = lane; m < d.M; m += 64) {
         double rm = (double)yb[m];
         for (int j = 0; j < K; ++j) {
-          const int sj = j < k ? __builtin_amdgcn_readlane(pick_i(si, j >> 6), j & 63) : nstar;
-          const float xj = readlane(pick(x, j >> 6), j & 63);
+          // (lanes past M are inactive in the last pass: lane_elem, not pick)
+          const int sj = j < k ? lane_elem(si, j) : nstar;
+          const float xj = lane_elem(x, j);
           rm -= (double)xj * (double)d.A32[(int64_t)sj * d.Mp + m];
         }
         acc += rm * rm;
@@ -1254,7 +1352,8 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
     if (lane == 0) w.pnorm[b * NSLICE_MAX] = r2;
   }
 
-  // 9. New state; the residual kernel picks the signal up through FLAG_NEWX.
+  // 9. New state; the residual kernel picks the signal up through FLAG_NEWX
+  //    (it is not launched when the residual is fused above).
   if (lane == 0) {
     fl |= FLAG_NEWX;
     if (K >= S_b) fl |= FLAG_DONE;
@@ -2030,16 +2129,6 @@ __global__ __launch_bounds__(256) void k_densify(const int32_t *__restrict__ sup
   }
 }
 
-// The solve reads the residual into registers in its first memory round when
-// a lane's share fills most of RREG chunks (512 < M <= 1024) and the form keeps
-// residual vectors. Shorter signals keep the memory path: with one or two
-// chunks per lane the register path's fixed four loads per operand cost more
-// than the round they save (2.3% slower at M = 64 and 256). Not in the slot
-// scheduler's solve either, whose retire-and-admit code would then leave three
-// wavefronts per SIMD instead of four.
-bool solve_rr(const DictView &d, const WorkView &w) {
-  return !w.gram_dom && d.Mp > 64 * 2 * RREG && d.Mp <= 64 * 4 * RREG;
-}
 
 template <int RPL, bool BF16, bool SLOTS>
 hipError_t launch_solve_t(const DictView &d, const WorkView &w, const SlotView &sv, hipStream_t st) {

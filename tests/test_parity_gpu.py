@@ -297,8 +297,10 @@ def test_graph_replays_match_direct_launches(form):
             print("graph timing", timing)
             v0 = kw.get("v0", False) or prec == "fp64"  # the FP64 form runs v0
             assert timing["corr"][1] == (0 if v0 else w.S) and timing["update"][1] == w.S
-            # the Gram-domain and v0 forms keep no residual vectors
-            assert timing["residual"][1] == (0 if gd or v0 else w.S)
+            # the Gram-domain and v0 forms keep no residual vectors; the 256 x 1024 dictionary
+            # (1 MiB in FP32) fits every XCD's L2, so there the solve forms the residual itself
+            assert w.M * w.N * 4 <= 2 << 20 or gd
+            assert timing["residual"][1] == 0
             assert timing["init"][1] == (3 if v0 else 2 if gd else 1)
             assert timing["output"][1] == (2 if v0 else 1)
             assert all(v[0] > 0 for k, v in timing.items() if v[1] > 0)
