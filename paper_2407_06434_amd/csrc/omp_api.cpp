@@ -478,7 +478,12 @@ int solve_impl(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y
     w.refactor = opts->refactor;
     // A dictionary that fits every XCD's L2 (the residual kernel would use one
     // slice of M): the solve forms the residual itself, one launch fewer per step.
-    w.fuse_res = (w.nslice == 1 && !gdom && !v0 && !f64) ? 1 : 0;
+    // Not for signals shorter than 256 samples in batches of more than 4096 (the
+    // solve's resident wavefronts): one wavefront per signal then leaves lanes
+    // idle, and each later generation of solve wavefronts waits for its gathers
+    // again, where the residual kernel packs several signals per wavefront and
+    // holds every one of them at once.
+    w.fuse_res = (w.nslice == 1 && !gdom && !v0 && !f64 && (d.Mp >= 256 || w.B <= 4096)) ? 1 : 0;
     if (solve_rr(d, w)) w.fuse_res = 0;  // that variant keeps its registers for the residual it reads
     e = timer.run(OMP_PHASE_INIT, [&] {
       return launch_init(Y, ldy, opts->S_per_signal, opts->eps_per_signal, eps, d, w, prec, cs);

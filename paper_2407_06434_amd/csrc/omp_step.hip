@@ -1278,12 +1278,25 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
     double nrm = 0.0, dlt = 0.0;
     for (int64_t c = lane; c < nc4; c += 64) {
       float4 r = Y4[c];
-      for (int j = 0; j < K; ++j) {
-        // (lanes past nc4 are inactive in the last pass: lane_elem, not pick)
-        const int sj = j < k ? lane_elem(si, j) : nstar;
-        const float xj = -lane_elem(x, j);
-        const float4 a = A4[(int64_t)sj * nc4 + c];
-        r.x = fmaf(xj, a.x, r.x); r.y = fmaf(xj, a.y, r.y); r.z = fmaf(xj, a.z, r.z); r.w = fmaf(xj, a.w, r.w);
+      // rounds of four atoms, their loads issued together; the sums run in
+      // support order (lanes past nc4 are inactive in the last pass: lane_elem,
+      // not pick)
+      for (int j0 = 0; j0 < K; j0 += 4) {
+        float4 a[4];
+        float xj[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int j = j0 + u < K ? j0 + u : K - 1;  // past K: a repeated load, not summed
+          const int sj = j < k ? lane_elem(si, j) : nstar;
+          xj[u] = -lane_elem(x, j);
+          a[u] = A4[(int64_t)sj * nc4 + c];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (j0 + u < K) {
+            r.x = fmaf(xj[u], a[u].x, r.x); r.y = fmaf(xj[u], a[u].y, r.y);
+            r.z = fmaf(xj[u], a[u].z, r.z); r.w = fmaf(xj[u], a[u].w, r.w);
+          }
       }
       R4[c] = r;
       if (BF16 && w.fp16) {

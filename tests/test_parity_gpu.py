@@ -114,6 +114,30 @@ def test_long_signals_residual_in_memory(orc, M, N, B, S, prec):
     assert rep["passed"] == w.B
 
 
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("M,N,B,S,caps", [(512, 1000, 40, 24, False), (60, 8000, 36, 12, False),
+                                          (200, 700, 48, 30, True)])
+def test_residual_formed_in_the_solve(orc, M, N, B, S, caps, prec):
+    """Dictionaries of at most 2 MiB in FP32 (one padded to exactly 2 MiB, one of 8192
+    atoms of 64 samples) fit every XCD's L2, so the solve forms each step's residual
+    itself; every signal against the oracle, one case with per-signal caps and
+    tolerances so that signals finish at different steps."""
+    from paper_2407_06434_amd import workloads
+    w = workloads.custom(M, N, B, S, seed=3 * M + N, k_true=S)
+    kw = {}
+    if caps:
+        rng = np.random.default_rng(M + N)
+        S_per = rng.integers(0, S + 1, size=B).astype(np.int32)
+        norms = np.linalg.norm(w.Y.astype(np.float64), axis=1)
+        eps_per = np.where(rng.random(B) < 0.5, rng.uniform(0.05, 0.6, size=B) * norms, 0.0).astype(np.float32)
+        w.S_per_signal, w.eps_per_signal = S_per, eps_per
+        kw = dict(S_per=S_per, eps_per=eps_per)
+    print(f"case residual in the solve M={M} N={N} B={B} S={S} caps={caps} {prec}", flush=True)
+    rep = parity.check(w, run_gpu(w, prec, **kw), orc)
+    print(rep)
+    assert rep["passed"] == w.B
+
+
 def ls_invariants(A, Y, sup, coef, chunk=256):
     """FP64 checks of every signal's GPU result on its own support: the coefficients
     against the least-squares solution on that support (QR of A_S in FP64), and the
