@@ -138,6 +138,27 @@ def test_residual_formed_in_the_solve(orc, M, N, B, S, caps, prec):
     assert rep["passed"] == w.B
 
 
+@pytest.mark.parametrize("prec", PRECS)
+def test_residual_in_the_solve_equals_the_residual_kernel(prec):
+    """Signals of 64 samples: a batch of 4096 forms each step's residual in the solve, a
+    batch of 4097 launches the residual kernel (the solve's resident wavefronts would
+    run in two generations). Both form r = y - A_S x in the same order and, at 64
+    samples (16 lanes of four), sum ||r||^2 over the same lane tree, so the first 4096
+    signals get bit-identical supports, coefficients and residual norms."""
+    torch = _torch()
+    from paper_2407_06434_amd import omp, workloads
+    w = workloads.custom(64, 256, 4097, 24, seed=11, k_true=20)
+    dev = torch.device("cuda:0")
+    A = torch.from_numpy(w.A).to(dev)
+    Y = torch.from_numpy(w.Y).to(dev)
+    print(f"case residual in the solve against the residual kernel {prec}", flush=True)
+    big = omp.solve(A, Y, w.S, w.eps, precision=prec)
+    small = omp.solve(A, Y[:4096].contiguous(), w.S, w.eps, precision=prec)
+    torch.cuda.synchronize()
+    for k in ("support", "coef", "rnorm", "status"):
+        assert torch.equal(getattr(big, k)[:4096], getattr(small, k)), k
+
+
 def ls_invariants(A, Y, sup, coef, chunk=256):
     """FP64 checks of every signal's GPU result on its own support: the coefficients
     against the least-squares solution on that support (QR of A_S in FP64), and the
