@@ -25,7 +25,13 @@
 // ||r||^2 accumulated in FP64 per slice of the signal. The signal is cut into
 // up to 8 slices of M and workgroup i works on slice i mod 8: workgroups are
 // dispatched round-robin over the 8 XCDs, so every XCD only ever gathers its
-// own eighth of every atom (one slice of M), which then stays in its L2.
+// own eighth of every atom (one slice of M), which then stays in its L2. A
+// dictionary of at most 2 MiB in FP32 fits every XCD's L2 whole (one slice):
+// there the solve's wavefront forms r itself after its back solve, in the same
+// order and with the same sums, and k_residual is not launched (except for
+// signals shorter than 256 samples in batches larger than the solve's resident
+// wavefronts, where the residual kernel's packing of several signals per
+// wavefront wins).
 //
 // The paper's code re-factorised A_k^T A_k at every step and names the
 // Cholesky update as its next step (Section 3.6); this file implements that
