@@ -23,10 +23,10 @@ progressive Cholesky; inverse Cholesky against re-factorisation), the paper's
 Algorithm v0 and the FP64 form, the Gram-domain form on the tall
 face-recognition shape, uneven batches, the learned proposal and the oracle on
 the host (CPU baseline, with every signal it solved checked against the GPU);
---no-* flags skip them. Two other modes print their own JSON line instead:
---sweep (the paper's parameter sweep as a speed map), --sweep-tall (every form on
-square and tall dictionaries), --apps (the shapes of its application table) and
---only-gram-domain.
+--no-* flags skip them. Other modes print their own JSON line instead: --sweep
+(the paper's parameter sweep as a speed map), --sweep-tall and --sweep-wide (every
+form on square and tall, or wide, dictionaries), --apps (the shapes of its
+application table) and --only-gram-domain.
 
 Prints ONE JSON line (rank 0, one GPU).
 """
@@ -597,39 +597,50 @@ TALL_M = (512, 2048, 8192)
 TALL_N = (256, 1024, 2048)
 
 
-def run_sweep_tall(B=2000, S=32, steps=3, warmup=1):
-    """Where the Gram-domain form pays: every form on square and tall dictionaries
-    (M >= N from the grid TALL_M x TALL_N), B signals, S = 32, unit-norm N(0,1/M) atoms,
-    S-sparse signals at 30 dB. Signals/s over graph-replayed calls on prepared
-    dictionaries."""
+def time_forms(cells, B=2000, S=32, steps=3, warmup=1, tag="sweep"):
+    """Every form (BF16, FP32, Gram-domain FP32) on the (M, N) cells: B signals,
+    S = 32, unit-norm N(0,1/M) atoms, S-sparse signals at 30 dB. Signals/s over
+    graph-replayed calls on prepared dictionaries."""
     import torch
     from paper_2407_06434_amd import omp, workloads
     dev = torch.device("cuda:0")
     rows = []
-    for M in TALL_M:
-        for N in TALL_N:
-            if N > M:
-                continue
-            w = workloads.custom(M, N, B, S, seed=M + N, k_true=S, column_norm="unit")
-            A = torch.from_numpy(w.A).to(dev)
-            Y = torch.from_numpy(w.Y).to(dev)
-            row = {"M": M, "N": N, "B": B, "S": S}
-            for fname, prec, gd in (("bf16", "bf16", False), ("fp32", "fp32", False),
-                                    ("gram_domain_fp32", "fp32", True)):
-                d = omp.Dictionary(A, prec)
-                r = None
-                for _ in range(warmup):
-                    r = omp.solve(A, Y, S, precision=prec, dictionary=d, out=r, gram_domain=gd)
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                for _ in range(steps):
-                    r = omp.solve(A, Y, S, precision=prec, dictionary=d, out=r, gram_domain=gd)
-                torch.cuda.synchronize()
-                row[fname] = round(B * steps / (time.perf_counter() - t0), 1)
-                del d
-            rows.append(row)
-            log(f"tall sweep: {row}")
+    for M, N in cells:
+        w = workloads.custom(M, N, B, S, seed=M + N, k_true=S, column_norm="unit")
+        A = torch.from_numpy(w.A).to(dev)
+        Y = torch.from_numpy(w.Y).to(dev)
+        row = {"M": M, "N": N, "B": B, "S": S}
+        for fname, prec, gd in (("bf16", "bf16", False), ("fp32", "fp32", False),
+                                ("gram_domain_fp32", "fp32", True)):
+            d = omp.Dictionary(A, prec)
+            r = None
+            for _ in range(warmup):
+                r = omp.solve(A, Y, S, precision=prec, dictionary=d, out=r, gram_domain=gd)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                r = omp.solve(A, Y, S, precision=prec, dictionary=d, out=r, gram_domain=gd)
+            torch.cuda.synchronize()
+            row[fname] = round(B * steps / (time.perf_counter() - t0), 1)
+            del d
+        rows.append(row)
+        log(f"{tag}: {row}")
     return rows
+
+
+def run_sweep_tall(**kw):
+    """Where the Gram-domain form pays: square and tall dictionaries (M >= N from the
+    grid TALL_M x TALL_N)."""
+    return time_forms([(M, N) for M in TALL_M for N in TALL_N if N <= M], tag="tall sweep", **kw)
+
+
+WIDE_M = (256, 512, 1024)
+
+
+def run_sweep_wide(**kw):
+    """Where the Gram-domain form stops paying: wide dictionaries, N = 2M and N = 4M
+    (M from WIDE_M; N = 4M at M = 1024 is the benchmark's shape)."""
+    return time_forms([(M, f * M) for M in WIDE_M for f in (2, 4)], tag="wide sweep", **kw)
 
 
 def cpu_model():
@@ -693,6 +704,8 @@ def main():
                     help="instead of the benchmark step, run the paper's parameter sweep and print its speed map")
     ap.add_argument("--sweep-tall", action="store_true",
                     help="instead of the benchmark step, time every form on square and tall dictionaries")
+    ap.add_argument("--sweep-wide", action="store_true",
+                    help="instead of the benchmark step, time every form on wide dictionaries (N = 2M, 4M)")
     ap.add_argument("--apps", action="store_true",
                     help="instead of the benchmark step, time every form on the paper's application shapes")
     ap.add_argument("--only-gram-domain", action="store_true",
@@ -718,6 +731,10 @@ def main():
     if args.sweep_tall:
         print(json.dumps({"metric": "tall_sweep", "unit": "signals/s", "data": "synthetic", "steps": 3,
                           "rows": run_sweep_tall()}), flush=True)
+        return
+    if args.sweep_wide:
+        print(json.dumps({"metric": "wide_sweep", "unit": "signals/s", "data": "synthetic", "steps": 3,
+                          "rows": run_sweep_wide()}), flush=True)
         return
     if args.apps:
         print(json.dumps({"metric": "application_shapes", "unit": "signals/s", "data": "synthetic",

@@ -151,7 +151,7 @@ typedef struct omp_opts {
                                    step (O(k^3)) instead of appending one row to the stored factor
                                    (O(k^2)); u = V^{-1} A_S^T y keeps its incremental form.
                                    0 (default): the progressive update. Other values: OMP_EINVAL. */
-  int32_t gram_domain;          /* 1 = Gram-domain form for tall dictionaries (M >= N; the
+  int32_t gram_domain;          /* 1 = Gram-domain form (for tall dictionaries, M >= N, the
                                    scikit-learn Gram solver the paper's Section 2.1 describes):
                                    P = A^T y is formed once per signal by one product, and each
                                    step takes its correlations as c = P - G[:, S] x (O(N k) per
@@ -164,8 +164,11 @@ typedef struct omp_opts {
                                    grows by (1 + c) * B_pad * N_pad * 4 bytes, c = 0 or the K
                                    chunks (2 to 8) of P's product when the tiles alone would leave
                                    CUs idle (omp_workspace_size with the same opts gives the total).
-                                   2 = automatic: the Gram-domain form for FP32 solves with M >= N,
-                                   the residual-vector form otherwise (the scikit-learn choice).
+                                   2 = automatic, FP32 solves only: the Gram-domain form when
+                                   4 M >= N, unless B > 4096 and the dictionary is under 1 MiB
+                                   in FP32 (4 M N < 2^20 bytes); the residual-vector form
+                                   otherwise (the crossover measured on one MI355X; the
+                                   scikit-learn choice would be M >= N).
                                    0 (default): residual vectors. Other values: OMP_EINVAL. */
   int32_t flag_near_ties;       /* 1 = record near-ties: status bit OMP_SIG_NEARTIE is set for a
                                    signal when, at any of its steps, the runner-up atom scored

@@ -388,9 +388,15 @@ int omp_dict_init(omp_dict_t *dict, const float *A, int64_t M, int64_t N, int64_
 }
 
 // Whether a solve runs in the Gram-domain form: on request (1), or automatically
-// (2) for FP32 solves of tall dictionaries (M >= N).
-static bool gram_domain_form(int32_t mode, int prec, int64_t M, int64_t N) {
-  return mode == 1 || (mode == 2 && prec == OMP_PREC_FP32 && M >= N);
+// (2) for FP32 solves where it was measured faster than the residual-vector form
+// (one MI355X, S = 32 with 2000 and 10,000 signals, S = 64 with 4096): every
+// dictionary at most four times wider than long (4M >= N), tall ones included,
+// except dictionaries under 1 MiB in FP32 in batches of more than 4096 signals,
+// where the residual-vector form (its residual formed in the solve) is faster.
+static bool gram_domain_form(int32_t mode, int prec, int64_t M, int64_t N, int64_t B) {
+  if (mode == 1) return true;
+  if (mode != 2 || prec != OMP_PREC_FP32) return false;
+  return 4 * M >= N && (B <= 4096 || M * N * 4 >= ((int64_t)1 << 20));
 }
 
 size_t omp_workspace_size(int64_t M, int64_t N, int64_t B, int32_t S, const omp_opts_t *opts) {
@@ -407,7 +413,7 @@ size_t bomp::solve_bytes(int64_t M, int64_t N, int64_t B, int32_t S, const omp_o
   if (cfg < 0 || cfg > MAX_TILE_CFG) return 0;
   const bool v0 = opts && opts->v0 == 1;
   size_t total = work_bytes(M, N, B, S, prec, cfg,
-                            !v0 && opts && gram_domain_form(opts->gram_domain, prec, M, N),
+                            !v0 && opts && gram_domain_form(opts->gram_domain, prec, M, N, B),
                             opts && opts->flag_near_ties == 1, v0);
   if (!opts || !opts->dict) total += dict_bytes(M, N, prec);
   return total;
@@ -434,7 +440,7 @@ int solve_impl(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y
   const bool v0 = opts->v0 == 1 || f64;
   if (v0 && (is_half(prec) || opts->gram_domain == 1 || opts->gram_on_the_fly || opts->refactor))
     return OMP_EINVAL;
-  const bool gdom = !v0 && gram_domain_form(opts->gram_domain, prec, M, N);
+  const bool gdom = !v0 && gram_domain_form(opts->gram_domain, prec, M, N, B);
   const bool ties = opts->flag_near_ties == 1;
   if (!dims_ok(M, N) || B < 0 || B > ((int64_t)1 << 26)) return OMP_EINVAL;
   if (S < 1 || S > M || S > N) return OMP_EINVAL;

@@ -245,9 +245,10 @@ def solve(A: torch.Tensor, Y: torch.Tensor, S: int, eps: float = 0.0, *, precisi
     `gram_on_the_fly` (ablation only) computes each pick's Gram row from the atoms
     instead of reading the prepared Gram matrix; `refactor` (ablation only) rebuilds
     the Cholesky factor of the support's Gram block at every step instead of
-    appending one row to it. `gram_domain` (FP32 only; for tall dictionaries, M >= N)
-    takes each step's correlations from P = A^T y and the Gram matrix instead of from
-    residual vectors; gram_domain="auto" picks that form for FP32 solves with M >= N.
+    appending one row to it. `gram_domain` (FP32 only) takes each step's correlations
+    from P = A^T y and the Gram matrix instead of from residual vectors;
+    gram_domain="auto" picks that form for FP32 solves with 4M >= N, except
+    dictionaries under 1 MiB in batches of more than 4096 signals.
     `flag_near_ties` sets status bit SIG_NEARTIE on signals where, at some step, the
     runner-up atom scored within 1e-5 (relative) of the picked one. `v0` (FP32 only)
     runs the paper's Algorithm v0 (inverse Cholesky factor and D = A^T Q).

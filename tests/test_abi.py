@@ -166,13 +166,17 @@ def test_gram_domain_form(lib):
     f0 = lib.omp_workspace_size(8064, 1207, 1200, 30, ctypes.byref(a))
     f1 = lib.omp_workspace_size(8064, 1207, 1200, 30, ctypes.byref(g))
     assert 9 * 1280 * 1280 * 4 <= f1 - f0 < 9 * 1280 * 1280 * 4 + (1 << 20)
-    # Automatic choice (2): the Gram-domain form for FP32 and M >= N only.
+    # Automatic choice (2): the Gram-domain form for FP32 and 4M >= N, except a dictionary
+    # under 1 MiB in a batch of more than 4096 signals.
     au = omp.OmpOptsStruct()
     lib.omp_opts_default(ctypes.byref(au))
     au.gram_domain = 2
     assert lib.omp_workspace_size(8064, 1207, 1200, 30, ctypes.byref(au)) == f1
-    assert lib.omp_workspace_size(1024, 4096, 4096, 64, ctypes.byref(au)) == \
-        lib.omp_workspace_size(1024, 4096, 4096, 64, ctypes.byref(a))
+    for (M, N, B), gd in {(1024, 4096, 4096): True, (1024, 8192, 4096): False, (256, 128, 5000): False,
+                          (512, 512, 5000): True, (128, 512, 60): True}.items():
+        want = g if gd else a
+        assert lib.omp_workspace_size(M, N, B, 30, ctypes.byref(au)) == \
+            lib.omp_workspace_size(M, N, B, 30, ctypes.byref(want)), (M, N, B)
     au.precision = omp.PREC["bf16"]
     ab = omp.OmpOptsStruct()
     lib.omp_opts_default(ctypes.byref(ab))

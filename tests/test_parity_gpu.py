@@ -748,10 +748,13 @@ def test_fp64_1024x4096_prefix(orc):
 
 
 @pytest.mark.parametrize("M,N,B,S,eps_frac", [(512, 128, 100, 20, 0.0), (300, 300, 64, 40, 0.0),
-                                              (1000, 700, 90, 30, 0.0), (640, 260, 77, 24, 0.05)])
+                                              (1000, 700, 90, 30, 0.0), (640, 260, 77, 24, 0.05),
+                                              (256, 1024, 80, 24, 0.0), (384, 760, 70, 32, 0.05),
+                                              (200, 800, 64, 40, 0.0)])
 def test_gram_domain_form(orc, M, N, B, S, eps_frac):
-    """Gram-domain form (tall dictionaries): correlations from P = A^T y and G, no residual
-    vectors; the oracle's picks and, up to near-ties, the residual-vector form's supports.
+    """Gram-domain form (tall, square and wide dictionaries): correlations from P = A^T y
+    and G, no residual vectors; the oracle's picks on every signal and, up to near-ties,
+    the residual-vector form's supports.
     With eps_frac > 0 every signal gets eps_b = eps_frac ||y_b|| (the running ||r||^2
     decides the stop)."""
     torch = _torch()
@@ -772,6 +775,7 @@ def test_gram_domain_form(orc, M, N, B, S, eps_frac):
     out = {k: v.cpu().numpy() for k, v in g._asdict().items() if v is not None}
     rep = parity.check(w, out, orc)
     print(rep)
+    assert rep["passed"] == w.B
     same = np.mean([set(x.tolist()) == set(y.tolist()) for x, y in zip(a.support.cpu().numpy(), out["support"])])
     print("same supports as the residual-vector form:", same)
     assert same >= 0.95
@@ -824,19 +828,22 @@ def test_gram_domain_face_shape_sampled(orc):
     print(rep)
 
 
-@pytest.mark.parametrize("M,N", [(512, 128), (128, 512)])
-def test_gram_domain_automatic_choice(M, N):
-    """gram_domain="auto" gives the Gram-domain form's results bit for bit on a tall
-    dictionary and the residual-vector form's on a wide one."""
+@pytest.mark.parametrize("M,N,B,gd", [(512, 128, 60, True), (128, 512, 60, True), (64, 512, 60, False),
+                                      (256, 128, 5000, False), (512, 512, 5000, True), (256, 1024, 5000, True)])
+def test_gram_domain_automatic_choice(M, N, B, gd):
+    """gram_domain="auto" gives the Gram-domain form's results bit for bit where it
+    chooses that form (FP32, 4M >= N, and at more than 4096 signals only for a
+    dictionary of at least 1 MiB) and the residual-vector form's elsewhere."""
     torch = _torch()
     from paper_2407_06434_amd import omp, workloads
-    w = workloads.custom(M, N, 60, 16, seed=M + 2 * N, k_true=16, column_norm="unit")
+    assert gd == (4 * M >= N and (B <= 4096 or M * N * 4 >= 1 << 20))
+    w = workloads.custom(M, N, B, 16, seed=M + 2 * N, k_true=16, column_norm="unit")
     dev = torch.device("cuda:0")
     A = torch.from_numpy(w.A).to(dev)
     Y = torch.from_numpy(w.Y).to(dev)
-    print(f"case automatic form M={M} N={N}", flush=True)
+    print(f"case automatic form M={M} N={N} B={B}", flush=True)
     auto = omp.solve(A, Y, w.S, precision="fp32", gram_domain="auto")
-    want = omp.solve(A, Y, w.S, precision="fp32", gram_domain=M >= N)
+    want = omp.solve(A, Y, w.S, precision="fp32", gram_domain=gd)
     torch.cuda.synchronize()
     for k in ("support", "coef", "status", "rnorm"):
         assert torch.equal(getattr(auto, k), getattr(want, k)), k
