@@ -490,7 +490,8 @@ int solve_impl(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y
     // again, where the residual kernel packs several signals per wavefront and
     // holds every one of them at once.
     w.fuse_res = (w.nslice == 1 && !gdom && !v0 && !f64 && (d.Mp >= 256 || w.B <= 4096)) ? 1 : 0;
-    if (solve_rr(d, w)) w.fuse_res = 0;  // that variant keeps its registers for the residual it reads
+    // the register-residual solve (512 < M <= 1024) forms it in a variant of its own, with one factor row per lane
+    if (solve_rr(d, w) && S > 64) w.fuse_res = 0;
     e = timer.run(OMP_PHASE_INIT, [&] {
       return launch_init(Y, ldy, opts->S_per_signal, opts->eps_per_signal, eps, d, w, prec, cs);
     });

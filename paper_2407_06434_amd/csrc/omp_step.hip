@@ -885,8 +885,9 @@ __device__ inline void stop_signal(const WorkView &w, const SlotView &sv, int64_
 
 // RPL: support rows per lane (S <= 64 RPL); BF16: the 16-bit forms' certified
 // pick; SLOTS: the slot scheduler's retire and admit; RR: the residual is held
-// in registers (512 < M <= 1024).
-template <int RPL, bool BF16, bool SLOTS, bool RR>
+// in registers (512 < M <= 1024); RRF: that variant also forms the next residual
+// (a variant of its own, so that the one that does not keeps its registers).
+template <int RPL, bool BF16, bool SLOTS, bool RR, bool RRF = false>
 __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView w, SlotView sv) {
   extern __shared__ float smem[];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -1269,7 +1270,7 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
     if (i < K) w.xh[b * S + i] = x[p];
   }
 
-  if (!SLOTS && !RR && w.fuse_res) {
+  if (!SLOTS && (!RR || RRF) && w.fuse_res) {
     // Residual fused into the solve (dictionaries small enough for every XCD's L2,
     // where the residual kernel would not slice M): this wavefront forms
     // r = y - A_K x for its own signal exactly as the residual kernel does (the
@@ -2157,6 +2158,14 @@ hipError_t launch_solve_t(const DictView &d, const WorkView &w, const SlotView &
   const unsigned blocks = (unsigned)((w.B + nw - 1) / nw);
   if constexpr (!SLOTS) {
     if (solve_rr(d, w)) {
+      if constexpr (RPL == 1) {
+        if (w.fuse_res) {
+          hipError_t e = allow_lds(k_solve<1, BF16, false, true, true>, lds);
+          if (e != hipSuccess) return e;
+          hipLaunchKernelGGL((k_solve<1, BF16, false, true, true>), dim3(blocks), dim3(64 * nw), lds, st, d, w, sv);
+          return hipGetLastError();
+        }
+      }
       hipError_t e = allow_lds(k_solve<RPL, BF16, false, true>, lds);
       if (e != hipSuccess) return e;
       hipLaunchKernelGGL((k_solve<RPL, BF16, false, true>), dim3(blocks), dim3(64 * nw), lds, st, d, w, sv);
