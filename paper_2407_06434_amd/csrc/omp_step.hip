@@ -31,7 +31,8 @@
 // order and with the same sums, and k_residual is not launched (except for
 // signals shorter than 256 samples in batches larger than the solve's resident
 // wavefronts, where the residual kernel's packing of several signals per
-// wavefront wins).
+// wavefront wins, and for S > 64 where the solve holds the residual in
+// registers).
 //
 // The paper's code re-factorised A_k^T A_k at every step and names the
 // Cholesky update as its next step (Section 3.6); this file implements that
