@@ -25,10 +25,10 @@
 // ||r||^2 accumulated in FP64 per slice of the signal. The signal is cut into
 // up to 8 slices of M and workgroup i works on slice i mod 8: workgroups are
 // dispatched round-robin over the 8 XCDs, so every XCD only ever gathers its
-// own eighth of every atom (one slice of M), which then stays in its L2. A
-// dictionary of at most 2 MiB in FP32 fits every XCD's L2 whole (one slice):
-// there the solve's wavefront forms r itself after its back solve, in the same
-// order and with the same sums, and k_residual is not launched (except for
+// own eighth of every atom (one slice of M), which then stays in its L2. For a
+// dictionary of at most 4 MiB in FP32 (one XCD's L2) the solve's wavefront
+// forms r itself after its back solve, in the same order per element, and
+// k_residual is not launched (except for
 // signals shorter than 256 samples in batches larger than the solve's resident
 // wavefronts, where the residual kernel's packing of several signals per
 // wavefront wins, and for S > 64 where the solve holds the residual in
@@ -1272,11 +1272,11 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
   }
 
   if (!SLOTS && (!RR || RRF) && w.fuse_res) {
-    // Residual fused into the solve (dictionaries small enough for every XCD's L2,
-    // where the residual kernel would not slice M): this wavefront forms
-    // r = y - A_K x for its own signal exactly as the residual kernel does (the
-    // same FMA order per element), its 16-bit copy, ||r||^2 and, in the 16-bit
-    // forms, the copy's error norm, and stores them where that kernel would.
+    // Residual fused into the solve (dictionaries of at most 4 MiB in FP32): this
+    // wavefront forms r = y - A_K x for its own signal as the residual kernel
+    // does (the same FMA order per element), its 16-bit copy, ||r||^2 and, in
+    // the 16-bit forms, the copy's error norm, and stores the norms in slice 0
+    // (the other slices' entries stay at the zero the set-up wrote).
     const int64_t nc4 = d.Mp / 4;
     const float4 *A4 = reinterpret_cast<const float4 *>(d.A32);
     const float4 *Y4 = reinterpret_cast<const float4 *>(w.Yp) + b * nc4;
@@ -1337,7 +1337,7 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
     nrm = wave_sum(nrm);
     if (BF16) dlt = wave_sum(dlt);
     if (lane == 0) {
-      w.pnorm[b * NSLICE_MAX] = nrm;  // one slice: entries 1 .. NSLICE_MAX-1 stay 0
+      w.pnorm[b * NSLICE_MAX] = nrm;  // entries 1 .. NSLICE_MAX-1 stay 0
       if (BF16) w.pdelta[b * NSLICE_MAX] = dlt;
       if (BF16 && w.fp16) w.rscale[b] = sig;
     }

@@ -117,13 +117,15 @@ def test_long_signals_residual_in_memory(orc, M, N, B, S, prec):
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("M,N,B,S,caps", [(512, 1000, 40, 24, False), (60, 8000, 36, 12, False),
                                           (200, 700, 48, 30, True), (1000, 500, 44, 40, False),
-                                          (640, 700, 50, 64, True)])
+                                          (640, 700, 50, 64, True), (512, 2000, 40, 24, True),
+                                          (128, 8000, 40, 16, False)])
 def test_residual_formed_in_the_solve(orc, M, N, B, S, caps, prec):
-    """Dictionaries of at most 2 MiB in FP32 (one padded to exactly 2 MiB, one of 8192
-    atoms of 64 samples, two with 512 < M <= 1024, where the solve holds the previous
-    residual in registers) fit every XCD's L2, so the solve forms each step's residual
-    itself; every signal against the oracle, two cases with per-signal caps and
-    tolerances so that signals finish at different steps."""
+    """Dictionaries of at most 4 MiB in FP32 (one padded to exactly 2 MiB, two to 4 MiB,
+    where the residual kernel would cut M into eight slices, one of 8192 atoms of 64
+    samples, two with 512 < M <= 1024, where the solve holds the previous residual in
+    registers): the solve forms each step's residual itself; every signal against the
+    oracle, three cases with per-signal caps and tolerances so that signals finish at
+    different steps."""
     from paper_2407_06434_amd import workloads
     w = workloads.custom(M, N, B, S, seed=3 * M + N, k_true=S)
     kw = {}
