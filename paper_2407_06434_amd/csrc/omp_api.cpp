@@ -482,15 +482,8 @@ int solve_impl(const float *A, int64_t M, int64_t N, int64_t lda, const float *Y
     WorkView w = work_view(workspace, M, N, B, S, prec, cfg, gdom, ties, v0);
     w.gram_fly = opts->gram_on_the_fly;
     w.refactor = opts->refactor;
-    // A dictionary of at most 4 MiB in FP32 (one XCD's L2; beyond that the gathers
-    // of whole atoms leave the L2s and the XCD-sliced residual kernel wins): the
-    // solve forms the residual itself, one launch fewer per step.
-    // Not for signals shorter than 256 samples in batches of more than 4096 (the
-    // solve's resident wavefronts): one wavefront per signal then leaves lanes
-    // idle, and each later generation of solve wavefronts waits for its gathers
-    // again, where the residual kernel packs several signals per wavefront and
-    // holds every one of them at once.
-    w.fuse_res = (d.Mp * d.Np * 4 <= ((int64_t)4 << 20) && !gdom && !v0 && !f64 && (d.Mp >= 256 || w.B <= 4096)) ? 1 : 0;
+    // the solve forms the residual itself where that was measured faster (one launch fewer per step)
+    w.fuse_res = (!gdom && !v0 && !f64 && residual_in_solve(d, B)) ? 1 : 0;
     // the register-residual solve (512 < M <= 1024) forms it in a variant of its own, with one factor row per lane
     if (solve_rr(d, w) && S > 64) w.fuse_res = 0;
     e = timer.run(OMP_PHASE_INIT, [&] {

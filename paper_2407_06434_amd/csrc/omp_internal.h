@@ -107,7 +107,7 @@ struct WorkView {
   int pchunks;    // K chunks of the P product (1: no split)
   int flag_ties;  // 1: near-tie flagging (the select stages keep the second best atom too)
   int v0;         // 1: Algorithm v0 (inverse Cholesky factor F in V, D = A^T Q, correlations in P)
-  int fuse_res;   // 1: the solve forms each updated signal's residual itself (one slice; no residual kernel)
+  int fuse_res;   // 1: the solve forms each updated signal's residual itself (norms in slice 0; no residual kernel)
   float *D;       // [Bp][S][Np] v0: D's columns d_j = A^T q_j, each Np long (else nullptr)
   // FP64 form (Algorithm v0 in FP64; else nullptr)
   double *P64;    // [Bp][Np] correlations c = A^T r
@@ -231,6 +231,7 @@ hipError_t launch_gram_select(const DictView &d, const WorkView &w, hipStream_t 
 hipError_t launch_solve(const DictView &d, const WorkView &w, int precision, hipStream_t st);
 // Whether the solve holds the residual in registers (its own variant, which does not fuse the residual).
 bool solve_rr(const DictView &d, const WorkView &w);
+bool residual_in_solve(const DictView &d, int64_t B);
 // Residual r = y - A_S x (and its BF16 copy and per-slice norms) for the signals just updated;
 // kbound is an upper bound on every signal's support size (the number of steps taken so far).
 hipError_t launch_residual(const DictView &d, const WorkView &w, int precision, int kbound, hipStream_t st);

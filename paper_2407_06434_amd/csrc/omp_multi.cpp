@@ -160,7 +160,8 @@ hipError_t capture_chunk(DevState *ds, const std::vector<Plan> &plans, int preci
       hipStream_t sp = ds->streams[p];
       e = launch_corr_select(q.d, q.w, precision, sp);
       if (e == hipSuccess) e = launch_solve_slots(q.d, q.w, q.sv, precision, sp);
-      if (e == hipSuccess) e = launch_residual_lp(q.d, q.w, precision, q.lanes, q.w.S, sp);  // slots: any k <= S
+      if (e == hipSuccess && !q.w.fuse_res)
+        e = launch_residual_lp(q.d, q.w, precision, q.lanes, q.w.S, sp);  // slots: any k <= S
     }
   }
   for (int p = 1; p < np && e == hipSuccess; ++p) {
@@ -272,6 +273,8 @@ int solve_multi_locked(const omp_problem_t *probs, int nprob, const omp_multi_op
     std::memset(&q, 0, sizeof(q));
     q.d = dict_view(dd->mem, dd->M, dd->N, prec);
     q.w = work_view(ws + off + L.work, dd->M, dd->N, slots, pr.S, prec, pr.tile_config);
+    // the same choice as omp_solve on this problem's signals, so results stay bit-identical to it
+    q.w.fuse_res = residual_in_solve(q.d, pr.B) ? 1 : 0;
     q.sv.sig = reinterpret_cast<int32_t *>(ws + off + L.sig);
     q.sv.ctrl = ctrl + (size_t)p * CTRL_WORDS;
     q.sv.Y = pr.Y;

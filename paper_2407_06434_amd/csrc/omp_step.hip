@@ -56,6 +56,18 @@ namespace bomp {
 // wavefronts per SIMD instead of four.
 bool solve_rr(const DictView &d, const WorkView &w) { return !w.gram_dom && d.Mp > 512 && d.Mp <= 1024; }
 
+// Whether the solve forms the residual itself instead of a residual launch, for
+// the residual-vector forms on a batch of B signals: dictionaries of at most
+// 4 MiB in FP32 (one XCD's L2; beyond that gathering whole atoms leaves the L2s
+// and the XCD-sliced residual kernel wins), except signals shorter than 256
+// samples in batches of more than 4096 (the solve's resident wavefronts): one
+// wavefront per signal then leaves lanes idle, and each later generation of
+// solve wavefronts waits for its gathers again, where the residual kernel packs
+// several signals per wavefront and holds every one of them at once.
+bool residual_in_solve(const DictView &d, int64_t B) {
+  return d.Mp * d.Np * 4 <= ((int64_t)4 << 20) && (d.Mp >= 256 || B <= 4096);
+}
+
 namespace {
 
 __device__ inline uint16_t f32_to_bf16_rne(float f) {
@@ -1271,7 +1283,7 @@ __global__ __launch_bounds__(64 * SOLVE_WAVES) void k_solve(DictView d, WorkView
     if (i < K) w.xh[b * S + i] = x[p];
   }
 
-  if (!SLOTS && (!RR || RRF) && w.fuse_res) {
+  if ((!RR || RRF) && w.fuse_res) {
     // Residual fused into the solve (dictionaries of at most 4 MiB in FP32): this
     // wavefront forms r = y - A_K x for its own signal as the residual kernel
     // does (the same FMA order per element), its 16-bit copy, ||r||^2 and, in
